@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of Coherent Fusion pose scoring on one MI355X.
+
+Workload: 4096 synthetic docked poses (ligands of 20-60 atoms, pockets of
+400-900 atoms), 48^3 grids at 1 A, the full-size model (3D-CNN with k=7 convs,
+64/128 channels and two residual blocks; SG-CNN with H=64, 3 + 3 gated rounds;
+74 -> 64 -> 1 SELU fusion head).  One step = one cf_score_poses call over the
+whole batch: centres, voxelisation, conv stack, pooling, neighbour lists,
+SG-CNN and fusion head, with inputs already resident in HBM.
+
+Reported: poses/s of the precision form (bfloat16 MFMA, float32 accumulation,
+batched 512 poses per launch), the plain float32 path on the same poses, score
+error of both against stored FP64 oracle scores, the roofline position of the
+dominant kernel (conv3d, timed with HIP events on its own stream) and the FP64
+CPU oracle timed on a bounded sample on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2516.6   # MI355X dense bf16 MFMA
+PEAK_FP32_TFLOPS = 157.3    # MI355X fp32 (matrix and vector)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def load_golden(cfg, G):
+    path = os.path.join(ROOT, "tests", "golden", f"{cfg}_G{G}_oracle.json")
+    if not os.path.exists(path):
+        return None
+    return json.load(open(path))
+
+
+def time_steps(scorer, db, G, steps, warmup, out, timing=False):
+    import torch
+    from paper_2104_04547_amd import cfabi
+    for _ in range(warmup):
+        scorer.score(db, G, out)
+    torch.cuda.synchronize()
+    rc = scorer.status()[0]
+    if rc != 0:
+        raise RuntimeError(f"device status {rc}: {cfabi.cf_last_error()}")
+    if timing:
+        cfabi.cf_timing_read(scorer.ctx)          # drop warm-up entries
+        cfabi.cf_timing_enable(scorer.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        scorer.score(db, G, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = None
+    if timing:
+        stats = cfabi.cf_timing_read(scorer.ctx)
+        cfabi.cf_timing_enable(scorer.ctx, False)
+    rc = scorer.status()[0]
+    if rc != 0:
+        raise RuntimeError(f"device status {rc}: {cfabi.cf_last_error()}")
+    return (t1 - t0) / steps, stats
+
+
+def by_kernel(stats):
+    """Merge per-layer conv entries ("conv<i>.<variant>") by kernel variant."""
+    out = {}
+    for k, v in stats.items():
+        key = "conv." + k.split(".", 1)[1] if k.startswith("conv") else k
+        e = out.setdefault(key, dict(launches=0, total_ms=0.0, flop=0.0, bytes=0.0))
+        for f in e:
+            e[f] += v[f]
+    return out
+
+
+def error_stats(got, gd, n):
+    import numpy as np
+    want = np.array([p["score"] for p in gd["poses"][:n]])
+    err = np.abs(np.asarray(got[:n], dtype=np.float64) - want)
+    rel = err / np.maximum(1.0, np.abs(want))
+    return dict(n_poses=int(n), max_abs_pk=float(err.max()), mean_abs_pk=float(err.mean()),
+                max_rel=float(rel.max()))
+
+
+def cnn_latent_error(scorer, batch, gd, G, n):
+    """CNN-branch latents through cf_voxelize + cf_cnn3d_fwd vs the oracle's."""
+    import numpy as np
+    from paper_2104_04547_amd import cfabi
+    sub = batch.select(list(range(n)))
+    db = cfabi.DeviceBatch.from_pose_batch(sub)
+    lat = scorer.cnn3d(scorer.voxelize(db, G), G).cpu().numpy().astype(np.float64)
+    want = np.array([p["cnn_lat"] for p in gd["poses"][:n]])
+    return float(np.abs(lat - want).max() / np.abs(want).max())
+
+
+def cpu_baseline(batch, arch, w, G, n):
+    """The FP64 oracle as it stands, on the first n poses, on this host's cores."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    for p in range(n):
+        a, b = int(batch.atom_off[p]), int(batch.atom_off[p + 1])
+        oracle.score_pose(batch.xyz[a:b], batch.feat[a:b], batch.is_lig[a:b], w, arch, G)
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="poses/s", cores=int(threads), kind="oracle",
+                sample=f"first {n} of the workload's poses, full path per pose (splat, conv stack, "
+                       f"graphs, SG-CNN, fusion) in float64 numpy; {dt:.1f} s",
+                seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--poses", type=int, default=4096)
+    ap.add_argument("--G", type=int, default=48)
+    ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--cpu-poses", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--json-out", default="")
+    a = ap.parse_args()
+
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: this build scores poses on a single MI355X and has no "
+              f"multi-GPU path (asked for --gpus {a.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_2104_04547_amd import Scorer, cfabi
+
+    cfg = "c2"
+    G = a.G
+    arch = synth.ARCHS["full"]
+    w = synth.make_weights(arch)
+    calib = json.load(open(os.path.join(ROOT, "tests", "golden", "calib.json")))["full"]
+    w = synth.apply_calibration(w, calib["scale"], calib["shift"])
+
+    t0 = time.perf_counter()
+    batch = synth.make_poses(cfg, a.poses)
+    log(f"generated {a.poses} poses ({batch.n_atoms} atoms) in {time.perf_counter() - t0:.1f}s")
+    db = cfabi.DeviceBatch.from_pose_batch(batch)
+    torch.cuda.synchronize()
+    out = torch.empty(a.poses, dtype=torch.float32, device="cuda")
+
+    res = {}
+    variants = {}
+    for prec, steps, warm in (("bf16", a.steps, a.warmup), ("fp32", a.fp32_steps, 1)):
+        if prec == "fp32" and a.no_fp32:
+            continue
+        s = Scorer(arch, w, prec)
+        if not a.no_autotune:
+            t0 = time.perf_counter()
+            v = s.autotune(G, 512)
+            log(f"{prec}: autotuned conv variants {v} in {time.perf_counter() - t0:.1f}s")
+        variants[prec] = s.variants(G)
+        sec, stats = time_steps(s, db, G, steps, warm, out, timing=True)
+        scores = out.cpu().numpy().astype(np.float64)
+        res[prec] = dict(sec_per_step=sec, poses_per_s=a.poses / sec, stats=stats, scores=scores)
+        log(f"{prec}: {sec * 1e3:.1f} ms/step, {a.poses / sec:.1f} poses/s")
+        gd = load_golden(cfg, G)
+        if gd is not None:
+            n = min(len(gd["poses"]), a.poses)
+            res[prec]["error"] = error_stats(scores, gd, n)
+            res[prec]["cnn_latent_max_rel_error"] = cnn_latent_error(s, batch, gd, G, min(n, 16))
+            log(f"{prec}: error vs oracle {res[prec]['error']}, cnn latent rel {res[prec]['cnn_latent_max_rel_error']:.2e}")
+        s.close()
+
+    # dominant kernel of the precision form: the conv kernel (one template instance,
+    # possibly several layers) with the most device time, as a profiler groups it
+    st = by_kernel(res["bf16"]["stats"])
+    total_ms = sum(v["total_ms"] for v in st.values())
+    dom = max((k for k in st if k.startswith("conv")), key=lambda k: st[k]["total_ms"])
+    d = st[dom]
+    avg_ms = d["total_ms"] / d["launches"]
+    flop_per_launch = d["flop"] / d["launches"]
+    achieved = flop_per_launch / (avg_ms * 1e-3) / 1e12
+    conv_ms = sum(v["total_ms"] for k, v in st.items() if k.startswith("conv"))
+    conv_flop = sum(v["flop"] for k, v in st.items() if k.startswith("conv"))
+    breakdown = {k: dict(launches=v["launches"], ms_per_step=v["total_ms"] / a.steps,
+                         share=v["total_ms"] / total_ms,
+                         **({"tflops": v["flop"] / (v["total_ms"] * 1e-3) / 1e12} if v["flop"] else {}),
+                         **({"gbs": v["bytes"] / (v["total_ms"] * 1e-3) / 1e9} if v["bytes"] and not v["flop"] else {}))
+                 for k, v in sorted(st.items())}
+
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(batch, arch, w, G, a.cpu_poses)
+        log(f"cpu oracle: {cpu['value']:.4f} poses/s on {cpu['cores']} threads")
+
+    bf = res["bf16"]
+    line = {
+        "metric": "poses scored/sec, BF16 batched vs FP32 plain at stated pK error; p50/p99 latency",
+        "value": round(bf["poses_per_s"], 2),
+        "unit": "poses/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(bf["sec_per_step"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (seeded docked-pose stand-ins, random He-normal weights with pK calibration)",
+        "config": {
+            "workload": f"4096 poses c2-shaped (ligand 20-60, pocket 400-900 atoms), {G}^3 grid, full model, "
+                        f"512 poses per launch",
+            "poses": a.poses, "grid": G, "model": "coherent-fusion full (3D-CNN k7 64/128 + 2 res blocks, "
+                                                 "SG-CNN H64 3+3 rounds, fusion 74-64-1)",
+            "conv_variants_bf16": variants.get("bf16"), "conv_variants_fp32": variants.get("fp32"),
+        },
+        "roofline": {
+            "bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+            "avg_launch_ms": round(avg_ms, 4), "flop_per_launch": flop_per_launch,
+            "conv_stack_tflops": round(conv_flop / (conv_ms * 1e-3) / 1e12, 2),
+            "conv_share_of_step": round(conv_ms / total_ms, 4),
+        },
+        "cpu_baseline": None if cpu is None else {k: (round(v, 6) if isinstance(v, float) else v)
+                                                  for k, v in cpu.items() if k != "seconds"},
+        "score_error_vs_oracle": {p: res[p].get("error") for p in res},
+        "cnn_latent_max_rel_error": {p: res[p].get("cnn_latent_max_rel_error") for p in res},
+        "kernels_bf16": breakdown,
+    }
+    if "fp32" in res:
+        f = res["fp32"]
+        fst = by_kernel(f["stats"])
+        fdom = max((k for k in fst if k.startswith("conv")), key=lambda k: fst[k]["total_ms"])
+        fd = fst[fdom]
+        f_ach = fd["flop"] / (fd["total_ms"] * 1e-3) / 1e12
+        line["fp32_plain"] = {"value": round(f["poses_per_s"], 2), "unit": "poses/s",
+                              "ms_per_step": round(f["sec_per_step"] * 1e3, 3), "steps": a.fp32_steps,
+                              "dominant_kernel": fdom, "achieved_tflops": round(f_ach, 2),
+                              "frac_of_fp32_peak": round(f_ach / PEAK_FP32_TFLOPS, 4)}
+        line["speedup_bf16_vs_fp32"] = round(bf["poses_per_s"] / f["poses_per_s"], 3)
+    if a.json_out:
+        json.dump(line, open(a.json_out, "w"), indent=1)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * cf.h -- C ABI of the Coherent Fusion pose scorer for AMD Instinct MI355X (gfx950).
+ *
+ * The library scores docked protein-ligand poses with a Coherent Fusion model
+ * (Stevenson et al., "High-Throughput Virtual Screening of Small Molecule
+ * Inhibitors for SARS-CoV-2 Protein Targets with Deep Fusion Models", SC 2021):
+ * each pose is turned into a voxel grid read by a 3D-CNN and into a spatial graph
+ * with covalent and non-covalent edges read by an SG-CNN; the two latents are
+ * concatenated and fused into one predicted affinity pK = -log K (Sec. 1,
+ * Sec. 2.1 Eq. 1, Sec. 2.2, Fig. 1, Sec. 3.3).  The paper's screening runs score
+ * fixed-size batches of featurised poses per GPU and return one prediction per
+ * pose (Sec. 4.2); this ABI takes such a batch, ragged and packed, and returns
+ * one score per pose.
+ *
+ * Conventions (all entry points):
+ *   - Array pointers inside cf_pose_batch / cf_csr and all grid / latent / score
+ *     pointers are DEVICE pointers owned by the caller.  The library never frees
+ *     them and never keeps them after the call returns.
+ *   - Every compute call is asynchronous on `stream` (a hipStream_t; NULL is the
+ *     default stream) and returns a cf_status.  Argument errors that the host can
+ *     see (sizes, null pointers, unsupported shapes) are reported before anything
+ *     is enqueued.  Errors only the device can see (malformed offsets, CSR
+ *     capacity overflow, coordinates or features out of range) set a per-context
+ *     device status word that cf_stream_status() reports.
+ *   - A context is not re-entrant: use one context per host thread at a time.
+ *     Several contexts may share a device.
+ *   - No C++ exception crosses this boundary.  cf_last_error() returns a
+ *     thread-local message for the last non-OK status.
+ *
+ * Units and layouts:
+ *   - Coordinates are int32 in u = 2^-10 Angstrom.  All distance tests are exact
+ *     integer tests (so neighbour lists are reproducible bit for bit).
+ *   - 19 feature channels per atom, float32, |value| <= 64.
+ *   - Voxel grids are channels-last: grid[pose][i][j][k][channel], where voxel
+ *     (i, j, k) has centre center + (i - (G-1)/2, j - (G-1)/2, k - (G-1)/2) A
+ *     (1 A spacing).
+ */
+#ifndef CF_H
+#define CF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CF_OK = 0,
+  CF_ERR_INVALID_ARG = -1, /* bad argument (host) or malformed batch data (device) */
+  CF_ERR_CAPACITY = -2,    /* a caller-provided CSR is too small; see cf_stream_status */
+  CF_ERR_OOM = -3,         /* device allocation failed or would exceed the HBM budget */
+  CF_ERR_HIP = -4,         /* a HIP runtime call failed */
+  CF_ERR_UNSUPPORTED = -5  /* valid request outside what this build implements */
+} cf_status;
+
+typedef enum {
+  CF_PREC_FP32 = 0, /* plain form: every stage in float32 */
+  CF_PREC_BF16 = 1  /* precision form: conv3d and graph-conv GEMMs take bfloat16
+                       operands (round to nearest even) with float32 accumulation;
+                       splatting, folded BatchNorm bias, gates and the fusion head
+                       stay float32 */
+} cf_precision;
+
+#define CF_NCH 19            /* feature channels per atom */
+#define CF_MAX_POSE_ATOMS 4096
+#define CF_MODEL_MAGIC 0x314D4643u /* "CFM1" */
+
+typedef struct cf_ctx cf_ctx;
+
+/* A ragged batch of poses, packed CSR-style: atoms of pose p are rows
+ * atom_off[p] .. atom_off[p+1]-1 of xyz / feat / is_lig. */
+typedef struct {
+  int32_t n_poses;          /* P >= 1 */
+  int32_t n_atoms;          /* N = atom_off[P] */
+  const int32_t *atom_off;  /* [P+1], atom_off[0] = 0, each pose has 1..4096 atoms */
+  const int32_t *xyz;       /* [N][3] coordinates, units 2^-10 A */
+  const float *feat;        /* [N][19] atom features */
+  const uint8_t *is_lig;    /* [N] 1 = ligand atom, 0 = pocket atom */
+  const int32_t *center;    /* [P][3] grid centres (2^-10 A) or NULL: the library then
+                               uses the rounded ligand centroid (cf_pose_centers) */
+} cf_pose_batch;
+
+/* Compressed sparse rows of a neighbour list.  row_ptr has n_atoms+1 entries,
+ * col has `capacity` entries; columns are global atom ids, ascending in a row. */
+typedef struct {
+  int32_t *row_ptr;
+  int32_t *col;
+  int64_t capacity;
+} cf_csr;
+
+/* Model blob (host memory), little-endian:
+ *   cf_model_desc header, then float32 parameters in this order --
+ *   for each conv i: W [c_out][c_in][k][k][k], b [c_out], and if bn:
+ *       gamma, beta, running_mean, running_var (each [c_out]);
+ *   if cnn_dense: W [cnn_dense][c_out_last], b [cnn_dense];
+ *   SG-CNN: embed W [H][19], b [H];
+ *       for stage in (covalent, non-covalent): message W_t [H][H] for each of its
+ *       K rounds, then GRU w_ih [3H][H], w_hh [3H][H], b_ih [3H], b_hh [3H]
+ *       (gate rows stacked r, z, n);
+ *       readout gate W [H][H+19], b [H]; readout value W [H][H], b [H];
+ *   fusion: if fusion_hidden: W [fusion_hidden][latent_cnn + H], b [fusion_hidden];
+ *       output W [1][fusion_hidden or latent_cnn + H], b [1].
+ * Conv i reads tensor t_i and writes t_{i+1} (t_0 = voxel grid); res_src >= 0
+ * adds t_{res_src} before the ReLU of conv i. */
+typedef struct {
+  uint32_t magic;        /* CF_MODEL_MAGIC */
+  int32_t n_ch;          /* must be 19 */
+  int32_t n_conv;        /* 1..8 */
+  int32_t conv[8][5];    /* c_in, c_out, k (odd, <= 7), stride (1|2), res_src */
+  int32_t bn;            /* 1: inference BatchNorm after every conv */
+  int32_t cnn_dense;     /* 0: CNN latent = pooled features; else dense + ReLU width */
+  int32_t H;             /* SG-CNN width: 16, 32 or 64 */
+  int32_t K_c, K_n;      /* covalent / non-covalent propagation rounds (<= 8 each) */
+  int32_t r_cov_u;       /* covalent cutoff, 2^-10 A */
+  int32_t r_nc_u;        /* non-covalent cutoff, 2^-10 A */
+  int32_t fusion_hidden; /* 0: linear fusion head; else width of one SELU layer */
+} cf_model_desc;
+
+/* Create a scoring context on the current device.  Copies the weights (the blob
+ * may be freed afterwards), folds BatchNorm into the conv weights and bias in
+ * float32, and repacks weights for the kernels.  hbm_budget_bytes bounds the
+ * scratch the context may allocate (0 = 16 GiB); batches larger than the budget
+ * allows are scored in chunks.  Section refs: model structure Sec. 2.2, 3.3. */
+int cf_create(const void *host_model_blob, size_t nbytes, int precision,
+              int64_t hbm_budget_bytes, cf_ctx **out);
+void cf_destroy(cf_ctx *ctx);
+
+/* Grid centre of every pose: the ligand centroid rounded to the nearest unit
+ * (halves up), floor((2*sum x + n) / (2*n)) per axis over ligand atoms; the
+ * centroid of all atoms if a pose has none.  center_out: device [P][3] int32.
+ * (Grid placement is deferred by the paper to its predecessor, Sec. 3.3.) */
+int cf_pose_centers(cf_ctx *ctx, const cf_pose_batch *batch, int32_t *center_out, void *stream);
+
+/* Voxelise every pose (3D representation, Sec. 1; grid sizing and atom
+ * propagation, Sec. 3.3): each atom spreads its features over the voxels within
+ * 1.5 A (3 sigma, sigma = 0.5 A) of it with weights exp(-d^2 / (2 sigma^2)),
+ * normalised over that whole support; voxels outside the grid are dropped.
+ * grid_out: device [P][G][G][G][19], float32 (ctx precision FP32) or bfloat16
+ * (BF16).  G a multiple of 4, 8 <= G <= 96. */
+int cf_voxelize(cf_ctx *ctx, const cf_pose_batch *batch, int G, void *grid_out, void *stream);
+
+/* Covalent (d <= r_cov) and non-covalent (d <= r_nc) neighbour lists: all
+ * ordered pairs i != j of the same pose (two edge types by distance threshold,
+ * Sec. 1; thresholds Table II).  Rows by atom, columns ascending, global atom
+ * ids.  If an edge count exceeds a capacity, nothing beyond the capacity is
+ * written, row_ptr is still complete, and cf_stream_status returns
+ * CF_ERR_CAPACITY with the required counts. */
+int cf_build_graphs(cf_ctx *ctx, const cf_pose_batch *batch, cf_csr *cov, cf_csr *nc, void *stream);
+
+/* 3D-CNN head (Sec. 3.3.1, Table III): conv stack with folded BatchNorm, ReLU
+ * and residual adds, global average pooling, optional dense + ReLU.
+ * grid: device [P][G][G][G][19] in the context's precision (as cf_voxelize
+ * writes it).  cnn_latent: device [P][latent_cnn] float32. */
+int cf_cnn3d_fwd(cf_ctx *ctx, const void *grid, int32_t n_poses, int G, float *cnn_latent, void *stream);
+
+/* SG-CNN head (PotentialNet / gated graph sequence networks, Sec. 3.3.1,
+ * Table II): linear embedding, K_c covalent then K_n non-covalent rounds of
+ * neighbour sum -> message matrix -> GRU update, then a sigmoid-gated sum over
+ * ligand atoms.  cov / nc as written by cf_build_graphs for the same batch.
+ * sg_latent: device [P][H] float32. */
+int cf_sgcnn_fwd(cf_ctx *ctx, const cf_pose_batch *batch, const cf_csr *cov, const cf_csr *nc,
+                 float *sg_latent, void *stream);
+
+/* Whole path: centres (unless given), voxelisation, 3D-CNN, neighbour lists,
+ * SG-CNN and the Coherent Fusion head (Sec. 2.2, 3.3.3, Table V: SELU fusion
+ * layers, inference without dropout).  scores: device [P] float32 pK, in batch
+ * order.  Uses context-owned scratch; poses are processed in chunks. */
+int cf_score_poses(cf_ctx *ctx, const cf_pose_batch *batch, int G, float *scores, void *stream);
+
+/* Synchronise `stream`, then report and clear the context's device status word:
+ * CF_OK, or the first device-side error since the last call.  For
+ * CF_ERR_CAPACITY, *need_cov / *need_nc (if non-NULL) receive the edge counts a
+ * retry needs. */
+int cf_stream_status(cf_ctx *ctx, void *stream, int64_t *need_cov, int64_t *need_nc);
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char *cf_last_error(void);
+
+/* Model summary: latent widths, parameter count, precision. */
+int cf_model_info(const cf_ctx *ctx, int32_t *latent_cnn, int32_t *latent_sg, int64_t *n_params,
+                  int32_t *precision);
+
+/* Conv autotuning (batching form): time the candidate tile / wave layouts of
+ * every conv layer at grid size G on a synthetic batch of n_poses poses and keep
+ * the fastest per layer (cached in the context and reused for that G). */
+int cf_autotune(cf_ctx *ctx, int G, int32_t n_poses, void *stream);
+
+/* Chosen kernel variant per conv layer for grid size G (after cf_autotune or the
+ * default table): variant_out[n_conv]. */
+int cf_conv_variants(const cf_ctx *ctx, int G, int32_t *variant_out, int32_t max_layers);
+
+/* Per-kernel timing (diagnostics).  While enabled, every kernel launch made by
+ * the scoring entry points is bracketed by a pair of HIP events recorded on the
+ * launch's own stream.  cf_timing_read synchronises on them and returns, per
+ * kernel kind (conv layers are keyed "conv<i>.<variant>"), the launch count,
+ * summed device time and the algorithmic FLOPs and bytes those launches cover
+ * (for a conv layer: 2 * c_in * c_out * k^3 * output voxels; padding channels
+ * are not counted).  Reading clears the accumulated entries.  out may hold
+ * max_entries entries; *n_out receives the number available. */
+typedef struct {
+  char name[64];
+  int32_t launches;
+  double total_ms;
+  double flop;
+  double bytes;
+} cf_kernel_stat;
+int cf_timing_enable(cf_ctx *ctx, int enable);
+int cf_timing_read(cf_ctx *ctx, cf_kernel_stat *out, int32_t max_entries, int32_t *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CF_H */

@@ -1,0 +1,769 @@
+// C ABI of the pose scorer: context, weight preparation, scratch management and
+// the scoring entry points declared in include/cf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "cf_internal.h"
+
+using cf::bf16_t;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define CF_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(CF_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct cf_ctx {
+  int device = 0;
+  int bf16 = 0;
+  cf_model_desc desc{};
+  int64_t budget = 0;
+  int64_t n_params = 0;
+  int64_t weight_bytes = 0;
+  int64_t scratch_bytes = 0;
+
+  std::vector<cf::ConvLayer> conv;
+  int lc = 0;  // CNN latent width
+  int c_last = 0;
+  float *dense_w = nullptr, *dense_b = nullptr;
+  cf::SgWeights sg{};
+  float *fus_w1 = nullptr, *fus_b1 = nullptr, *fus_w2 = nullptr, *fus_b2 = nullptr;
+  int64_t *status = nullptr;
+  std::vector<void *> weight_allocs;
+
+  // per-kernel timing (diagnostics, off by default)
+  struct Pending {
+    std::string key;
+    hipEvent_t e0, e1;
+    double flop, bytes;
+  };
+  struct Stat {
+    int launches = 0;
+    double ms = 0, flop = 0, bytes = 0;
+  };
+  bool timing = false;
+  std::vector<Pending> pending;
+  std::map<std::string, Stat> stats;
+
+  // scratch
+  DevBuf grid, centers, cnn_lat, sg_lat, deg, pose_tot, cov_row, cov_col, nc_row, nc_col, hbuf;
+  std::vector<DevBuf> act;  // t_1 .. t_L
+  std::map<int, std::vector<int>> variants;  // per G
+};
+
+namespace {
+
+int alloc_weight(cf_ctx *c, void **p, size_t bytes, const void *host) {
+  if (hipMalloc(p, bytes) != hipSuccess) return fail(CF_ERR_OOM, "weight allocation failed");
+  c->weight_allocs.push_back(*p);
+  c->weight_bytes += (int64_t)bytes;
+  if (host && hipMemcpy(*p, host, bytes, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(CF_ERR_HIP, "weight upload failed");
+  return CF_OK;
+}
+
+int ensure(cf_ctx *c, DevBuf &b, size_t bytes) {
+  if (b.n >= bytes) return CF_OK;
+  const int64_t grow = (int64_t)bytes - (int64_t)b.n;
+  if (c->scratch_bytes + grow + c->weight_bytes > c->budget)
+    return fail(CF_ERR_OOM, "scratch would exceed the context's HBM budget");
+  if (b.p) {
+    (void)hipFree(b.p);
+    c->scratch_bytes -= (int64_t)b.n;
+    b.p = nullptr;
+    b.n = 0;
+  }
+  if (hipMalloc(&b.p, bytes) != hipSuccess) return fail(CF_ERR_OOM, "scratch allocation failed");
+  b.n = bytes;
+  c->scratch_bytes += (int64_t)bytes;
+  return CF_OK;
+}
+
+int conv_out_dim(int D, int k, int s) { return (D + 2 * ((k - 1) / 2) - k) / s + 1; }
+
+// Event pair around one launch on its own stream (only when timing is enabled).
+hipEvent_t tbegin(cf_ctx *c, hipStream_t s) {
+  if (!c->timing) return nullptr;
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  (void)hipEventRecord(e, s);
+  return e;
+}
+
+void tend(cf_ctx *c, hipStream_t s, hipEvent_t e0, const std::string &key, double flop, double bytes) {
+  if (!e0) return;
+  hipEvent_t e1 = nullptr;
+  if (hipEventCreate(&e1) != hipSuccess) return;
+  (void)hipEventRecord(e1, s);
+  c->pending.push_back({key, e0, e1, flop, bytes});
+}
+
+size_t elem_size(const cf_ctx *c) { return c->bf16 ? 2 : 4; }
+int grid_cpad(const cf_ctx *c) { return c->bf16 ? 32 : 24; }
+
+// bytes per pose of the conv-stack tensors at grid size G
+int64_t pose_bytes(const cf_ctx *c, int G) {
+  int64_t b = (int64_t)G * G * G * grid_cpad(c) * elem_size(c);
+  int D = G;
+  for (auto &L : c->conv) {
+    D = conv_out_dim(D, L.k, L.stride);
+    b += (int64_t)D * D * D * L.cout_store * elem_size(c);
+  }
+  return b;
+}
+
+int chunk_poses(const cf_ctx *c, int G, int P) {
+  const int64_t avail = c->budget - c->weight_bytes - ((int64_t)64 << 20);
+  int64_t n = avail / (pose_bytes(c, G) + 4096);
+  if (n > 512) n = 512;
+  if (n < 1) n = 1;
+  return (int)std::min<int64_t>(n, P);
+}
+
+int validate_batch(const cf_pose_batch *b) {
+  if (!b) return fail(CF_ERR_INVALID_ARG, "batch is NULL");
+  if (b->n_poses < 1) return fail(CF_ERR_INVALID_ARG, "n_poses must be >= 1");
+  if (b->n_atoms < 1) return fail(CF_ERR_INVALID_ARG, "n_atoms must be >= 1");
+  if ((int64_t)b->n_atoms > (int64_t)b->n_poses * CF_MAX_POSE_ATOMS)
+    return fail(CF_ERR_INVALID_ARG, "n_atoms exceeds n_poses * 4096");
+  if (!b->atom_off || !b->xyz || !b->feat || !b->is_lig)
+    return fail(CF_ERR_INVALID_ARG, "batch array pointer is NULL");
+  return CF_OK;
+}
+
+int validate_G(int G) {
+  if (G < 8 || G > 96 || (G & 3)) return fail(CF_ERR_UNSUPPORTED, "grid size G must be a multiple of 4 in 8..96");
+  return CF_OK;
+}
+
+// Per-layer kernel variants for grid size G (default table unless autotuned).
+int variants_for(cf_ctx *c, int G, std::vector<int> &out) {
+  auto it = c->variants.find(G);
+  if (it != c->variants.end()) {
+    out = it->second;
+    return CF_OK;
+  }
+  out.clear();
+  int D = G;
+  for (auto &L : c->conv) {
+    const int v = cf::conv_default_variant(L, D, c->bf16);
+    if (v < 0) return fail(CF_ERR_UNSUPPORTED, "no conv kernel for this layer shape");
+    out.push_back(v);
+    D = conv_out_dim(D, L.k, L.stride);
+    if (D < 1) return fail(CF_ERR_UNSUPPORTED, "grid too small for the conv stack");
+  }
+  c->variants[G] = out;
+  return CF_OK;
+}
+
+int ensure_act(cf_ctx *c, int G, int np) {
+  if ((int)c->act.size() != (int)c->conv.size()) c->act.resize(c->conv.size());
+  int D = G;
+  int rc = ensure(c, c->grid, (size_t)np * G * G * G * grid_cpad(c) * elem_size(c));
+  if (rc) return rc;
+  for (size_t i = 0; i < c->conv.size(); ++i) {
+    D = conv_out_dim(D, c->conv[i].k, c->conv[i].stride);
+    rc = ensure(c, c->act[i], (size_t)np * D * D * D * c->conv[i].cout_store * elem_size(c));
+    if (rc) return rc;
+  }
+  return CF_OK;
+}
+
+// conv stack + pooling on grids already in the internal padded layout in c->grid
+int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s) {
+  std::vector<int> var;
+  int rc = variants_for(c, G, var);
+  if (rc) return rc;
+  std::vector<const void *> t;
+  t.push_back(c->grid.p);
+  int D = G;
+  for (size_t i = 0; i < c->conv.size(); ++i) {
+    const auto &L = c->conv[i];
+    const void *res = L.res_src >= 0 ? t[L.res_src] : nullptr;
+    const int Do = conv_out_dim(D, L.k, L.stride);
+    hipEvent_t e = tbegin(c, s);
+    CF_HIP(cf::launch_conv(var[i], L, c->bf16, t[i], res, c->act[i].p, np, D, s));
+    if (e) {
+      const double vox = (double)Do * Do * Do * np;
+      const double flop = 2.0 * L.cin * L.cout * L.k * L.k * L.k * vox;
+      const double bytes = ((double)D * D * D * np * L.cin + vox * L.cout * (res ? 2 : 1)) * elem_size(c);
+      tend(c, s, e, "conv" + std::to_string(i) + "." + cf::conv_variant_name(var[i]), flop, bytes);
+    }
+    D = Do;
+    t.push_back(c->act[i].p);
+  }
+  const auto &Ll = c->conv.back();
+  hipEvent_t e = tbegin(c, s);
+  CF_HIP(cf::launch_pool_dense(t.back(), c->bf16, np, D * D * D, Ll.cout_store, Ll.cout, c->dense_w, c->dense_b,
+                               c->desc.cnn_dense, cnn_lat, s));
+  tend(c, s, e, "pool_dense", 0.0, (double)D * D * D * np * Ll.cout * elem_size(c));
+  return CF_OK;
+}
+
+// ---------------------------------------------------------------- weights
+
+struct BlobReader {
+  const float *p;
+  size_t left;
+  const float *take(size_t n) {
+    if (n > left) return nullptr;
+    const float *r = p;
+    p += n;
+    left -= n;
+    return r;
+  }
+};
+
+template <typename T>
+T to_t(float v);
+template <>
+float to_t<float>(float v) {
+  return v;
+}
+template <>
+bf16_t to_t<bf16_t>(float v) {
+  return (bf16_t)v;
+}
+
+template <typename T>
+std::vector<T> pack_conv(const std::vector<float> &W, int cout, int cin, int k, int cin_pad, int cout_pad32) {
+  const int CC = sizeof(T) == 2 ? 16 : 8;
+  const int nchunks = cin_pad / CC;
+  const int taps = k * k * k;
+  std::vector<T> out((size_t)taps * nchunks * cout_pad32 * CC, to_t<T>(0.0f));
+  for (int tap = 0; tap < taps; ++tap)
+    for (int ch = 0; ch < nchunks; ++ch)
+      for (int n = 0; n < cout; ++n)
+        for (int e = 0; e < CC; ++e) {
+          const int c = sizeof(T) == 2 ? ch * CC + e : ch * CC + 2 * (e % 4) + (e / 4);
+          if (c >= cin) continue;
+          const float v = W[((size_t)n * cin + c) * taps + tap];
+          out[(((size_t)tap * nchunks + ch) * cout_pad32 + n) * CC + e] = to_t<T>(v);
+        }
+  return out;
+}
+
+std::vector<float> transpose(const float *w, int rows, int cols) {  // [rows][cols] -> [cols][rows]
+  std::vector<float> t((size_t)rows * cols);
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c) t[(size_t)c * rows + r] = w[(size_t)r * cols + c];
+  return t;
+}
+
+int upload_f(cf_ctx *c, float **dst, const float *src, size_t n) {
+  return alloc_weight(c, reinterpret_cast<void **>(dst), n * sizeof(float), src);
+}
+
+int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
+  if (!blob || nbytes < sizeof(cf_model_desc)) return fail(CF_ERR_INVALID_ARG, "model blob too small");
+  memcpy(&c->desc, blob, sizeof(cf_model_desc));
+  const cf_model_desc &d = c->desc;
+  if (d.magic != CF_MODEL_MAGIC) return fail(CF_ERR_INVALID_ARG, "bad model magic");
+  if (d.n_ch != CF_NCH) return fail(CF_ERR_INVALID_ARG, "model must take 19 feature channels");
+  if (d.n_conv < 1 || d.n_conv > 8) return fail(CF_ERR_INVALID_ARG, "n_conv must be 1..8");
+  if (d.H != 16 && d.H != 32 && d.H != 64) return fail(CF_ERR_UNSUPPORTED, "H must be 16, 32 or 64");
+  if (d.K_c < 0 || d.K_n < 0 || d.K_c > 8 || d.K_n > 8) return fail(CF_ERR_INVALID_ARG, "K_c, K_n must be 0..8");
+  if (d.r_cov_u <= 0 || d.r_nc_u <= 0 || d.r_cov_u > 65536 || d.r_nc_u > 65536)
+    return fail(CF_ERR_INVALID_ARG, "cutoffs must be 1..65536 u");
+  if (d.r_cov_u > d.r_nc_u) return fail(CF_ERR_UNSUPPORTED, "covalent cutoff must not exceed the non-covalent one");
+  if (d.cnn_dense < 0 || d.cnn_dense > 256 || d.fusion_hidden < 0 || d.fusion_hidden > 4096)
+    return fail(CF_ERR_INVALID_ARG, "bad dense sizes");
+  BlobReader R{reinterpret_cast<const float *>(reinterpret_cast<const char *>(blob) + sizeof(cf_model_desc)),
+               (nbytes - sizeof(cf_model_desc)) / sizeof(float)};
+  if ((nbytes - sizeof(cf_model_desc)) % sizeof(float)) return fail(CF_ERR_INVALID_ARG, "blob size not float-aligned");
+  const size_t total_floats = R.left;
+  int cin = CF_NCH;
+  int cin_pad = grid_cpad(c);
+  std::vector<int> chans{CF_NCH};
+  for (int i = 0; i < d.n_conv; ++i) {
+    const int ci = d.conv[i][0], co = d.conv[i][1], k = d.conv[i][2], st = d.conv[i][3], rs = d.conv[i][4];
+    if (ci != cin) return fail(CF_ERR_INVALID_ARG, "conv input channels do not chain");
+    if (co < 1 || co > 256) return fail(CF_ERR_INVALID_ARG, "conv output channels must be 1..256");
+    if ((k != 5 && k != 7)) return fail(CF_ERR_UNSUPPORTED, "conv kernel size must be 5 or 7");
+    if (st != 1 && st != 2) return fail(CF_ERR_INVALID_ARG, "conv stride must be 1 or 2");
+    if (rs >= 0) {
+      if (rs > i || chans[rs] != co) return fail(CF_ERR_INVALID_ARG, "residual source must match channels");
+      // spatial match: every conv between t_rs and t_{i+1} keeps the size
+      for (int q = rs; q <= i; ++q)
+        if (d.conv[q][3] != 1) return fail(CF_ERR_INVALID_ARG, "residual across a strided conv");
+    }
+    const size_t nw = (size_t)co * ci * k * k * k;
+    const float *W = R.take(nw), *b = R.take(co);
+    if (!W || !b) return fail(CF_ERR_INVALID_ARG, "blob truncated (conv)");
+    std::vector<double> sc(co, 1.0), sh(co, 0.0);
+    if (d.bn) {
+      const float *g = R.take(co), *bt = R.take(co), *mu = R.take(co), *var = R.take(co);
+      if (!g || !bt || !mu || !var) return fail(CF_ERR_INVALID_ARG, "blob truncated (bn)");
+      for (int o = 0; o < co; ++o) {
+        if (!(var[o] + 1e-5 > 0.0)) return fail(CF_ERR_INVALID_ARG, "BatchNorm variance must be > -eps");
+        sc[o] = (double)g[o] / std::sqrt((double)var[o] + 1e-5);
+        sh[o] = (double)bt[o] - (double)mu[o] * sc[o];
+      }
+    }
+    // fold: W' = W * sc, b' = b * sc + sh  (== (b - mu) * sc + beta)
+    std::vector<float> Wf(nw);
+    for (int o = 0; o < co; ++o)
+      for (size_t q = 0; q < (size_t)ci * k * k * k; ++q)
+        Wf[(size_t)o * ci * k * k * k + q] = (float)((double)W[(size_t)o * ci * k * k * k + q] * sc[o]);
+    cf::ConvLayer L{};
+    L.cin = ci;
+    L.cout = co;
+    L.k = k;
+    L.stride = st;
+    L.res_src = rs;
+    L.cin_pad = cin_pad;
+    L.cout_pad32 = (co + 31) / 32 * 32;
+    L.cout_store = c->bf16 ? (co + 15) / 16 * 16 : (co + 7) / 8 * 8;
+    std::vector<float> bf(L.cout_pad32, 0.0f);
+    for (int o = 0; o < co; ++o) bf[o] = (float)((double)b[o] * sc[o] + sh[o]);
+    int rc;
+    if (c->bf16) {
+      auto pk = pack_conv<bf16_t>(Wf, co, ci, k, cin_pad, L.cout_pad32);
+      rc = alloc_weight(c, &L.wpk, pk.size() * sizeof(bf16_t), pk.data());
+    } else {
+      auto pk = pack_conv<float>(Wf, co, ci, k, cin_pad, L.cout_pad32);
+      rc = alloc_weight(c, &L.wpk, pk.size() * sizeof(float), pk.data());
+    }
+    if (rc) return rc;
+    if ((rc = upload_f(c, &L.bias, bf.data(), bf.size()))) return rc;
+    c->conv.push_back(L);
+    chans.push_back(co);
+    cin = co;
+    cin_pad = L.cout_store;
+  }
+  c->c_last = cin;
+  if (c->c_last > 256) return fail(CF_ERR_UNSUPPORTED, "last conv width must be <= 256");
+  int rc;
+  if (d.cnn_dense) {
+    const float *W = R.take((size_t)d.cnn_dense * c->c_last), *b = R.take(d.cnn_dense);
+    if (!W || !b) return fail(CF_ERR_INVALID_ARG, "blob truncated (cnn dense)");
+    if ((rc = upload_f(c, &c->dense_w, W, (size_t)d.cnn_dense * c->c_last))) return rc;
+    if ((rc = upload_f(c, &c->dense_b, b, d.cnn_dense))) return rc;
+    c->lc = d.cnn_dense;
+  } else {
+    c->lc = c->c_last;
+  }
+  const int H = d.H;
+  cf::SgWeights &S = c->sg;
+  S.H = H;
+  S.K_c = d.K_c;
+  S.K_n = d.K_n;
+  {
+    const float *W = R.take((size_t)H * CF_NCH), *b = R.take(H);
+    if (!W || !b) return fail(CF_ERR_INVALID_ARG, "blob truncated (embed)");
+    auto t = transpose(W, H, CF_NCH);
+    float *p;
+    if ((rc = upload_f(c, &p, t.data(), t.size()))) return rc;
+    S.embed_wT = p;
+    if ((rc = upload_f(c, &p, b, H))) return rc;
+    S.embed_b = p;
+  }
+  int r = 0;
+  for (int stage = 0; stage < 2; ++stage) {
+    const int K = stage ? d.K_n : d.K_c;
+    for (int q = 0; q < K; ++q, ++r) {
+      const float *W = R.take((size_t)H * H);
+      if (!W) return fail(CF_ERR_INVALID_ARG, "blob truncated (message)");
+      auto t = transpose(W, H, H);
+      float *p;
+      if ((rc = upload_f(c, &p, t.data(), t.size()))) return rc;
+      S.msgT[r] = p;
+    }
+    const float *wih = R.take((size_t)3 * H * H), *whh = R.take((size_t)3 * H * H);
+    const float *bih = R.take(3 * H), *bhh = R.take(3 * H);
+    if (!wih || !whh || !bih || !bhh) return fail(CF_ERR_INVALID_ARG, "blob truncated (gru)");
+    auto ti = transpose(wih, 3 * H, H), th = transpose(whh, 3 * H, H);
+    float *p;
+    if ((rc = upload_f(c, &p, ti.data(), ti.size()))) return rc;
+    S.w_ihT[stage] = p;
+    if ((rc = upload_f(c, &p, th.data(), th.size()))) return rc;
+    S.w_hhT[stage] = p;
+    if ((rc = upload_f(c, &p, bih, 3 * H))) return rc;
+    S.b_ih[stage] = p;
+    if ((rc = upload_f(c, &p, bhh, 3 * H))) return rc;
+    S.b_hh[stage] = p;
+  }
+  {
+    const float *gw = R.take((size_t)H * (H + CF_NCH)), *gb = R.take(H);
+    const float *vw = R.take((size_t)H * H), *vb = R.take(H);
+    if (!gw || !gb || !vw || !vb) return fail(CF_ERR_INVALID_ARG, "blob truncated (readout)");
+    auto tg = transpose(gw, H, H + CF_NCH), tv = transpose(vw, H, H);
+    float *p;
+    if ((rc = upload_f(c, &p, tg.data(), tg.size()))) return rc;
+    S.gate_wT = p;
+    if ((rc = upload_f(c, &p, gb, H))) return rc;
+    S.gate_b = p;
+    if ((rc = upload_f(c, &p, tv.data(), tv.size()))) return rc;
+    S.val_wT = p;
+    if ((rc = upload_f(c, &p, vb, H))) return rc;
+    S.val_b = p;
+  }
+  const int nin = c->lc + H;
+  if (nin > 512) return fail(CF_ERR_UNSUPPORTED, "fusion input wider than 512");
+  if (d.fusion_hidden) {
+    const float *w1 = R.take((size_t)d.fusion_hidden * nin), *b1 = R.take(d.fusion_hidden);
+    const float *w2 = R.take(d.fusion_hidden), *b2 = R.take(1);
+    if (!w1 || !b1 || !w2 || !b2) return fail(CF_ERR_INVALID_ARG, "blob truncated (fusion)");
+    if ((rc = upload_f(c, &c->fus_w1, w1, (size_t)d.fusion_hidden * nin))) return rc;
+    if ((rc = upload_f(c, &c->fus_b1, b1, d.fusion_hidden))) return rc;
+    if ((rc = upload_f(c, &c->fus_w2, w2, d.fusion_hidden))) return rc;
+    if ((rc = upload_f(c, &c->fus_b2, b2, 1))) return rc;
+  } else {
+    const float *w2 = R.take(nin), *b2 = R.take(1);
+    if (!w2 || !b2) return fail(CF_ERR_INVALID_ARG, "blob truncated (fusion)");
+    if ((rc = upload_f(c, &c->fus_w2, w2, nin))) return rc;
+    if ((rc = upload_f(c, &c->fus_b2, b2, 1))) return rc;
+  }
+  if (R.left != 0) return fail(CF_ERR_INVALID_ARG, "blob has trailing data");
+  c->n_params = (int64_t)total_floats;
+  return CF_OK;
+}
+
+void free_ctx(cf_ctx *c) {
+  for (void *p : c->weight_allocs) (void)hipFree(p);
+  DevBuf *bufs[] = {&c->grid, &c->centers, &c->cnn_lat, &c->sg_lat, &c->deg, &c->pose_tot,
+                    &c->cov_row, &c->cov_col, &c->nc_row, &c->nc_col, &c->hbuf};
+  for (DevBuf *b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (auto &b : c->act)
+    if (b.p) (void)hipFree(b.p);
+  if (c->status) (void)hipFree(c->status);
+  delete c;
+}
+
+// per-atom scratch for a pose range holding at most `atoms` atoms
+int ensure_atoms(cf_ctx *c, int64_t atoms, int np) {
+  int rc;
+  const int H = c->desc.H;
+  if ((rc = ensure(c, c->deg, (size_t)2 * atoms * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(c, c->pose_tot, (size_t)4 * np * sizeof(int64_t)))) return rc;
+  if ((rc = ensure(c, c->cov_row, (size_t)(atoms + 1) * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(c, c->nc_row, (size_t)(atoms + 1) * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(c, c->cov_col, (size_t)atoms * 16 * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(c, c->nc_col, (size_t)atoms * 96 * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(c, c->hbuf, (size_t)2 * atoms * H * sizeof(float)))) return rc;
+  return CF_OK;
+}
+
+int64_t atoms_cap_for(const cf_pose_batch *b, int np) {
+  return std::min<int64_t>((int64_t)b->n_atoms, (int64_t)np * CF_MAX_POSE_ATOMS);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cf_last_error(void) { return g_last_error.c_str(); }
+
+int cf_create(const void *blob, size_t nbytes, int precision, int64_t hbm_budget_bytes, cf_ctx **out) {
+  if (!out) return fail(CF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (precision != CF_PREC_FP32 && precision != CF_PREC_BF16) return fail(CF_ERR_INVALID_ARG, "bad precision");
+  cf_ctx *c = new (std::nothrow) cf_ctx();
+  if (!c) return fail(CF_ERR_OOM, "host allocation failed");
+  c->bf16 = precision == CF_PREC_BF16;
+  c->budget = hbm_budget_bytes > 0 ? hbm_budget_bytes : ((int64_t)16 << 30);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(CF_ERR_HIP, "no HIP device");
+  }
+  int rc = build_model(c, blob, nbytes);
+  if (rc == CF_OK) {
+    if (hipMalloc(&c->status, 4 * sizeof(int64_t)) != hipSuccess ||
+        hipMemset(c->status, 0, 4 * sizeof(int64_t)) != hipSuccess)
+      rc = fail(CF_ERR_OOM, "status word allocation failed");
+  }
+  if (rc != CF_OK) {
+    free_ctx(c);
+    return rc;
+  }
+  *out = c;
+  return CF_OK;
+}
+
+void cf_destroy(cf_ctx *c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  free_ctx(c);
+}
+
+int cf_model_info(const cf_ctx *c, int32_t *latent_cnn, int32_t *latent_sg, int64_t *n_params, int32_t *precision) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  if (latent_cnn) *latent_cnn = c->lc;
+  if (latent_sg) *latent_sg = c->desc.H;
+  if (n_params) *n_params = c->n_params;
+  if (precision) *precision = c->bf16 ? CF_PREC_BF16 : CF_PREC_FP32;
+  return CF_OK;
+}
+
+int cf_pose_centers(cf_ctx *c, const cf_pose_batch *b, int32_t *center_out, void *stream) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  int rc = validate_batch(b);
+  if (rc) return rc;
+  if (!center_out) return fail(CF_ERR_INVALID_ARG, "center_out is NULL");
+  CF_HIP(cf::launch_centers(b->atom_off, b->n_atoms, b->xyz, b->is_lig, 0, b->n_poses, center_out, c->status, (hipStream_t)stream));
+  return CF_OK;
+}
+
+int cf_voxelize(cf_ctx *c, const cf_pose_batch *b, int G, void *grid_out, void *stream) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  int rc = validate_batch(b);
+  if (rc) return rc;
+  if ((rc = validate_G(G))) return rc;
+  if (!grid_out) return fail(CF_ERR_INVALID_ARG, "grid_out is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t *cen = b->center;
+  if (!cen) {
+    if ((rc = ensure(c, c->centers, (size_t)b->n_poses * 3 * sizeof(int32_t)))) return rc;
+    CF_HIP(cf::launch_centers(b->atom_off, b->n_atoms, b->xyz, b->is_lig, 0, b->n_poses, (int32_t *)c->centers.p, c->status, s));
+    cen = (const int32_t *)c->centers.p;
+  }
+  CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, 0, b->n_poses, G, grid_out, c->bf16 ? 1 : 0, 0,
+                          c->status, s));
+  return CF_OK;
+}
+
+int cf_build_graphs(cf_ctx *c, const cf_pose_batch *b, cf_csr *cov, cf_csr *nc, void *stream) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  int rc = validate_batch(b);
+  if (rc) return rc;
+  if (!cov || !nc || !cov->row_ptr || !nc->row_ptr || (cov->capacity > 0 && !cov->col) ||
+      (nc->capacity > 0 && !nc->col) || cov->capacity < 0 || nc->capacity < 0)
+    return fail(CF_ERR_INVALID_ARG, "bad CSR arguments");
+  if ((rc = ensure(c, c->deg, (size_t)2 * b->n_atoms * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(c, c->pose_tot, (size_t)4 * b->n_poses * sizeof(int64_t)))) return rc;
+  CF_HIP(cf::launch_graph(b->atom_off, b->n_atoms, b->xyz, 0, b->n_poses, c->desc.r_cov_u, c->desc.r_nc_u, cov->row_ptr,
+                          cov->col, cov->capacity, nc->row_ptr, nc->col, nc->capacity, (int32_t *)c->deg.p,
+                          (int64_t)b->n_atoms, (int64_t *)c->pose_tot.p, c->status, (hipStream_t)stream));
+  return CF_OK;
+}
+
+int cf_cnn3d_fwd(cf_ctx *c, const void *grid, int32_t n_poses, int G, float *cnn_latent, void *stream) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  if (!grid || !cnn_latent || n_poses < 1) return fail(CF_ERR_INVALID_ARG, "bad arguments");
+  int rc = validate_G(G);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int chunk = chunk_poses(c, G, n_poses);
+  if ((rc = ensure_act(c, G, chunk))) return rc;
+  const int64_t vox = (int64_t)G * G * G;
+  for (int p0 = 0; p0 < n_poses; p0 += chunk) {
+    const int np = std::min(chunk, n_poses - p0);
+    const char *src = reinterpret_cast<const char *>(grid) + (size_t)p0 * vox * CF_NCH * elem_size(c);
+    CF_HIP(cf::launch_grid_repack(src, c->bf16, (int)(np * vox), c->grid.p, c->bf16, grid_cpad(c), s));
+    if ((rc = run_cnn(c, G, np, cnn_latent + (size_t)p0 * c->lc, s))) return rc;
+  }
+  return CF_OK;
+}
+
+int cf_sgcnn_fwd(cf_ctx *c, const cf_pose_batch *b, const cf_csr *cov, const cf_csr *nc, float *sg_latent,
+                 void *stream) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  int rc = validate_batch(b);
+  if (rc) return rc;
+  if (!cov || !nc || !cov->row_ptr || !nc->row_ptr || !sg_latent) return fail(CF_ERR_INVALID_ARG, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const int chunk = std::min(b->n_poses, 512);
+  const int64_t acap = atoms_cap_for(b, chunk);
+  if ((rc = ensure(c, c->hbuf, (size_t)2 * acap * c->desc.H * sizeof(float)))) return rc;
+  for (int p0 = 0; p0 < b->n_poses; p0 += chunk) {
+    const int np = std::min(chunk, b->n_poses - p0);
+    CF_HIP(cf::launch_sgcnn(c->sg, c->bf16, b->atom_off, b->n_atoms, b->feat, b->is_lig, p0, np, cov->row_ptr, cov->col,
+                            cov->capacity, nc->row_ptr, nc->col, nc->capacity, 1, (float *)c->hbuf.p, acap,
+                            sg_latent + (size_t)p0 * c->desc.H, c->status, s));
+  }
+  return CF_OK;
+}
+
+int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void *stream) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  int rc = validate_batch(b);
+  if (rc) return rc;
+  if ((rc = validate_G(G))) return rc;
+  if (!scores) return fail(CF_ERR_INVALID_ARG, "scores is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int chunk = chunk_poses(c, G, b->n_poses);
+  const int64_t acap = atoms_cap_for(b, chunk);
+  if ((rc = ensure_act(c, G, chunk))) return rc;
+  if ((rc = ensure_atoms(c, acap, chunk))) return rc;
+  if ((rc = ensure(c, c->centers, (size_t)chunk * 3 * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(c, c->cnn_lat, (size_t)chunk * c->lc * sizeof(float)))) return rc;
+  if ((rc = ensure(c, c->sg_lat, (size_t)chunk * c->desc.H * sizeof(float)))) return rc;
+  const int H = c->desc.H;
+  for (int p0 = 0; p0 < b->n_poses; p0 += chunk) {
+    const int np = std::min(chunk, b->n_poses - p0);
+    const int32_t *cen;
+    const double atoms = (double)b->n_atoms * np / b->n_poses;  // for the byte counts only
+    if (b->center) {
+      cen = b->center + 3 * (size_t)p0;
+    } else {
+      hipEvent_t e = tbegin(c, s);
+      CF_HIP(cf::launch_centers(b->atom_off, b->n_atoms, b->xyz, b->is_lig, p0, np, (int32_t *)c->centers.p, c->status, s));
+      tend(c, s, e, "centers", 0.0, atoms * 13.0);
+      cen = (const int32_t *)c->centers.p;
+    }
+    hipEvent_t e = tbegin(c, s);
+    CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, p0, np, G, c->grid.p, c->bf16 ? 3 : 2,
+                            grid_cpad(c), c->status, s));
+    tend(c, s, e, "splat", 0.0, atoms * (12.0 + 4.0 * CF_NCH) + (double)np * G * G * G * CF_NCH * elem_size(c));
+    if ((rc = run_cnn(c, G, np, (float *)c->cnn_lat.p, s))) return rc;
+    e = tbegin(c, s);
+    CF_HIP(cf::launch_graph(b->atom_off, b->n_atoms, b->xyz, p0, np, c->desc.r_cov_u, c->desc.r_nc_u, (int32_t *)c->cov_row.p,
+                            (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
+                            acap * 96, (int32_t *)c->deg.p, acap, (int64_t *)c->pose_tot.p, c->status, s));
+    tend(c, s, e, "graph", 0.0, atoms * 12.0);
+    e = tbegin(c, s);
+    CF_HIP(cf::launch_sgcnn(c->sg, c->bf16, b->atom_off, b->n_atoms, b->feat, b->is_lig, p0, np, (int32_t *)c->cov_row.p,
+                            (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
+                            acap * 96, 0, (float *)c->hbuf.p, acap, (float *)c->sg_lat.p, c->status, s));
+    {
+      const double Hd = H, rounds = c->desc.K_c + c->desc.K_n;
+      tend(c, s, e, "sgcnn", atoms * (2.0 * CF_NCH * Hd + rounds * 2.0 * (Hd * Hd + 6.0 * Hd * Hd)), atoms * 4.0 * CF_NCH);
+    }
+    e = tbegin(c, s);
+    CF_HIP(cf::launch_fusion((float *)c->cnn_lat.p, c->lc, (float *)c->sg_lat.p, H, c->fus_w1, c->fus_b1,
+                             c->desc.fusion_hidden, c->fus_w2, c->fus_b2, np, scores + p0, s));
+    tend(c, s, e, "fusion", 0.0, 0.0);
+  }
+  return CF_OK;
+}
+
+int cf_stream_status(cf_ctx *c, void *stream, int64_t *need_cov, int64_t *need_nc) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  CF_HIP(hipStreamSynchronize((hipStream_t)stream));
+  int64_t st[4];
+  CF_HIP(hipMemcpy(st, c->status, sizeof(st), hipMemcpyDeviceToHost));
+  CF_HIP(hipMemset(c->status, 0, sizeof(st)));
+  if (need_cov) *need_cov = st[1];
+  if (need_nc) *need_nc = st[2];
+  switch (st[0]) {
+    case cf::kDevOk: return CF_OK;
+    case cf::kDevCapacity: return fail(CF_ERR_CAPACITY, "neighbour list capacity exceeded");
+    case cf::kDevBadOffsets: return fail(CF_ERR_INVALID_ARG, "atom_off malformed (decreasing, or a pose outside 1..4096 atoms)");
+    case cf::kDevBadFeature: return fail(CF_ERR_INVALID_ARG, "feature value not finite or |value| > 64");
+    case cf::kDevPoseTooLarge: return fail(CF_ERR_INVALID_ARG, "a pose has more than 4096 atoms");
+    case cf::kDevBadGraph: return fail(CF_ERR_INVALID_ARG, "neighbour list references an atom of another pose");
+    default: return fail(CF_ERR_INVALID_ARG, "device reported an invalid input");
+  }
+}
+
+int cf_timing_enable(cf_ctx *c, int enable) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  c->timing = enable != 0;
+  return CF_OK;
+}
+
+int cf_timing_read(cf_ctx *c, cf_kernel_stat *out, int32_t max_entries, int32_t *n_out) {
+  if (!c || (!out && max_entries > 0)) return fail(CF_ERR_INVALID_ARG, "bad arguments");
+  for (auto &p : c->pending) {
+    CF_HIP(hipEventSynchronize(p.e1));
+    float ms = 0.0f;
+    CF_HIP(hipEventElapsedTime(&ms, p.e0, p.e1));
+    auto &st = c->stats[p.key];
+    st.launches += 1;
+    st.ms += ms;
+    st.flop += p.flop;
+    st.bytes += p.bytes;
+    (void)hipEventDestroy(p.e0);
+    (void)hipEventDestroy(p.e1);
+  }
+  c->pending.clear();
+  int n = 0;
+  for (auto &kv : c->stats) {
+    if (n < max_entries) {
+      memset(&out[n], 0, sizeof(cf_kernel_stat));
+      strncpy(out[n].name, kv.first.c_str(), sizeof(out[n].name) - 1);
+      out[n].launches = kv.second.launches;
+      out[n].total_ms = kv.second.ms;
+      out[n].flop = kv.second.flop;
+      out[n].bytes = kv.second.bytes;
+    }
+    ++n;
+  }
+  if (n_out) *n_out = n;
+  c->stats.clear();
+  return CF_OK;
+}
+
+int cf_conv_variants(const cf_ctx *c, int G, int32_t *variant_out, int32_t max_layers) {
+  if (!c || !variant_out) return fail(CF_ERR_INVALID_ARG, "bad arguments");
+  std::vector<int> v;
+  int rc = variants_for(const_cast<cf_ctx *>(c), G, v);
+  if (rc) return rc;
+  for (int i = 0; i < (int)v.size() && i < max_layers; ++i) variant_out[i] = v[i];
+  return CF_OK;
+}
+
+int cf_autotune(cf_ctx *c, int G, int32_t n_poses, void *stream) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  int rc = validate_G(G);
+  if (rc) return rc;
+  if (n_poses < 1) return fail(CF_ERR_INVALID_ARG, "n_poses must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const int np = std::min(n_poses, chunk_poses(c, G, n_poses));
+  if ((rc = ensure_act(c, G, np))) return rc;
+  // deterministic non-zero inputs: small constant activations
+  CF_HIP(hipMemsetAsync(c->grid.p, 0x3c, c->grid.n, s));
+  for (auto &b : c->act) CF_HIP(hipMemsetAsync(b.p, 0x3c, b.n, s));
+  std::vector<int> best;
+  hipEvent_t e0, e1;
+  CF_HIP(hipEventCreate(&e0));
+  CF_HIP(hipEventCreate(&e1));
+  std::vector<const void *> t{c->grid.p};
+  for (auto &b : c->act) t.push_back(b.p);
+  int D = G;
+  for (size_t i = 0; i < c->conv.size(); ++i) {
+    const auto &L = c->conv[i];
+    float best_ms = 1e30f;
+    int best_v = -1;
+    for (int v = 0; v < cf::conv_num_variants(); ++v) {
+      if (!cf::conv_variant_ok(v, L, c->bf16)) continue;
+      const void *res = L.res_src >= 0 ? t[L.res_src] : nullptr;
+      CF_HIP(cf::launch_conv(v, L, c->bf16, t[i], res, c->act[i].p, np, D, s));  // warm-up
+      CF_HIP(hipEventRecord(e0, s));
+      for (int rep = 0; rep < 3; ++rep) CF_HIP(cf::launch_conv(v, L, c->bf16, t[i], res, c->act[i].p, np, D, s));
+      CF_HIP(hipEventRecord(e1, s));
+      CF_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      CF_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_v = v;
+      }
+    }
+    if (best_v < 0) return fail(CF_ERR_UNSUPPORTED, "no conv kernel for a layer");
+    best.push_back(best_v);
+    D = conv_out_dim(D, L.k, L.stride);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->variants[G] = best;
+  return CF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+// conv3d as an implicit GEMM on the CDNA4 matrix cores (MFMA).
+//
+// The 3D-CNN head (Sec. 3.3.1, Table III) is a stack of 3-D convolutions with
+// BatchNorm (folded into weights and bias at context creation), ReLU and
+// residual adds; it holds >99 % of the scoring FLOPs, so it is the one place the
+// path is a dense contraction: M = output voxels, N = output channels,
+// K = input channels x k^3 taps.
+//
+// Design (per workgroup = one spatial output tile of one pose, all of N or an
+// N-tile of 64/128 columns):
+//   * activations are channels-last; K is walked as (channel chunk, tap).  For
+//     each 16-channel chunk (bf16) or 8-channel chunk (fp32) the tile's input
+//     halo is staged once in LDS (32 bytes per voxel), then all k^3 taps are read
+//     from LDS as shifted windows: no im2col buffer, and each input byte is
+//     fetched from L2 once per tile and chunk.
+//   * LDS rows are padded by 16 bytes (so the 16 lanes of one ds_read_b128 phase
+//     hit disjoint banks) and stride-2 layers store the halo parity-split per
+//     axis, so consecutive output voxels stay 32 bytes apart for every tap.
+//   * the weight (B) fragments are pre-packed so that one 16-byte load per lane
+//     gives one MFMA operand; they stream from L2/L1 straight into VGPRs.
+//   * bf16: v_mfma_f32_32x32x16_bf16, one per (32-row block, 32-column block)
+//     per chunk-tap; fp32: four v_mfma_f32_32x32x2_f32 (channels stored
+//     even/odd-interleaved within a chunk so a lane's four K values are
+//     contiguous).  Accumulation is fp32 in both.
+//   * epilogue: + folded bias, + residual tensor, ReLU, convert, store.
+#include "cf_internal.h"
+
+namespace cf {
+
+namespace {
+
+template <typename T>
+struct Frag;
+template <>
+struct Frag<bf16_t> {
+  static constexpr int CC = 16;  // channels per chunk
+};
+template <>
+struct Frag<float> {
+  static constexpr int CC = 8;
+};
+
+__device__ inline int stored_index(int h, int n, int S) { return S == 1 ? h : (h & 1) * ((n + 1) >> 1) + (h >> 1); }
+
+template <typename T, int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+struct ConvCfg {
+  static constexpr int CC = Frag<T>::CC;
+  static constexpr int PAD = (KS - 1) / 2;
+  static constexpr int HZ = TZ * S + KS - S, HY = TY * S + KS - S, HX = TX * S + KS - S;
+  static constexpr int ROW = HX * 32 + 16;  // bytes
+  static constexpr int SLAB = HY * ROW;
+  static constexpr int LDS = HZ * SLAB;
+  static constexpr int MT = TZ * TY * TX;
+  static constexpr int WM = MT / NW;
+  static constexpr int MB = WM / 32, NB = NT / 32;
+  static_assert(WM % 32 == 0, "rows per wave must be a multiple of 32");
+  static_assert(LDS <= 163840, "halo exceeds LDS");
+};
+
+template <typename T, int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+__global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, const T *__restrict__ wpk,
+                                                   const float *__restrict__ bias,
+                                                   const T *__restrict__ res, T *__restrict__ out, int D,
+                                                   int Do, int cin_pad, int cout_pad32, int cout,
+                                                   int cout_store, int nty, int ntx) {
+  using C = ConvCfg<T, KS, S, TZ, TY, TX, NW, NT>;
+  constexpr int CC = C::CC;
+  __shared__ __attribute__((aligned(16))) char lds[C::LDS];
+
+  const int tile = blockIdx.x;
+  const int pose = blockIdx.y;
+  const int n0 = blockIdx.z * NT;
+  const int tz0 = (tile / (nty * ntx)) * TZ, ty0 = ((tile / ntx) % nty) * TY, tx0 = (tile % ntx) * TX;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int khalf = lane >> 5, lrow = lane & 31;
+  const int nchunks = cin_pad / CC;
+
+  // per M-block LDS byte offset of this lane's output row (tap (0,0,0))
+  int rowoff[C::MB];
+#pragma unroll
+  for (int mb = 0; mb < C::MB; ++mb) {
+    const int m = wave * C::WM + mb * 32 + lrow;
+    const int z = m / (TY * TX), y = (m / TX) % TY, x = m % TX;
+    rowoff[mb] = z * C::SLAB + y * C::ROW + x * 32 + khalf * 16;
+  }
+
+  typedef float accv __attribute__((ext_vector_type(16)));
+  accv acc[C::MB][C::NB];
+#pragma unroll
+  for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
+
+  const int oz = tz0 * S - C::PAD, oy = ty0 * S - C::PAD, ox = tx0 * S - C::PAD;
+  const int64_t pose_in = (int64_t)pose * D * D * D;
+  constexpr int HZ2 = S == 1 ? 0 : (C::HZ + 1) / 2;
+  constexpr int HY2 = S == 1 ? 0 : (C::HY + 1) / 2;
+  constexpr int HX2 = S == 1 ? 0 : (C::HX + 1) / 2;
+
+  for (int chunk = 0; chunk < nchunks; ++chunk) {
+    __syncthreads();
+    // ---- stage the halo of this channel chunk: 32 bytes per voxel ----
+    constexpr int NV = C::HZ * C::HY * C::HX;
+    for (int v = threadIdx.x; v < NV; v += NW * 64) {
+      const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
+      const int gz = oz + hz, gy = oy + hy, gx = ox + hx;
+      uint4 lo = make_uint4(0, 0, 0, 0), hi = make_uint4(0, 0, 0, 0);
+      if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gx < (unsigned)D) {
+        const T *src = in + ((pose_in + ((int64_t)gz * D + gy) * D + gx) * cin_pad + chunk * CC);
+        lo = reinterpret_cast<const uint4 *>(src)[0];
+        hi = reinterpret_cast<const uint4 *>(src)[1];
+        if (sizeof(T) == 4) {  // fp32: channels (0..7) -> (0,2,4,6 | 1,3,5,7)
+          const uint4 a = lo, b = hi;
+          lo = make_uint4(a.x, a.z, b.x, b.z);
+          hi = make_uint4(a.y, a.w, b.y, b.w);
+        }
+      }
+      const int off = stored_index(hz, C::HZ, S) * C::SLAB + stored_index(hy, C::HY, S) * C::ROW +
+                      stored_index(hx, C::HX, S) * 32;
+      *reinterpret_cast<uint4 *>(lds + off) = lo;
+      *reinterpret_cast<uint4 *>(lds + off + 16) = hi;
+    }
+    __syncthreads();
+
+    const T *wchunk = wpk + ((int64_t)chunk * cout_pad32 + n0 + lrow) * CC + khalf * (CC / 2);
+    const int64_t tap_stride = (int64_t)nchunks * cout_pad32 * CC;
+    for (int dz = 0; dz < KS; ++dz) {
+      const int offz = (S == 1 ? dz : (dz & 1) * HZ2 + (dz >> 1)) * C::SLAB;
+      for (int dy = 0; dy < KS; ++dy) {
+        const int offzy = offz + (S == 1 ? dy : (dy & 1) * HY2 + (dy >> 1)) * C::ROW;
+        const T *wrow = wchunk + (int64_t)((dz * KS + dy) * KS) * tap_stride;
+#pragma unroll
+        for (int dx = 0; dx < KS; ++dx) {
+          const int toff = offzy + (S == 1 ? dx : (dx & 1) * HX2 + (dx >> 1)) * 32;
+          const T *wt = wrow + (int64_t)dx * tap_stride;
+          uint4 bfr[C::NB];
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) bfr[nb] = *reinterpret_cast<const uint4 *>(wt + nb * 32 * CC);
+          uint4 afr[C::MB];
+#pragma unroll
+          for (int mb = 0; mb < C::MB; ++mb) afr[mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + toff);
+#pragma unroll
+          for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb) {
+              if constexpr (sizeof(T) == 2) {
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, afr[mb]), __builtin_bit_cast(bf16x8, bfr[nb]), acc[mb][nb], 0, 0, 0);
+              } else {
+                const float4 a = __builtin_bit_cast(float4, afr[mb]);
+                const float4 b = __builtin_bit_cast(float4, bfr[nb]);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc[mb][nb], 0, 0, 0);
+              }
+            }
+        }
+      }
+    }
+  }
+
+  // ---- epilogue: bias, residual, ReLU, store ----
+  const int64_t pose_out = (int64_t)pose * Do * Do * Do;
+#pragma unroll
+  for (int mb = 0; mb < C::MB; ++mb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = wave * C::WM + mb * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
+      const int z = tz0 + m / (TY * TX), y = ty0 + (m / TX) % TY, x = tx0 + m % TX;
+      if (z >= Do || y >= Do || x >= Do) continue;
+      const int64_t ob = (pose_out + ((int64_t)z * Do + y) * Do + x) * cout_store;
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb) {
+        const int n = n0 + nb * 32 + lrow;
+        if (n >= cout) continue;
+        float v = acc[mb][nb][r] + bias[n];
+        if (res) v += (float)res[ob + n];
+        v = v > 0.0f ? v : 0.0f;
+        out[ob + n] = (T)v;
+      }
+    }
+  }
+}
+
+struct Variant {
+  const char *name;
+  int ks, s, tz, ty, tx, nw, nt;
+  hipError_t (*launch_bf16)(const ConvLayer &, const void *, const void *, void *, int, int, hipStream_t);
+  hipError_t (*launch_f32)(const ConvLayer &, const void *, const void *, void *, int, int, hipStream_t);
+};
+
+template <typename T, int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+hipError_t launch_t(const ConvLayer &L, const void *in, const void *res, void *out, int n_poses, int D,
+                    hipStream_t s) {
+  const int Do = (D + 2 * ((KS - 1) / 2) - KS) / S + 1;
+  const int ntz = (Do + TZ - 1) / TZ, nty = (Do + TY - 1) / TY, ntx = (Do + TX - 1) / TX;
+  const dim3 grid(ntz * nty * ntx, n_poses, L.cout_pad32 / NT);
+  hipLaunchKernelGGL((k_conv<T, KS, S, TZ, TY, TX, NW, NT>), grid, dim3(NW * 64), 0, s,
+                     reinterpret_cast<const T *>(in), reinterpret_cast<const T *>(L.wpk), L.bias,
+                     reinterpret_cast<const T *>(res), reinterpret_cast<T *>(out), D, Do, L.cin_pad,
+                     L.cout_pad32, L.cout, L.cout_store, nty, ntx);
+  return hipGetLastError();
+}
+
+#define CF_VARIANT(KS, S, TZ, TY, TX, NW, NT)                                              \
+  Variant {                                                                                \
+    "k" #KS "s" #S "_t" #TZ "x" #TY "x" #TX "_w" #NW "_n" #NT, KS, S, TZ, TY, TX, NW, NT, \
+        &launch_t<bf16_t, KS, S, TZ, TY, TX, NW, NT>, &launch_t<float, KS, S, TZ, TY, TX, NW, NT> \
+  }
+
+const Variant kVariants[] = {
+    CF_VARIANT(7, 1, 8, 8, 8, 4, 64),   // 0: full-model residual layers
+    CF_VARIANT(7, 1, 4, 8, 8, 4, 64),   // 1
+    CF_VARIANT(7, 1, 8, 8, 8, 8, 64),   // 2
+    CF_VARIANT(7, 2, 4, 4, 8, 4, 64),   // 3: stride-2 layers
+    CF_VARIANT(7, 2, 4, 4, 8, 4, 128),  // 4
+    CF_VARIANT(7, 2, 2, 8, 8, 4, 64),   // 5
+    CF_VARIANT(5, 1, 8, 8, 8, 4, 32),   // 6: tiny model
+    CF_VARIANT(5, 1, 4, 8, 8, 4, 32),   // 7
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+}  // namespace
+
+int conv_num_variants() { return kNumVariants; }
+const char *conv_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : "?"; }
+
+bool conv_variant_ok(int v, const ConvLayer &L, int bf16) {
+  if (v < 0 || v >= kNumVariants) return false;
+  const Variant &V = kVariants[v];
+  const int cc = bf16 ? 16 : 8;
+  return V.ks == L.k && V.s == L.stride && L.cout_pad32 % V.nt == 0 && L.cin_pad % cc == 0;
+}
+
+int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
+  (void)D_in;
+  const int pref[] = {0, 4, 3, 6, 1, 2, 5, 7};
+  for (int v : pref)
+    if (conv_variant_ok(v, L, bf16)) return v;
+  return -1;
+}
+
+hipError_t launch_conv(int variant, const ConvLayer &L, int bf16, const void *in, const void *res,
+                       void *out, int n_poses, int D_in, hipStream_t s) {
+  if (!conv_variant_ok(variant, L, bf16)) return hipErrorInvalidValue;
+  const Variant &V = kVariants[variant];
+  return bf16 ? V.launch_bf16(L, in, res, out, n_poses, D_in, s) : V.launch_f32(L, in, res, out, n_poses, D_in, s);
+}
+
+}  // namespace cf

@@ -1,0 +1,108 @@
+// Global average pooling + dense head of the 3D-CNN, and the fusion head.
+//
+// Pooling and the CNN dense layer close the 3D-CNN (Sec. 3.3.1, Table III: dense
+// nodes); the fusion head concatenates the two latents and applies the fusion
+// dense layers with SELU (Coherent Fusion, Sec. 2.2 / 3.3.3, Table V) to give one
+// pK (Eq. 1).  Inference applies no dropout.  Reductions run in a fixed order,
+// so a pose's result does not depend on the batch it is scored in.
+#include "cf_internal.h"
+
+namespace cf {
+
+namespace {
+
+constexpr float kSeluLambda = 1.0507009873554804934193349852946f;
+constexpr float kSeluAlpha = 1.6732632423543772848170429916717f;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pool_dense(const T *__restrict__ act, int vox, int cstride, int c,
+                                                    const float *__restrict__ dw, const float *__restrict__ db,
+                                                    int n_dense, float *__restrict__ latent) {
+  __shared__ float part[4][256];
+  __shared__ float mean[256];
+  const int pose = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const T *a = act + (int64_t)pose * vox * cstride;
+  float s[4] = {0.f, 0.f, 0.f, 0.f};  // channels lane, lane+64, lane+128, lane+192
+  for (int v = wave; v < vox; v += 4) {
+    const T *row = a + (int64_t)v * cstride;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = lane + 64 * q;
+      if (ch < c) s[q] += (float)row[ch];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) part[wave][lane + 64 * q] = s[q];
+  __syncthreads();
+  const float inv = 1.0f / (float)vox;
+  for (int ch = threadIdx.x; ch < c; ch += 256)
+    mean[ch] = ((part[0][ch] + part[1][ch]) + (part[2][ch] + part[3][ch])) * inv;
+  __syncthreads();
+  if (n_dense == 0) {
+    for (int ch = threadIdx.x; ch < c; ch += 256) latent[(int64_t)pose * c + ch] = mean[ch];
+  } else {
+    for (int o = threadIdx.x; o < n_dense; o += 256) {
+      float acc = db[o];
+      for (int k = 0; k < c; ++k) acc += dw[o * c + k] * mean[k];
+      latent[(int64_t)pose * n_dense + o] = acc > 0.f ? acc : 0.f;
+    }
+  }
+}
+
+__device__ inline float selu(float x) { return x > 0.f ? kSeluLambda * x : kSeluLambda * kSeluAlpha * expm1f(x); }
+
+// One wavefront per pose.
+__global__ __launch_bounds__(64) void k_fusion(const float *__restrict__ cnn, int lc, const float *__restrict__ sg,
+                                               int H, const float *__restrict__ w1, const float *__restrict__ b1,
+                                               int hidden, const float *__restrict__ w2,
+                                               const float *__restrict__ b2, float *__restrict__ scores) {
+  __shared__ float z[512];
+  const int pose = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int nin = lc + H;
+  for (int k = lane; k < nin; k += 64)
+    z[k] = k < lc ? cnn[(int64_t)pose * lc + k] : sg[(int64_t)pose * H + (k - lc)];
+  __syncthreads();
+  float part = 0.f;
+  if (hidden > 0) {
+    for (int o = lane; o < hidden; o += 64) {
+      float acc = b1[o];
+      for (int k = 0; k < nin; ++k) acc += w1[o * nin + k] * z[k];
+      part += w2[o] * selu(acc);
+    }
+  } else {
+    for (int k = lane; k < nin; k += 64) part += w2[k] * z[k];
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+  if (lane == 0) scores[pose] = part + b2[0];
+}
+
+}  // namespace
+
+hipError_t launch_pool_dense(const void *act, int bf16, int n_poses, int vox, int cstride, int c,
+                             const float *dense_w, const float *dense_b, int n_dense, float *latent,
+                             hipStream_t s) {
+  if (n_poses <= 0) return hipSuccess;
+  if (c > 256 || n_dense > 256) return hipErrorInvalidValue;
+  if (bf16)
+    hipLaunchKernelGGL(k_pool_dense<bf16_t>, dim3(n_poses), dim3(256), 0, s, reinterpret_cast<const bf16_t *>(act),
+                       vox, cstride, c, dense_w, dense_b, n_dense, latent);
+  else
+    hipLaunchKernelGGL(k_pool_dense<float>, dim3(n_poses), dim3(256), 0, s, reinterpret_cast<const float *>(act),
+                       vox, cstride, c, dense_w, dense_b, n_dense, latent);
+  return hipGetLastError();
+}
+
+hipError_t launch_fusion(const float *cnn_lat, int lc, const float *sg_lat, int H, const float *w1,
+                         const float *b1, int hidden, const float *w2, const float *b2, int n_poses,
+                         float *scores, hipStream_t s) {
+  if (n_poses <= 0) return hipSuccess;
+  if (lc + H > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fusion, dim3(n_poses), dim3(64), 0, s, cnn_lat, lc, sg_lat, H, w1, b1, hidden, w2, b2,
+                     scores);
+  return hipGetLastError();
+}
+
+}  // namespace cf

@@ -1,0 +1,106 @@
+// Internal declarations shared by the HIP translation units of libcf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cf.h"
+
+namespace cf {
+
+typedef __bf16 bf16_t;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Fixed-point scale of the splat accumulators: 2^20 units per feature unit.
+constexpr float kSplatScale = 1048576.0f;
+constexpr float kSplatInvScale = 1.0f / 1048576.0f;
+constexpr float kFeatMax = 64.0f;
+
+// Device status word layout (int64[4]): [0] first error code (0 = none),
+// [1] covalent edges needed, [2] non-covalent edges needed, [3] detail.
+enum DevErr : int64_t {
+  kDevOk = 0,
+  kDevBadOffsets = 1,
+  kDevBadFeature = 2,
+  kDevCoordRange = 3,
+  kDevCapacity = 4,
+  kDevPoseTooLarge = 5,
+  kDevBadGraph = 6,
+};
+
+__device__ inline void dev_fail(int64_t *status, int64_t code) {
+  atomicCAS(reinterpret_cast<unsigned long long *>(status), 0ull, (unsigned long long)code);
+}
+
+// Atom range [a0, a1) of pose p, checked against the batch arrays (n_atoms rows).
+// Malformed offsets give an empty range and false.
+__device__ inline bool pose_range(const int32_t *atom_off, int p, int n_atoms, int &a0, int &a1) {
+  a0 = atom_off[p];
+  a1 = atom_off[p + 1];
+  const bool ok = a0 >= 0 && a1 >= a0 && a1 <= n_atoms && a1 - a0 <= CF_MAX_POSE_ATOMS;
+  if (!ok) a1 = a0 = 0;
+  return ok;
+}
+
+// ---- per-layer conv launch description (host side) ----
+struct ConvLayer {
+  int cin, cout, k, stride, res_src;
+  int cin_pad;     // input channel stride (multiple of the chunk width)
+  int cout_pad32;  // output channels rounded up to 32 (packed weight rows)
+  int cout_store;  // output channel stride (multiple of 16)
+  void *wpk;       // packed weights (precision dtype)
+  float *bias;     // folded bias [cout_pad32]
+};
+
+// Kernel launchers (defined in the .hip files).
+hipError_t launch_centers(const int32_t *atom_off, int n_atoms, const int32_t *xyz, const uint8_t *is_lig,
+                          int p0, int n_poses, int32_t *center_out, int64_t *status, hipStream_t s);
+// out_mode: 0 = float [19], 1 = bf16 [19], 2 = float padded [cpad], 3 = bf16 padded [cpad]
+hipError_t launch_splat(const int32_t *atom_off, int n_atoms, const int32_t *xyz, const float *feat,
+                        const int32_t *centers, int p0, int n_poses, int G, void *grid, int out_mode,
+                        int cpad, int64_t *status, hipStream_t s);
+hipError_t launch_grid_repack(const void *src, int src_bf16, int n_vox, void *dst, int dst_bf16,
+                              int cpad, hipStream_t s);
+
+hipError_t launch_graph(const int32_t *atom_off, int n_atoms, const int32_t *xyz, int p0, int n_poses, int r_cov,
+                        int r_nc, int32_t *cov_row, int32_t *cov_col, int64_t cov_cap, int32_t *nc_row,
+                        int32_t *nc_col, int64_t nc_cap, int32_t *deg_scratch, int64_t n_chunk_cap,
+                        int64_t *pose_scratch, int64_t *status, hipStream_t s);
+
+int conv_num_variants();
+const char *conv_variant_name(int v);
+bool conv_variant_ok(int v, const ConvLayer &L, int bf16);
+int conv_default_variant(const ConvLayer &L, int D_in, int bf16);
+hipError_t launch_conv(int variant, const ConvLayer &L, int bf16, const void *in, const void *res,
+                       void *out, int n_poses, int D_in, hipStream_t s);
+
+hipError_t launch_pool_dense(const void *act, int bf16, int n_poses, int vox, int cstride, int c,
+                             const float *dense_w, const float *dense_b, int n_dense, float *latent,
+                             hipStream_t s);
+
+// SG-CNN weights on the device, transposed to [k][out] so that consecutive lanes
+// (consecutive outputs) read consecutive words.
+struct SgWeights {
+  int H, K_c, K_n;
+  const float *embed_wT, *embed_b;  // [19][H], [H]
+  const float *msgT[16];            // per round [H][H] (covalent rounds first)
+  const float *w_ihT[2], *w_hhT[2]; // per stage [H][3H] (gate columns r, z, n)
+  const float *b_ih[2], *b_hh[2];   // per stage [3H]
+  const float *gate_wT, *gate_b;    // [H+19][H], [H]
+  const float *val_wT, *val_b;      // [H][H], [H]
+};
+// csr_global = 1: rows indexed by global atom id and columns are global ids (the
+// public neighbour-list layout); 0: both are relative to the first atom of pose p0.
+hipError_t launch_sgcnn(const SgWeights &W, int bf16, const int32_t *atom_off, int n_atoms, const float *feat,
+                        const uint8_t *is_lig, int p0, int n_poses, const int32_t *cov_row,
+                        const int32_t *cov_col, int64_t cov_cap, const int32_t *nc_row,
+                        const int32_t *nc_col, int64_t nc_cap, int csr_global, float *hbuf,
+                        int64_t hcap_atoms, float *sg_latent, int64_t *status, hipStream_t s);
+
+hipError_t launch_fusion(const float *cnn_lat, int lc, const float *sg_lat, int H, const float *w1,
+                         const float *b1, int hidden, const float *w2, const float *b2, int n_poses,
+                         float *scores, hipStream_t s);
+
+}  // namespace cf

@@ -1,0 +1,257 @@
+// Pose centres and Gaussian atom splatting into channels-last voxel grids.
+//
+// Voxelisation is the 3D-CNN's input representation (Sec. 1); its sizing and
+// atom propagation are taken from the predecessor model (Sec. 3.3).  Here: 1 A
+// voxels centred on the pose centre, Gaussian weights exp(-d^2 / 2 sigma^2) with
+// sigma = 0.5 A truncated at 3 sigma, normalised per atom over its whole support.
+//
+// Design: one workgroup per (pose, 2 x 4 x G tile).  The tile's accumulators sit
+// in LDS as 2^20 fixed-point int32, so the atomics are exact and the result does
+// not depend on the order in which waves add contributions.  Each wave culls 64
+// atoms at a time against the tile (one atom per lane, ballot), then sweeps the
+// survivors: an atom's candidate voxels form at most a 4 x 4 x 4 box, one per
+// lane, so the normaliser is a single (exact, integer) wavefront reduction and
+// the adds are wavefront-wide LDS atomics.  The finished tile is streamed to HBM
+// once.  Results are bitwise independent of launch shape and atom scheduling, so
+// a 90 degree rotation of a pose permutes its grid exactly.
+#include "cf_internal.h"
+
+namespace cf {
+
+namespace {
+
+constexpr int kTA = 2, kTB = 4;   // tile extent along grid axes 0 and 1 (axis 2 whole)
+constexpr int kRcut = 1536;       // 3 sigma in u
+constexpr float kInv2s2 = 1.0f / 524288.0f;
+
+__device__ inline int64_t floordiv(int64_t a, int64_t b) {  // b > 0
+  int64_t q = a / b;
+  return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+__device__ inline int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_centers(const int32_t *__restrict__ atom_off, int n_atoms,
+                                                const int32_t *__restrict__ xyz,
+                                                const uint8_t *__restrict__ is_lig, int p0,
+                                                int32_t *__restrict__ center_out, int64_t *status) {
+  const int p = p0 + blockIdx.x;
+  int a0, a1;
+  if (!pose_range(atom_off, p, n_atoms, a0, a1) && threadIdx.x == 0) dev_fail(status, kDevBadOffsets);
+  int64_t s[3] = {0, 0, 0}, sa[3] = {0, 0, 0};
+  int n = 0, na = 0;
+  for (int a = a0 + threadIdx.x; a < a1; a += 64) {
+    const int l = is_lig[a] != 0;
+    for (int d = 0; d < 3; ++d) {
+      const int64_t x = xyz[3 * a + d];
+      sa[d] += x;
+      if (l) s[d] += x;
+    }
+    n += l;
+    na += 1;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    for (int d = 0; d < 3; ++d) {
+      s[d] += __shfl_xor(s[d], o, 64);
+      sa[d] += __shfl_xor(sa[d], o, 64);
+    }
+    n += __shfl_xor(n, o, 64);
+    na += __shfl_xor(na, o, 64);
+  }
+  if (threadIdx.x < 3) {
+    const int d = threadIdx.x;
+    const int64_t sd = d == 0 ? s[0] : (d == 1 ? s[1] : s[2]);
+    const int64_t sad = d == 0 ? sa[0] : (d == 1 ? sa[1] : sa[2]);
+    const int64_t S = n > 0 ? sd : sad;
+    const int64_t N = n > 0 ? n : (na > 0 ? na : 1);
+    center_out[3 * (p - p0) + d] = (int32_t)floordiv(2 * S + N, 2 * N);
+  }
+}
+
+// MODE 0: float [19]; 1: bf16 [19]; 2: float [cpad]; 3: bf16 [cpad] (channels >= 19 zero)
+template <int MODE>
+__global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_off, int n_atoms,
+                                               const int32_t *__restrict__ xyz,
+                                               const float *__restrict__ feat,
+                                               const int32_t *__restrict__ centers, int p0, int G,
+                                               void *__restrict__ grid, int cpad,
+                                               int64_t *__restrict__ status) {
+  extern __shared__ int acc[];  // [kTA][kTB][G][19]
+  const int pl = blockIdx.y;    // pose within this launch
+  const int p = p0 + pl;
+  const int ntb = G / kTB;
+  const int i0 = (blockIdx.x / ntb) * kTA, j0 = (blockIdx.x % ntb) * kTB;
+  const int nacc = kTA * kTB * G * CF_NCH;
+  for (int e = threadIdx.x; e < nacc; e += blockDim.x) acc[e] = 0;
+  int a0, a1;
+  if (!pose_range(atom_off, p, n_atoms, a0, a1) && blockIdx.x == 0 && threadIdx.x == 0)
+    dev_fail(status, kDevBadOffsets);
+  const int64_t c0 = centers[3 * pl], c1 = centers[3 * pl + 1], c2 = centers[3 * pl + 2];
+  const int64_t off = 512LL * (G - 1);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int aend = a1;
+  for (int base = a0 + wave * 64; base < aend; base += 256) {
+    const int a = base + lane;
+    bool ov = false;
+    int lo0 = 0, lo1 = 0, lo2 = 0;
+    if (a < aend) {
+      const int64_t X0 = xyz[3 * a] - c0, X1 = xyz[3 * a + 1] - c1, X2 = xyz[3 * a + 2] - c2;
+      lo0 = (int)floordiv(X0 + off - kRcut + 1023, 1024);
+      lo1 = (int)floordiv(X1 + off - kRcut + 1023, 1024);
+      lo2 = (int)floordiv(X2 + off - kRcut + 1023, 1024);
+      const int hi0 = (int)floordiv(X0 + off + kRcut, 1024);
+      const int hi1 = (int)floordiv(X1 + off + kRcut, 1024);
+      const int hi2 = (int)floordiv(X2 + off + kRcut, 1024);
+      ov = lo0 <= i0 + kTA - 1 && hi0 >= i0 && lo1 <= j0 + kTB - 1 && hi1 >= j0 && lo2 <= G - 1 &&
+           hi2 >= 0;
+    }
+    uint64_t m = __ballot(ov);
+    while (m) {
+      const int b = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int ai = base + b;
+      const int l0 = __shfl(lo0, b, 64), l1 = __shfl(lo1, b, 64), l2 = __shfl(lo2, b, 64);
+      const int64_t X0 = xyz[3 * ai] - c0, X1 = xyz[3 * ai + 1] - c1, X2 = xyz[3 * ai + 2] - c2;
+      const int v0 = l0 + (lane >> 4), v1 = l1 + ((lane >> 2) & 3), v2 = l2 + (lane & 3);
+      const int64_t d0 = X0 - 512LL * (2 * v0 - G + 1);
+      const int64_t d1 = X1 - 512LL * (2 * v1 - G + 1);
+      const int64_t d2 = X2 - 512LL * (2 * v2 - G + 1);
+      const int64_t D = d0 * d0 + d1 * d1 + d2 * d2;
+      const bool in = D <= (int64_t)kRcut * kRcut;
+      const float w = in ? expf(-(float)D * kInv2s2) : 0.0f;
+      // Normaliser: every w >= exp(-4.5) > 2^-7 is an exact multiple of 2^-31, so
+      // w * 2^40 is an exact integer and the integer wave sum is the exact sum of
+      // the float weights, whatever lane holds which voxel.
+      const int64_t wq = (int64_t)((double)w * 1099511627776.0);
+      const double Z = (double)wave_sum_i64(wq) * (1.0 / 1099511627776.0);
+      const float f = (float)((double)w / Z);
+      const bool tile = in && v0 >= i0 && v0 < i0 + kTA && v1 >= j0 && v1 < j0 + kTB && v2 >= 0 && v2 < G;
+      if (tile) {
+        int *dst = acc + (((v0 - i0) * kTB + (v1 - j0)) * G + v2) * CF_NCH;
+        const float *F = feat + (int64_t)CF_NCH * ai;
+        for (int ch = 0; ch < CF_NCH; ++ch) {
+          const float fv = F[ch];
+          if (!(fabsf(fv) <= kFeatMax)) {
+            dev_fail(status, kDevBadFeature);
+            continue;
+          }
+          atomicAdd(dst + ch, (int)rintf(fv * f * kSplatScale));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // stream the tile out
+  const int nvox = kTA * kTB * G;
+  if (MODE == 0 || MODE == 1) {
+    for (int e = threadIdx.x; e < nvox * CF_NCH; e += blockDim.x) {
+      const int v = e / CF_NCH, ch = e - v * CF_NCH;
+      const int k = v % G, jj = (v / G) % kTB, ii = v / (G * kTB);
+      const int64_t gv = (((int64_t)pl * G + (i0 + ii)) * G + (j0 + jj)) * G + k;
+      const float val = (float)acc[e] * kSplatInvScale;
+      if (MODE == 0)
+        reinterpret_cast<float *>(grid)[gv * CF_NCH + ch] = val;
+      else
+        reinterpret_cast<bf16_t *>(grid)[gv * CF_NCH + ch] = (bf16_t)val;
+    }
+  } else {
+    const int ng = cpad / 8;
+    for (int e = threadIdx.x; e < nvox * ng; e += blockDim.x) {
+      const int v = e / ng, g = e - v * ng;
+      const int k = v % G, jj = (v / G) % kTB, ii = v / (G * kTB);
+      const int64_t gv = (((int64_t)pl * G + (i0 + ii)) * G + (j0 + jj)) * G + k;
+      float val[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int ch = g * 8 + q;
+        val[q] = ch < CF_NCH ? (float)acc[v * CF_NCH + ch] * kSplatInvScale : 0.0f;
+      }
+      if (MODE == 2) {
+        float4 *dst = reinterpret_cast<float4 *>(reinterpret_cast<float *>(grid) + gv * cpad + g * 8);
+        dst[0] = make_float4(val[0], val[1], val[2], val[3]);
+        dst[1] = make_float4(val[4], val[5], val[6], val[7]);
+      } else {
+        bf16x8 pk;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pk[q] = (bf16_t)val[q];
+        *reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16_t *>(grid) + gv * cpad + g * 8) = pk;
+      }
+    }
+  }
+}
+
+// Public [19]-channel grid -> internal padded [cpad] grid (conversion between
+// precisions allowed).
+__global__ __launch_bounds__(256) void k_grid_repack(const void *__restrict__ src, int src_bf16,
+                                                     int64_t n_vox, void *__restrict__ dst,
+                                                     int dst_bf16, int cpad) {
+  const int ng = cpad / 8;
+  const int64_t total = n_vox * ng;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = e / ng;
+    const int g = (int)(e - v * ng);
+    float val[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int ch = g * 8 + q;
+      if (ch < CF_NCH)
+        val[q] = src_bf16 ? (float)reinterpret_cast<const bf16_t *>(src)[v * CF_NCH + ch]
+                          : reinterpret_cast<const float *>(src)[v * CF_NCH + ch];
+      else
+        val[q] = 0.0f;
+    }
+    if (dst_bf16) {
+      bf16x8 pk;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) pk[q] = (bf16_t)val[q];
+      *reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16_t *>(dst) + v * cpad + g * 8) = pk;
+    } else {
+      float4 *d = reinterpret_cast<float4 *>(reinterpret_cast<float *>(dst) + v * cpad + g * 8);
+      d[0] = make_float4(val[0], val[1], val[2], val[3]);
+      d[1] = make_float4(val[4], val[5], val[6], val[7]);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_centers(const int32_t *atom_off, int n_atoms, const int32_t *xyz, const uint8_t *is_lig,
+                          int p0, int n_poses, int32_t *center_out, int64_t *status, hipStream_t s) {
+  if (n_poses <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_centers, dim3(n_poses), dim3(64), 0, s, atom_off, n_atoms, xyz, is_lig, p0, center_out,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t launch_splat(const int32_t *atom_off, int n_atoms, const int32_t *xyz, const float *feat,
+                        const int32_t *centers, int p0, int n_poses, int G, void *grid, int out_mode,
+                        int cpad, int64_t *status, hipStream_t s) {
+  if (n_poses <= 0) return hipSuccess;
+  const dim3 grd((G / kTA) * (G / kTB), n_poses);
+  const size_t lds = sizeof(int) * kTA * kTB * G * CF_NCH;
+  switch (out_mode) {
+    case 0: hipLaunchKernelGGL(k_splat<0>, grd, dim3(256), lds, s, atom_off, n_atoms, xyz, feat, centers, p0, G, grid, cpad, status); break;
+    case 1: hipLaunchKernelGGL(k_splat<1>, grd, dim3(256), lds, s, atom_off, n_atoms, xyz, feat, centers, p0, G, grid, cpad, status); break;
+    case 2: hipLaunchKernelGGL(k_splat<2>, grd, dim3(256), lds, s, atom_off, n_atoms, xyz, feat, centers, p0, G, grid, cpad, status); break;
+    case 3: hipLaunchKernelGGL(k_splat<3>, grd, dim3(256), lds, s, atom_off, n_atoms, xyz, feat, centers, p0, G, grid, cpad, status); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_repack(const void *src, int src_bf16, int n_vox, void *dst, int dst_bf16,
+                              int cpad, hipStream_t s) {
+  const int64_t total = (int64_t)n_vox * (cpad / 8);
+  const int blocks = (int)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+  hipLaunchKernelGGL(k_grid_repack, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, src, src_bf16,
+                     (int64_t)n_vox, dst, dst_bf16, cpad);
+  return hipGetLastError();
+}
+
+}  // namespace cf

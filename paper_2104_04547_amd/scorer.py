@@ -1,0 +1,107 @@
+"""Convenience wrapper over the C ABI: owns a context and allocates outputs with torch.
+
+All computation happens in libcf.so; this class only allocates output tensors on
+the current device and forwards pointers and the current HIP stream.
+"""
+from __future__ import annotations
+
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+from . import cfabi
+
+
+class Scorer:
+    def __init__(self, arch, params: Dict[str, np.ndarray], precision: str = "bf16", hbm_budget_bytes: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Scorer needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.arch = arch
+        self.precision = precision
+        prec = {"bf16": cfabi.CF_PREC_BF16, "fp32": cfabi.CF_PREC_FP32}[precision]
+        self.ctx = cfabi.cf_create(cfabi.pack_model(arch, params), prec, hbm_budget_bytes)
+        self.lc, self.H, self.n_params, _ = cfabi.cf_model_info(self.ctx)
+
+    # -- lifetime
+    def close(self):
+        if self.ctx:
+            cfabi.cf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def grid_dtype(self):
+        import torch
+        return torch.bfloat16 if self.precision == "bf16" else torch.float32
+
+    def _stream(self) -> int:
+        return cfabi.current_stream()
+
+    # -- entry points
+    def centers(self, db: "cfabi.DeviceBatch"):
+        import torch
+        out = torch.empty((db.n_poses, 3), dtype=torch.int32, device="cuda")
+        cfabi.cf_pose_centers(self.ctx, db.c, out.data_ptr(), self._stream())
+        return out
+
+    def voxelize(self, db, G: int):
+        import torch
+        out = torch.empty((db.n_poses, G, G, G, cfabi.CF_NCH), dtype=self.grid_dtype, device="cuda")
+        cfabi.cf_voxelize(self.ctx, db.c, G, out.data_ptr(), self._stream())
+        return out
+
+    def build_graphs(self, db, cov_capacity: Optional[int] = None, nc_capacity: Optional[int] = None):
+        import torch
+        n = db.n_atoms
+        cov_capacity = 16 * n if cov_capacity is None else cov_capacity
+        nc_capacity = 96 * n if nc_capacity is None else nc_capacity
+        t = dict(cov_row=torch.empty(n + 1, dtype=torch.int32, device="cuda"),
+                 cov_col=torch.empty(max(cov_capacity, 1), dtype=torch.int32, device="cuda"),
+                 nc_row=torch.empty(n + 1, dtype=torch.int32, device="cuda"),
+                 nc_col=torch.empty(max(nc_capacity, 1), dtype=torch.int32, device="cuda"))
+        cov = cfabi.cf_csr(t["cov_row"].data_ptr(), t["cov_col"].data_ptr(), cov_capacity)
+        nc = cfabi.cf_csr(t["nc_row"].data_ptr(), t["nc_col"].data_ptr(), nc_capacity)
+        cfabi.cf_build_graphs(self.ctx, db.c, cov, nc, self._stream())
+        t["cov"], t["nc"] = cov, nc
+        return t
+
+    def cnn3d(self, grid, G: int):
+        import torch
+        P = grid.shape[0]
+        out = torch.empty((P, self.lc), dtype=torch.float32, device="cuda")
+        cfabi.cf_cnn3d_fwd(self.ctx, grid.data_ptr(), P, G, out.data_ptr(), self._stream())
+        return out
+
+    def sgcnn(self, db, graphs):
+        import torch
+        out = torch.empty((db.n_poses, self.H), dtype=torch.float32, device="cuda")
+        cfabi.cf_sgcnn_fwd(self.ctx, db.c, graphs["cov"], graphs["nc"], out.data_ptr(), self._stream())
+        return out
+
+    def score(self, db, G: int, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(db.n_poses, dtype=torch.float32, device="cuda")
+        cfabi.cf_score_poses(self.ctx, db.c, G, out.data_ptr(), self._stream())
+        return out
+
+    def status(self) -> Tuple[int, int, int]:
+        return cfabi.cf_stream_status(self.ctx, self._stream())
+
+    def check(self):
+        rc, nc_, nn_ = self.status()
+        if rc != cfabi.CF_OK:
+            raise cfabi.CfError(rc, cfabi.cf_last_error() + f" (need cov={nc_}, nc={nn_})")
+
+    def autotune(self, G: int, n_poses: int):
+        cfabi.cf_autotune(self.ctx, G, n_poses, self._stream())
+        return cfabi.cf_conv_variants(self.ctx, G, len(self.arch.conv))
+
+    def variants(self, G: int):
+        return cfabi.cf_conv_variants(self.ctx, G, len(self.arch.conv))
