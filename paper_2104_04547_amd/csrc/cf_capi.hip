@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -255,7 +256,8 @@ std::vector<T> pack_conv(const std::vector<float> &W, int cout, int cin, int k, 
   const int CC = sizeof(T) == 2 ? 16 : 8;
   const int nchunks = cin_pad / CC;
   const int taps = k * k * k;
-  std::vector<T> out((size_t)taps * nchunks * cout_pad32 * CC, to_t<T>(0.0f));
+  // two extra zero taps: the conv kernel prefetches weights two taps ahead
+  std::vector<T> out((size_t)(taps + 2) * nchunks * cout_pad32 * CC, to_t<T>(0.0f));
   for (int tap = 0; tap < taps; ++tap)
     for (int ch = 0; ch < nchunks; ++ch)
       for (int n = 0; n < cout; ++n)
@@ -277,6 +279,27 @@ std::vector<float> transpose(const float *w, int rows, int cols) {  // [rows][co
 
 int upload_f(cf_ctx *c, float **dst, const float *src, size_t n) {
   return alloc_weight(c, reinterpret_cast<void **>(dst), n * sizeof(float), src);
+}
+
+// W [N][K] (row-major) -> split-bfloat16 MFMA B operands [K/16][N][16] (hi, lo)
+int upload_split(cf_ctx *c, const float *W, int N, int K, const bf16_t **hi, const bf16_t **lo) {
+  std::vector<bf16_t> h((size_t)N * K), l((size_t)N * K);
+  for (int ks = 0; ks < K / 16; ++ks)
+    for (int n = 0; n < N; ++n)
+      for (int e = 0; e < 16; ++e) {
+        const float w = W[(size_t)n * K + ks * 16 + e];
+        const bf16_t wh = (bf16_t)w;
+        const size_t o = ((size_t)ks * N + n) * 16 + e;
+        h[o] = wh;
+        l[o] = (bf16_t)(w - (float)wh);
+      }
+  void *ph, *pl;
+  int rc = alloc_weight(c, &ph, h.size() * sizeof(bf16_t), h.data());
+  if (rc) return rc;
+  if ((rc = alloc_weight(c, &pl, l.size() * sizeof(bf16_t), l.data()))) return rc;
+  *hi = reinterpret_cast<const bf16_t *>(ph);
+  *lo = reinterpret_cast<const bf16_t *>(pl);
+  return CF_OK;
 }
 
 int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
@@ -393,6 +416,7 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
       float *p;
       if ((rc = upload_f(c, &p, t.data(), t.size()))) return rc;
       S.msgT[r] = p;
+      if (c->bf16 && H >= 32 && (rc = upload_split(c, W, H, H, &S.msg_hi[r], &S.msg_lo[r]))) return rc;
     }
     const float *wih = R.take((size_t)3 * H * H), *whh = R.take((size_t)3 * H * H);
     const float *bih = R.take(3 * H), *bhh = R.take(3 * H);
@@ -407,6 +431,10 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     S.b_ih[stage] = p;
     if ((rc = upload_f(c, &p, bhh, 3 * H))) return rc;
     S.b_hh[stage] = p;
+    if (c->bf16 && H >= 32) {
+      if ((rc = upload_split(c, wih, 3 * H, H, &S.ih_hi[stage], &S.ih_lo[stage]))) return rc;
+      if ((rc = upload_split(c, whh, 3 * H, H, &S.hh_hi[stage], &S.hh_lo[stage]))) return rc;
+    }
   }
   {
     const float *gw = R.take((size_t)H * (H + CF_NCH)), *gb = R.take(H);
@@ -731,6 +759,8 @@ int cf_autotune(cf_ctx *c, int G, int32_t n_poses, void *stream) {
   CF_HIP(hipMemsetAsync(c->grid.p, 0x3c, c->grid.n, s));
   for (auto &b : c->act) CF_HIP(hipMemsetAsync(b.p, 0x3c, b.n, s));
   std::vector<int> best;
+  const char *ve = getenv("CF_AUTOTUNE_VERBOSE");
+  const bool verbose = ve && ve[0] && ve[0] != '0';
   hipEvent_t e0, e1;
   CF_HIP(hipEventCreate(&e0));
   CF_HIP(hipEventCreate(&e1));
@@ -751,6 +781,12 @@ int cf_autotune(cf_ctx *c, int G, int32_t n_poses, void *stream) {
       CF_HIP(hipEventSynchronize(e1));
       float ms = 0;
       CF_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (verbose) {
+        const double Do = conv_out_dim(D, L.k, L.stride);
+        const double tf = 2.0 * L.cin * L.cout * L.k * L.k * L.k * Do * Do * Do * np / (ms / 3.0 * 1e-3) / 1e12;
+        fprintf(stderr, "[cf_autotune] G=%d layer %zu variant %2d %-24s %8.3f ms %7.1f TFLOP/s\n", G, i, v,
+                cf::conv_variant_name(v), ms / 3.0, tf);
+      }
       if (ms < best_ms) {
         best_ms = ms;
         best_v = v;

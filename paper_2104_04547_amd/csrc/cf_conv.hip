@@ -99,45 +99,79 @@ __global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, cons
   constexpr int HY2 = S == 1 ? 0 : (C::HY + 1) / 2;
   constexpr int HX2 = S == 1 ? 0 : (C::HX + 1) / 2;
 
-  for (int chunk = 0; chunk < nchunks; ++chunk) {
-    __syncthreads();
-    // ---- stage the halo of this channel chunk: 32 bytes per voxel ----
-    constexpr int NV = C::HZ * C::HY * C::HX;
-    for (int v = threadIdx.x; v < NV; v += NW * 64) {
+  // ---- halo staging: 32 bytes per voxel; iteration `it` of a thread covers voxel
+  // it * threads + tid.  All of a thread's loads are issued before the first LDS
+  // store, so a chunk's staging costs about one memory latency, which the other
+  // workgroup on the CU covers with its MFMAs. ----
+  constexpr int NV = C::HZ * C::HY * C::HX;
+  constexpr int NTH = NW * 64;
+  constexpr int HITER = (NV + NTH - 1) / NTH;
+  auto halo_load = [&](int it, int ch, uint4 &lo, uint4 &hi) {
+    const int v = it * NTH + (int)threadIdx.x;
+    lo = make_uint4(0, 0, 0, 0);
+    hi = lo;
+    if (v < NV) {
       const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
       const int gz = oz + hz, gy = oy + hy, gx = ox + hx;
-      uint4 lo = make_uint4(0, 0, 0, 0), hi = make_uint4(0, 0, 0, 0);
       if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gx < (unsigned)D) {
-        const T *src = in + ((pose_in + ((int64_t)gz * D + gy) * D + gx) * cin_pad + chunk * CC);
+        const T *src = in + ((pose_in + ((int64_t)gz * D + gy) * D + gx) * cin_pad + ch * CC);
         lo = reinterpret_cast<const uint4 *>(src)[0];
         hi = reinterpret_cast<const uint4 *>(src)[1];
-        if (sizeof(T) == 4) {  // fp32: channels (0..7) -> (0,2,4,6 | 1,3,5,7)
-          const uint4 a = lo, b = hi;
-          lo = make_uint4(a.x, a.z, b.x, b.z);
-          hi = make_uint4(a.y, a.w, b.y, b.w);
-        }
+      }
+    }
+  };
+  auto halo_store = [&](int it, uint4 lo, uint4 hi) {
+    const int v = it * NTH + (int)threadIdx.x;
+    if (v < NV) {
+      const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
+      if (sizeof(T) == 4) {  // fp32: channels (0..7) -> (0,2,4,6 | 1,3,5,7)
+        const uint4 a = lo, b = hi;
+        lo = make_uint4(a.x, a.z, b.x, b.z);
+        hi = make_uint4(a.y, a.w, b.y, b.w);
       }
       const int off = stored_index(hz, C::HZ, S) * C::SLAB + stored_index(hy, C::HY, S) * C::ROW +
                       stored_index(hx, C::HX, S) * 32;
       *reinterpret_cast<uint4 *>(lds + off) = lo;
       *reinterpret_cast<uint4 *>(lds + off + 16) = hi;
     }
+  };
+  const int64_t tap_stride = (int64_t)nchunks * cout_pad32 * CC;
+  for (int chunk = 0; chunk < nchunks; ++chunk) {
+    if (chunk) __syncthreads();  // every wave is done reading the previous chunk's halo
+    {
+      uint4 hl[HITER], hh[HITER];
+#pragma unroll
+      for (int it = 0; it < HITER; ++it) halo_load(it, chunk, hl[it], hh[it]);
+#pragma unroll
+      for (int it = 0; it < HITER; ++it) halo_store(it, hl[it], hh[it]);
+    }
     __syncthreads();
-
-    const T *wchunk = wpk + ((int64_t)chunk * cout_pad32 + n0 + lrow) * CC + khalf * (CC / 2);
-    const int64_t tap_stride = (int64_t)nchunks * cout_pad32 * CC;
+    // Taps are consecutive in the packed weights, so the B fragments of tap t+1 and
+    // t+2 are in flight while tap t's MFMAs issue (the weight buffer carries two
+    // zero taps of padding for the prefetch past the last tap).
+    const T *wp = wpk + ((int64_t)chunk * cout_pad32 + n0 + lrow) * CC + khalf * (CC / 2);
+    uint4 b1[C::NB], b2[C::NB];
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb) {
+      b1[nb] = *reinterpret_cast<const uint4 *>(wp + nb * 32 * CC);
+      b2[nb] = *reinterpret_cast<const uint4 *>(wp + tap_stride + nb * 32 * CC);
+    }
+    wp += 2 * tap_stride;
     for (int dz = 0; dz < KS; ++dz) {
       const int offz = (S == 1 ? dz : (dz & 1) * HZ2 + (dz >> 1)) * C::SLAB;
       for (int dy = 0; dy < KS; ++dy) {
         const int offzy = offz + (S == 1 ? dy : (dy & 1) * HY2 + (dy >> 1)) * C::ROW;
-        const T *wrow = wchunk + (int64_t)((dz * KS + dy) * KS) * tap_stride;
 #pragma unroll
         for (int dx = 0; dx < KS; ++dx) {
           const int toff = offzy + (S == 1 ? dx : (dx & 1) * HX2 + (dx >> 1)) * 32;
-          const T *wt = wrow + (int64_t)dx * tap_stride;
           uint4 bfr[C::NB];
 #pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb) bfr[nb] = *reinterpret_cast<const uint4 *>(wt + nb * 32 * CC);
+          for (int nb = 0; nb < C::NB; ++nb) {
+            bfr[nb] = b1[nb];
+            b1[nb] = b2[nb];
+            b2[nb] = *reinterpret_cast<const uint4 *>(wp + nb * 32 * CC);
+          }
+          wp += tap_stride;
           uint4 afr[C::MB];
 #pragma unroll
           for (int mb = 0; mb < C::MB; ++mb) afr[mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + toff);
@@ -220,6 +254,10 @@ const Variant kVariants[] = {
     CF_VARIANT(7, 2, 2, 8, 8, 4, 64),   // 5
     CF_VARIANT(5, 1, 8, 8, 8, 4, 32),   // 6: tiny model
     CF_VARIANT(5, 1, 4, 8, 8, 4, 32),   // 7
+    CF_VARIANT(7, 1, 4, 8, 8, 2, 64),   // 8: 128 rows per wave, two workgroups per CU
+    CF_VARIANT(7, 2, 4, 4, 8, 2, 64),   // 9
+    CF_VARIANT(7, 2, 4, 4, 8, 2, 128),  // 10
+    CF_VARIANT(7, 2, 2, 8, 8, 2, 64),   // 11
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -237,7 +275,7 @@ bool conv_variant_ok(int v, const ConvLayer &L, int bf16) {
 
 int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
   (void)D_in;
-  const int pref[] = {0, 4, 3, 6, 1, 2, 5, 7};
+  const int pref[] = {1, 4, 3, 6, 0, 2, 5, 7, 8, 9, 10, 11};
   for (int v : pref)
     if (conv_variant_ok(v, L, bf16)) return v;
   return -1;

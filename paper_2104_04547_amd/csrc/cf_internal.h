@@ -90,6 +90,11 @@ struct SgWeights {
   const float *b_ih[2], *b_hh[2];   // per stage [3H]
   const float *gate_wT, *gate_b;    // [H+19][H], [H]
   const float *val_wT, *val_b;      // [H][H], [H]
+  // precision form (H >= 32): split-bfloat16 copies (hi = bf16(w), lo = bf16(w - hi))
+  // packed as MFMA B operands, [K/16][N][16] with element [ks][n][e] = W[n][16 ks + e]
+  const bf16_t *msg_hi[16], *msg_lo[16];  // N = H
+  const bf16_t *ih_hi[2], *ih_lo[2];      // N = 3H
+  const bf16_t *hh_hi[2], *hh_lo[2];      // N = 3H
 };
 // csr_global = 1: rows indexed by global atom id and columns are global ids (the
 // public neighbour-list layout); 0: both are relative to the first atom of pose p0.

@@ -8,14 +8,19 @@
 // over the ligand atoms ("gather") gives the latent that enters the fusion head.
 //
 // Design: one workgroup per pose (a pose's states, <= 4096 x H floats, stay in
-// L2 between rounds).  Atoms are processed in blocks of 32: the neighbour sums
-// are segmented CSR reductions (consecutive lanes = consecutive features, so a
-// neighbour row is one coalesced read), and the message and GRU products run out
-// of LDS with the weights staged once per round / stage, each thread owning one
-// output feature for several atoms (register blocking).  In the precision form
-// the GEMM operands (neighbour sums, messages, states and the message / GRU
-// weights) are rounded to bfloat16 and accumulated in float32; gates, state
-// update and readout stay float32.
+// L2 between rounds).  Atoms are processed in blocks: the neighbour sums are
+// segmented CSR reductions (consecutive lanes = consecutive features, so a
+// neighbour row is one coalesced read) staged in LDS, then the message and GRU
+// products run on the block.
+//   * plain form: float32 FMAs, weights staged in LDS, each thread owning one
+//     output feature for several atoms;
+//   * precision form (H = 32 or 64): the products run on the matrix cores as
+//     v_mfma_f32_32x32x16_bf16 with every float32 operand split into a bfloat16
+//     pair (hi + lo) and three products per term (hi*hi + hi*lo + lo*hi), float32
+//     accumulation.  Single bfloat16 operands move the scores of this model by
+//     ~0.1 pK; the split keeps ~16 mantissa bits.  Each wave owns a 32-atom x
+//     32-feature tile of all six GRU gate products, so the gates, the state
+//     update and the store happen straight from the accumulators.
 #include "cf_internal.h"
 
 namespace cf {
@@ -23,19 +28,95 @@ namespace cf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kBlk = 32;  // atoms per block
-
-template <bool BF>
-__device__ inline float rb(float x) {
-  if constexpr (BF)
-    return (float)(bf16_t)x;
-  else
-    return x;
-}
 
 __device__ inline float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
 
-template <int H, bool BF>
+// ---- shared pieces ------------------------------------------------------------
+
+// h = W_e x + b_e for the pose's atoms (float32)
+template <int H>
+__device__ inline void sg_embed(const SgWeights &W, const float *__restrict__ feat, int a0, int n, int64_t lb,
+                                float *h0) {
+  for (int e = threadIdx.x; e < n * H; e += kThreads) {
+    const int i = e / H, oo = e % H;
+    const float *x = feat + (int64_t)(a0 + i) * CF_NCH;
+    float v = W.embed_b[oo];
+    for (int c = 0; c < CF_NCH; ++c) v += W.embed_wT[c * H + oo] * x[c];
+    h0[(lb + i) * H + oo] = v;
+  }
+}
+
+// Neighbour sums of atoms [blk, blk+nblk) into A (row stride ld) and their current
+// states into Hc; rows past the pose are zero.
+template <int H>
+__device__ inline void sg_aggregate(const float *__restrict__ cur, const int32_t *__restrict__ rowp,
+                                    const int32_t *__restrict__ colp, int64_t cap, int csr_global, int a0, int base,
+                                    int64_t lb, int n, int blk, int nblk, int ld, float *A, float *Hc,
+                                    int64_t *status) {
+  for (int e = threadIdx.x; e < nblk * H; e += kThreads) {
+    const int a = e / H, oo = e % H;
+    const int i = blk + a;
+    float s = 0.0f, hc = 0.0f;
+    if (i < n) {
+      const int64_t ri = csr_global ? (int64_t)a0 + i : lb + i;
+      int64_t e0 = rowp[ri], e1 = rowp[ri + 1];
+      if (e1 > cap) e1 = cap;
+      if (e0 < 0) {
+        dev_fail(status, kDevBadGraph);
+        e0 = e1;
+      }
+      for (int64_t q = e0; q < e1; ++q) {
+        int64_t j = colp[q];
+        if (csr_global) j -= base;
+        if (j < lb || j >= lb + n) {
+          dev_fail(status, kDevBadGraph);
+          continue;
+        }
+        s += cur[j * H + oo];
+      }
+      hc = cur[(lb + i) * H + oo];
+    }
+    A[a * ld + oo] = s;
+    Hc[a * ld + oo] = hc;
+  }
+}
+
+// s = sum over ligand atoms of sigmoid(W_g [h; x] + b_g) * (W_v h + b_v), float32.
+// Wg, Wv: LDS copies of the transposed readout weights; red: >= kThreads floats.
+template <int H>
+__device__ inline void sg_readout(const SgWeights &W, const float *__restrict__ cur, const float *__restrict__ feat,
+                                  const uint8_t *__restrict__ is_lig, int a0, int n, int64_t lb, const float *Wg,
+                                  const float *Wv, float *red, float *out) {
+  constexpr int G = kThreads / H;
+  const int o = threadIdx.x % H, g = threadIdx.x / H;
+  float acc = 0.0f;
+  for (int i = g; i < n; i += G) {
+    if (!is_lig[a0 + i]) continue;
+    const float *hi = cur + (lb + i) * H;
+    const float *xi = feat + (int64_t)(a0 + i) * CF_NCH;
+    float gt = W.gate_b[o], vl = W.val_b[o];
+    for (int k = 0; k < H; ++k) {
+      const float hk = hi[k];
+      gt += Wg[k * H + o] * hk;
+      vl += Wv[k * H + o] * hk;
+    }
+    for (int c = 0; c < CF_NCH; ++c) gt += Wg[(H + c) * H + o] * xi[c];
+    acc += sigm(gt) * vl;
+  }
+  red[g * H + o] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < H) {
+    float s = 0.0f;
+    for (int q = 0; q < G; ++q) s += red[q * H + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// ---- plain form: float32 on the vector ALUs ----------------------------------
+
+constexpr int kBlk = 32;  // atoms per block (plain form)
+
+template <int H>
 struct SgShared {
   float Wt[H * H];
   float Wih[H * 3 * H];
@@ -45,21 +126,20 @@ struct SgShared {
   float Hc[kBlk * H];
 };
 
-template <int H, bool BF>
-__global__ __launch_bounds__(kThreads) void k_sgcnn(SgWeights W, const int32_t *__restrict__ atom_off, int n_atoms,
-                                                    const float *__restrict__ feat,
-                                                    const uint8_t *__restrict__ is_lig, int p0,
-                                                    const int32_t *__restrict__ cov_row,
-                                                    const int32_t *__restrict__ cov_col, int64_t cov_cap,
-                                                    const int32_t *__restrict__ nc_row,
-                                                    const int32_t *__restrict__ nc_col, int64_t nc_cap,
-                                                    int csr_global, float *__restrict__ hbuf,
-                                                    int64_t hcap, float *__restrict__ sg_latent,
-                                                    int64_t *__restrict__ status) {
+template <int H>
+__global__ __launch_bounds__(kThreads) void k_sgcnn_f32(SgWeights W, const int32_t *__restrict__ atom_off,
+                                                        int n_atoms, const float *__restrict__ feat,
+                                                        const uint8_t *__restrict__ is_lig, int p0,
+                                                        const int32_t *__restrict__ cov_row,
+                                                        const int32_t *__restrict__ cov_col, int64_t cov_cap,
+                                                        const int32_t *__restrict__ nc_row,
+                                                        const int32_t *__restrict__ nc_col, int64_t nc_cap,
+                                                        int csr_global, float *__restrict__ hbuf, int64_t hcap,
+                                                        float *__restrict__ sg_latent, int64_t *__restrict__ status) {
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
-  SgShared<H, BF> &S = *reinterpret_cast<SgShared<H, BF> *>(smem_raw);
-  constexpr int G = kThreads / H;     // thread groups (one output feature per thread)
-  constexpr int APT = kBlk / G;       // atoms per thread in a block
+  SgShared<H> &S = *reinterpret_cast<SgShared<H> *>(smem_raw);
+  constexpr int G = kThreads / H;  // thread groups (one output feature per thread)
+  constexpr int APT = kBlk / G;    // atoms per thread in a block
   const int t = threadIdx.x;
   const int o = t % H, g = t / H;
   const int pl = blockIdx.x;
@@ -74,15 +154,7 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn(SgWeights W, const int32_t *
     return;
   }
   float *h0 = hbuf, *h1 = hbuf + hcap * H;
-
-  // ---- embedding h = W_e x + b_e (float32) ----
-  for (int e = t; e < n * H; e += kThreads) {
-    const int i = e / H, oo = e % H;
-    const float *x = feat + (int64_t)(a0 + i) * CF_NCH;
-    float v = W.embed_b[oo];
-    for (int c = 0; c < CF_NCH; ++c) v += W.embed_wT[c * H + oo] * x[c];
-    h0[(lb + i) * H + oo] = v;
-  }
+  sg_embed<H>(W, feat, a0, n, lb, h0);
   __threadfence();
   __syncthreads();
 
@@ -93,45 +165,19 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn(SgWeights W, const int32_t *
     const int32_t *rowp = stage ? nc_row : cov_row;
     const int32_t *colp = stage ? nc_col : cov_col;
     const int64_t cap = stage ? nc_cap : cov_cap;
-    for (int e = t; e < H * H; e += kThreads) S.Wt[e] = rb<BF>(W.msgT[r][e]);
+    for (int e = t; e < H * H; e += kThreads) S.Wt[e] = W.msgT[r][e];
     if (r == 0 || r == W.K_c) {
       for (int e = t; e < 3 * H * H; e += kThreads) {
-        S.Wih[e] = rb<BF>(W.w_ihT[stage][e]);
-        S.Whh[e] = rb<BF>(W.w_hhT[stage][e]);
+        S.Wih[e] = W.w_ihT[stage][e];
+        S.Whh[e] = W.w_hhT[stage][e];
       }
     }
     const float *bih = W.b_ih[stage], *bhh = W.b_hh[stage];
     __syncthreads();
     for (int blk = 0; blk < n; blk += kBlk) {
-      // phase A: neighbour sums and the block's current states
-      for (int e = t; e < kBlk * H; e += kThreads) {
-        const int a = e / H, oo = e % H;
-        const int i = blk + a;
-        float s = 0.0f, hc = 0.0f;
-        if (i < n) {
-          const int64_t ri = csr_global ? (int64_t)a0 + i : lb + i;
-          int64_t e0 = rowp[ri], e1 = rowp[ri + 1];
-          if (e1 > cap) e1 = cap;
-          if (e0 < 0) {
-            dev_fail(status, kDevBadGraph);
-            e0 = e1;
-          }
-          for (int64_t q = e0; q < e1; ++q) {
-            int64_t j = colp[q];
-            if (csr_global) j -= base;
-            if (j < lb || j >= lb + n) {
-              dev_fail(status, kDevBadGraph);
-              continue;
-            }
-            s += cur[j * H + oo];
-          }
-          hc = cur[(lb + i) * H + oo];
-        }
-        S.A[a * H + oo] = rb<BF>(s);
-        S.Hc[a * H + oo] = hc;
-      }
+      sg_aggregate<H>(cur, rowp, colp, cap, csr_global, a0, base, lb, n, blk, kBlk, H, S.A, S.Hc, status);
       __syncthreads();
-      // phase B: messages m = W_t a
+      // messages m = W_t a
       {
         float acc[APT];
 #pragma unroll
@@ -142,10 +188,10 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn(SgWeights W, const int32_t *
           for (int u = 0; u < APT; ++u) acc[u] += w * S.A[(g * APT + u) * H + k];
         }
 #pragma unroll
-        for (int u = 0; u < APT; ++u) S.M[(g * APT + u) * H + o] = rb<BF>(acc[u]);
+        for (int u = 0; u < APT; ++u) S.M[(g * APT + u) * H + o] = acc[u];
       }
       __syncthreads();
-      // phase C: GRU update
+      // GRU update
       {
         float ir[APT], iz[APT], in_[APT], hr[APT], hz[APT], hn[APT];
 #pragma unroll
@@ -163,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn(SgWeights W, const int32_t *
 #pragma unroll
           for (int u = 0; u < APT; ++u) {
             const float m = S.M[(g * APT + u) * H + k];
-            const float hk = rb<BF>(S.Hc[(g * APT + u) * H + k]);
+            const float hk = S.Hc[(g * APT + u) * H + k];
             ir[u] += wir * m;
             iz[u] += wiz * m;
             in_[u] += win * m;
@@ -180,8 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn(SgWeights W, const int32_t *
             const float rr = sigm(ir[u] + hr[u]);
             const float zz = sigm(iz[u] + hz[u]);
             const float nn = tanhf(in_[u] + rr * hn[u]);
-            const float hold = S.Hc[a * H + o];
-            nxt[(lb + i) * H + o] = (1.0f - zz) * nn + zz * hold;
+            nxt[(lb + i) * H + o] = (1.0f - zz) * nn + zz * S.Hc[a * H + o];
           }
         }
       }
@@ -193,49 +238,195 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn(SgWeights W, const int32_t *
     cur = nxt;
     nxt = tmp;
   }
-
-  // ---- gated readout over ligand atoms (float32) ----
+  // readout (weights staged in the GRU areas)
   for (int e = t; e < (H + CF_NCH) * H; e += kThreads) S.Wih[e] = W.gate_wT[e];
   for (int e = t; e < H * H; e += kThreads) S.Whh[e] = W.val_wT[e];
   __syncthreads();
-  float acc = 0.0f;
-  for (int i = g; i < n; i += G) {
-    if (!is_lig[a0 + i]) continue;
-    const float *hi = cur + (lb + i) * H;
-    const float *xi = feat + (int64_t)(a0 + i) * CF_NCH;
-    float gt = W.gate_b[o], vl = W.val_b[o];
-    for (int k = 0; k < H; ++k) {
-      const float hk = hi[k];
-      gt += S.Wih[k * H + o] * hk;
-      vl += S.Whh[k * H + o] * hk;
-    }
-    for (int c = 0; c < CF_NCH; ++c) gt += S.Wih[(H + c) * H + o] * xi[c];
-    acc += sigm(gt) * vl;
-  }
-  S.A[g * H + o] = acc;
-  __syncthreads();
-  if (t < H) {
-    float s = 0.0f;
-    for (int q = 0; q < G; ++q) s += S.A[q * H + t];
-    sg_latent[(int64_t)pl * H + t] = s;
+  sg_readout<H>(W, cur, feat, is_lig, a0, n, lb, S.Wih, S.Whh, S.A, sg_latent + (int64_t)pl * H);
+}
+
+// ---- precision form: split-bfloat16 MFMA --------------------------------------
+
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+
+// hi/lo bfloat16 split of 8 consecutive floats
+__device__ inline void split8(const float *p, bf16x8 &hi, bf16x8 &lo) {
+  const float4 a = *reinterpret_cast<const float4 *>(p);
+  const float4 b = *reinterpret_cast<const float4 *>(p + 4);
+  const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const bf16_t h = (bf16_t)v[q];
+    hi[q] = h;
+    lo[q] = (bf16_t)(v[q] - (float)h);
   }
 }
 
-template <int H, bool BF>
-hipError_t launch_h(const SgWeights &W, const int32_t *atom_off, int n_atoms, const float *feat, const uint8_t *is_lig,
-                    int p0, int n_poses, const int32_t *cov_row, const int32_t *cov_col, int64_t cov_cap,
-                    const int32_t *nc_row, const int32_t *nc_col, int64_t nc_cap, int csr_global, float *hbuf,
-                    int64_t hcap, float *sg_latent, int64_t *status, hipStream_t s) {
+__device__ inline f32x16v mfma3(const bf16x8 &ah, const bf16x8 &al, const bf16x8 &bh, const bf16x8 &bl, f32x16v c) {
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
+  return c;
+}
+
+template <int H>
+struct SgMfmaShared {
+  static constexpr int LD = H + 4;      // padded row stride (floats)
+  static constexpr int FB = H / 32;     // 32-feature blocks
+  static constexpr int MBK = 4 / FB;    // 32-atom blocks per workgroup block
+  static constexpr int BLK = 32 * MBK;  // atoms per block
+  float A[BLK * LD];
+  float M[BLK * LD];
+  float Hc[BLK * LD];
+  float Wg[(H + CF_NCH) * H];
+  float Wv[H * H];
+};
+
+template <int H>
+__global__ __launch_bounds__(kThreads) void k_sgcnn_mfma(SgWeights W, const int32_t *__restrict__ atom_off,
+                                                         int n_atoms, const float *__restrict__ feat,
+                                                         const uint8_t *__restrict__ is_lig, int p0,
+                                                         const int32_t *__restrict__ cov_row,
+                                                         const int32_t *__restrict__ cov_col, int64_t cov_cap,
+                                                         const int32_t *__restrict__ nc_row,
+                                                         const int32_t *__restrict__ nc_col, int64_t nc_cap,
+                                                         int csr_global, float *__restrict__ hbuf, int64_t hcap,
+                                                         float *__restrict__ sg_latent, int64_t *__restrict__ status) {
+  using SS = SgMfmaShared<H>;
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+  SS &S = *reinterpret_cast<SS *>(smem_raw);
+  constexpr int LD = SS::LD, BLK = SS::BLK;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int mb = wave / SS::FB, fb = wave % SS::FB;  // this wave's 32-atom x 32-feature tile
+  const int lrow = lane & 31, khalf = lane >> 5;
+  const int pl = blockIdx.x;
+  const int base = atom_off[p0];
+  int a0, a1;
+  const bool ok = pose_range(atom_off, p0 + pl, n_atoms, a0, a1);
+  const int n = a1 - a0;
+  const int64_t lb = (int64_t)a0 - base;
+  if (!ok || n <= 0 || lb < 0 || lb + n > hcap) {
+    if (t == 0 && (!ok || lb < 0 || lb + n > hcap)) dev_fail(status, kDevBadOffsets);
+    if (t < H) sg_latent[(int64_t)pl * H + t] = 0.0f;
+    return;
+  }
+  float *h0 = hbuf, *h1 = hbuf + hcap * H;
+  sg_embed<H>(W, feat, a0, n, lb, h0);
+  __threadfence();
+  __syncthreads();
+
+  const int ocol = fb * 32 + lrow;  // output feature of this lane's accumulator column
+  float *cur = h0, *nxt = h1;
+  const int rounds = W.K_c + W.K_n;
+  for (int r = 0; r < rounds; ++r) {
+    const int stage = r < W.K_c ? 0 : 1;
+    const int32_t *rowp = stage ? nc_row : cov_row;
+    const int32_t *colp = stage ? nc_col : cov_col;
+    const int64_t cap = stage ? nc_cap : cov_cap;
+    const bf16_t *mh = W.msg_hi[r], *ml = W.msg_lo[r];
+    const bf16_t *ih = W.ih_hi[stage], *il = W.ih_lo[stage], *hh = W.hh_hi[stage], *hl = W.hh_lo[stage];
+    const float *bih = W.b_ih[stage], *bhh = W.b_hh[stage];
+    const float bir = bih[ocol], biz = bih[H + ocol], bin = bih[2 * H + ocol];
+    const float bhr = bhh[ocol], bhz = bhh[H + ocol], bhn = bhh[2 * H + ocol];
+    for (int blk = 0; blk < n; blk += BLK) {
+      sg_aggregate<H>(cur, rowp, colp, cap, csr_global, a0, base, lb, n, blk, BLK, LD, S.A, S.Hc, status);
+      __syncthreads();
+      // messages: M[atoms, ocol] = sum_k A[atoms, k] W_t[ocol, k]
+      {
+        f32x16v acc = {};
+#pragma unroll
+        for (int ks = 0; ks < H / 16; ++ks) {
+          bf16x8 ah, al;
+          split8(&S.A[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], ah, al);
+          const int64_t wo = ((int64_t)ks * H + ocol) * 16 + khalf * 8;
+          const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(mh + wo);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(ml + wo);
+          acc = mfma3(ah, al, bh, bl, acc);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int row = mb * 32 + 8 * (j >> 2) + 4 * khalf + (j & 3);
+          S.M[row * LD + ocol] = acc[j];
+        }
+      }
+      __syncthreads();
+      // GRU gates for this wave's tile, all six products from the same operands
+      {
+        f32x16v gir = {}, giz = {}, gin = {}, ghr = {}, ghz = {}, ghn = {};
+#pragma unroll
+        for (int ks = 0; ks < H / 16; ++ks) {
+          bf16x8 mhi, mlo, hhi, hlo;
+          split8(&S.M[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], mhi, mlo);
+          split8(&S.Hc[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], hhi, hlo);
+          const int64_t w0 = ((int64_t)ks * 3 * H + ocol) * 16 + khalf * 8;
+          const int64_t gs = (int64_t)H * 16;  // next gate's rows
+          gir = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0), *reinterpret_cast<const bf16x8 *>(il + w0), gir);
+          giz = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0 + gs), *reinterpret_cast<const bf16x8 *>(il + w0 + gs), giz);
+          gin = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0 + 2 * gs), *reinterpret_cast<const bf16x8 *>(il + w0 + 2 * gs), gin);
+          ghr = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0), *reinterpret_cast<const bf16x8 *>(hl + w0), ghr);
+          ghz = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0 + gs), *reinterpret_cast<const bf16x8 *>(hl + w0 + gs), ghz);
+          ghn = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0 + 2 * gs), *reinterpret_cast<const bf16x8 *>(hl + w0 + 2 * gs), ghn);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int row = mb * 32 + 8 * (j >> 2) + 4 * khalf + (j & 3);
+          const int i = blk + row;
+          if (i < n) {
+            const float rr = sigm(gir[j] + bir + ghr[j] + bhr);
+            const float zz = sigm(giz[j] + biz + ghz[j] + bhz);
+            const float nn = tanhf(gin[j] + bin + rr * (ghn[j] + bhn));
+            nxt[(lb + i) * H + ocol] = (1.0f - zz) * nn + zz * S.Hc[row * LD + ocol];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    __threadfence();
+    __syncthreads();
+    float *tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  for (int e = t; e < (H + CF_NCH) * H; e += kThreads) S.Wg[e] = W.gate_wT[e];
+  for (int e = t; e < H * H; e += kThreads) S.Wv[e] = W.val_wT[e];
+  __syncthreads();
+  sg_readout<H>(W, cur, feat, is_lig, a0, n, lb, S.Wg, S.Wv, S.A, sg_latent + (int64_t)pl * H);
+}
+
+template <typename K>
+void set_lds_attr(K kernel, size_t lds) {
+  hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int H>
+hipError_t launch_h(const SgWeights &W, int mfma, const int32_t *atom_off, int n_atoms, const float *feat,
+                    const uint8_t *is_lig, int p0, int n_poses, const int32_t *cov_row, const int32_t *cov_col,
+                    int64_t cov_cap, const int32_t *nc_row, const int32_t *nc_col, int64_t nc_cap, int csr_global,
+                    float *hbuf, int64_t hcap, float *sg_latent, int64_t *status, hipStream_t s) {
   static_assert((H + CF_NCH) * H <= 3 * H * H, "readout weights must fit the staging area");
-  const size_t lds = sizeof(SgShared<H, BF>);
+  if constexpr (H >= 32) {
+    if (mfma) {
+      const size_t lds = sizeof(SgMfmaShared<H>);
+      static bool attr = false;
+      if (!attr) {
+        set_lds_attr(&k_sgcnn_mfma<H>, lds);
+        attr = true;
+      }
+      hipLaunchKernelGGL((k_sgcnn_mfma<H>), dim3(n_poses), dim3(kThreads), lds, s, W, atom_off, n_atoms, feat,
+                         is_lig, p0, cov_row, cov_col, cov_cap, nc_row, nc_col, nc_cap, csr_global, hbuf, hcap,
+                         sg_latent, status);
+      return hipGetLastError();
+    }
+  }
+  const size_t lds = sizeof(SgShared<H>);
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sgcnn<H, BF>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
+    set_lds_attr(&k_sgcnn_f32<H>, lds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_sgcnn<H, BF>), dim3(n_poses), dim3(kThreads), lds, s, W, atom_off, n_atoms, feat, is_lig, p0,
-                     cov_row, cov_col, cov_cap, nc_row, nc_col, nc_cap, csr_global, hbuf, hcap, sg_latent,
+  hipLaunchKernelGGL((k_sgcnn_f32<H>), dim3(n_poses), dim3(kThreads), lds, s, W, atom_off, n_atoms, feat, is_lig,
+                     p0, cov_row, cov_col, cov_cap, nc_row, nc_col, nc_cap, csr_global, hbuf, hcap, sg_latent,
                      status);
   return hipGetLastError();
 }
@@ -248,17 +439,12 @@ hipError_t launch_sgcnn(const SgWeights &W, int bf16, const int32_t *atom_off, i
                         const int32_t *nc_col, int64_t nc_cap, int csr_global, float *hbuf,
                         int64_t hcap_atoms, float *sg_latent, int64_t *status, hipStream_t s) {
   if (n_poses <= 0) return hipSuccess;
-  // The precision form keeps float32 operands here until the split-bfloat16
-  // matrix-core path lands: single bfloat16 operands move scores by ~0.1 pK.
-  bf16 = 0;
-#define CF_SG(HH)                                                                                            \
-  if (W.H == HH)                                                                                             \
-    return bf16 ? launch_h<HH, true>(W, atom_off, n_atoms, feat, is_lig, p0, n_poses, cov_row, cov_col, cov_cap,      \
-                                     nc_row, nc_col, nc_cap, csr_global, hbuf, hcap_atoms, sg_latent,        \
-                                     status, s)                                                              \
-                : launch_h<HH, false>(W, atom_off, n_atoms, feat, is_lig, p0, n_poses, cov_row, cov_col, cov_cap,     \
-                                      nc_row, nc_col, nc_cap, csr_global, hbuf, hcap_atoms, sg_latent,       \
-                                      status, s);
+  // the matrix-core path needs the split-bfloat16 weight copies (precision form, H >= 32)
+  const int mfma = bf16 && W.msg_hi[0] != nullptr;
+#define CF_SG(HH)                                                                                              \
+  if (W.H == HH)                                                                                               \
+    return launch_h<HH>(W, mfma, atom_off, n_atoms, feat, is_lig, p0, n_poses, cov_row, cov_col, cov_cap,      \
+                        nc_row, nc_col, nc_cap, csr_global, hbuf, hcap_atoms, sg_latent, status, s);
   CF_SG(16)
   CF_SG(32)
   CF_SG(64)
