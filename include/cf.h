@@ -208,6 +208,43 @@ typedef struct {
 int cf_timing_enable(cf_ctx *ctx, int enable);
 int cf_timing_read(cf_ctx *ctx, cf_kernel_stat *out, int32_t max_entries, int32_t *n_out);
 
+/* ---- Serving engine (continuous batching) ------------------------------------
+ * The request-driven form of the paper's per-GPU scoring loop (Sec. 4.2): each
+ * request carries one or more poses (host arrays, copied before submit returns)
+ * and its own grid size.  A scheduler thread owns n_slots device slots (a stream,
+ * a scoring context with resident weights and scratch, pinned staging); whenever
+ * a slot is free it packs queued requests of one grid size, in arrival order,
+ * into one batch of up to slot_poses poses / slot_atoms atoms, pads it with empty
+ * poses to a power-of-two bucket and replays the hipGraph captured for that
+ * (grid size, bucket) -- so requests that arrive while others run are admitted as
+ * slots free up, and batches on different slots overlap on the device.  A pose's
+ * score is bitwise the same whatever batch it lands in.  Slots whose scratch
+ * would exceed hbm_budget_bytes fail creation (CF_ERR_OOM); queued work waits for
+ * a free slot and is never rejected for lack of memory. */
+typedef struct cf_engine cf_engine;
+typedef struct {
+  int32_t n_slots;          /* 1..8 concurrent batches */
+  int32_t slot_poses;       /* poses per batch, 1..512 */
+  int64_t slot_atoms;       /* atoms per batch */
+  int64_t hbm_budget_bytes; /* for all slots together; 0 = 32 GiB */
+  int32_t use_graphs;       /* 1: capture and replay hipGraphs per (G, bucket) */
+  int32_t reserved;
+} cf_engine_config;
+int cf_engine_create(const void *host_model_blob, size_t nbytes, int precision, const cf_engine_config *cfg,
+                     cf_engine **out);
+/* Host pointers: atom_off [n_poses+1] (atom_off[0] = 0), xyz [N][3], feat [N][19],
+ * is_lig [N]; G a multiple of 4 in 8..96.  Returns a ticket for cf_engine_poll. */
+int cf_engine_submit(cf_engine *e, int32_t n_poses, const int32_t *atom_off, const int32_t *xyz, const float *feat,
+                     const uint8_t *is_lig, int32_t G, uint64_t *ticket);
+/* *done = 1 once scored: scores_out (host [n_poses]) and *latency_ms (submit to
+ * scores on the host) are filled, the ticket is released and the request's
+ * status (device-side checks included) is returned. */
+int cf_engine_poll(cf_engine *e, uint64_t ticket, float *scores_out, int32_t *done, double *latency_ms);
+int cf_engine_wait_all(cf_engine *e);
+int cf_engine_info(cf_engine *e, int64_t *poses_done, int64_t *batches, int64_t *graph_replays, int64_t *queued);
+const char *cf_engine_last_error(cf_engine *e);
+void cf_engine_destroy(cf_engine *e);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["cf_splat.hip", "cf_graph.hip", "cf_conv.hip", "cf_head.hip", "cf_sgcnn.hip", "cf_capi.hip"]
+SOURCES = ["cf_splat.hip", "cf_graph.hip", "cf_conv.hip", "cf_head.hip", "cf_sgcnn.hip", "cf_capi.hip",
+           "cf_engine.hip"]
 HEADERS = ["cf_internal.h"]
 
 FLAGS = [

@@ -26,7 +26,9 @@ CF_MODEL_MAGIC = 0x314D4643
 
 EXPORTS = ["cf_create", "cf_destroy", "cf_pose_centers", "cf_voxelize", "cf_build_graphs", "cf_cnn3d_fwd",
            "cf_sgcnn_fwd", "cf_score_poses", "cf_stream_status", "cf_last_error", "cf_model_info",
-           "cf_autotune", "cf_conv_variants", "cf_timing_enable", "cf_timing_read"]
+           "cf_autotune", "cf_conv_variants", "cf_timing_enable", "cf_timing_read",
+           "cf_engine_create", "cf_engine_submit", "cf_engine_poll", "cf_engine_wait_all", "cf_engine_info",
+           "cf_engine_last_error", "cf_engine_destroy"]
 
 
 class CfError(RuntimeError):
@@ -55,6 +57,11 @@ class cf_model_desc(ctypes.Structure):
 class cf_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double),
                 ("flop", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class cf_engine_config(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("slot_poses", ctypes.c_int32), ("slot_atoms", ctypes.c_int64),
+                ("hbm_budget_bytes", ctypes.c_int64), ("use_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -88,6 +95,16 @@ def load(path: str = LIB_PATH):
         "cf_conv_variants": ([vp, ctypes.c_int, ctypes.POINTER(i32), i32], ctypes.c_int),
         "cf_timing_enable": ([vp, ctypes.c_int], ctypes.c_int),
         "cf_timing_read": ([vp, ctypes.POINTER(cf_kernel_stat), i32, ctypes.POINTER(i32)], ctypes.c_int),
+        "cf_engine_create": ([vp, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(cf_engine_config),
+                              ctypes.POINTER(vp)], ctypes.c_int),
+        "cf_engine_submit": ([vp, i32, vp, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "cf_engine_poll": ([vp, ctypes.c_uint64, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
+                           ctypes.c_int),
+        "cf_engine_wait_all": ([vp], ctypes.c_int),
+        "cf_engine_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+                           ctypes.c_int),
+        "cf_engine_last_error": ([vp], ctypes.c_char_p),
+        "cf_engine_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -227,6 +244,55 @@ def cf_timing_read(ctx):
     _check(load().cf_timing_read(ctx, arr, 64, ctypes.byref(n)))
     return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms, flop=arr[i].flop,
                                        bytes=arr[i].bytes) for i in range(min(n.value, 64))}
+
+
+def cf_engine_create(blob: bytes, precision: int, n_slots: int = 4, slot_poses: int = 512,
+                     slot_atoms: int = 512 * 1600, hbm_budget_bytes: int = 0, use_graphs: bool = True) -> int:
+    cfg = cf_engine_config(n_slots, slot_poses, slot_atoms, hbm_budget_bytes, int(use_graphs), 0)
+    out = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(load().cf_engine_create(ctypes.cast(buf, ctypes.c_void_p), len(blob), precision, ctypes.byref(cfg),
+                                   ctypes.byref(out)))
+    return out.value
+
+
+def cf_engine_submit(eng, atom_off, xyz, feat, is_lig, G: int) -> int:
+    """Host numpy arrays (copied by the engine before this returns)."""
+    t = ctypes.c_uint64(0)
+    atom_off = np.ascontiguousarray(atom_off, dtype=np.int32)
+    xyz = np.ascontiguousarray(xyz, dtype=np.int32)
+    feat = np.ascontiguousarray(feat, dtype=np.float32)
+    is_lig = np.ascontiguousarray(is_lig, dtype=np.uint8)
+    rc = load().cf_engine_submit(eng, len(atom_off) - 1, atom_off.ctypes.data, xyz.ctypes.data, feat.ctypes.data,
+                                 is_lig.ctypes.data, G, ctypes.byref(t))
+    if rc != CF_OK:
+        raise CfError(rc, load().cf_engine_last_error(eng).decode(errors="replace"))
+    return t.value
+
+
+def cf_engine_poll(eng, ticket: int, n_poses: int):
+    """(done, scores or None, latency_ms or None); raises if the request failed."""
+    out = np.empty(n_poses, dtype=np.float32)
+    done = ctypes.c_int32(0)
+    lat = ctypes.c_double(0.0)
+    rc = load().cf_engine_poll(eng, ticket, out.ctypes.data, ctypes.byref(done), ctypes.byref(lat))
+    if rc != CF_OK:
+        raise CfError(rc, load().cf_engine_last_error(eng).decode(errors="replace"))
+    return (True, out, lat.value) if done.value else (False, None, None)
+
+
+def cf_engine_wait_all(eng):
+    _check(load().cf_engine_wait_all(eng))
+
+
+def cf_engine_info(eng):
+    a, b, c, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().cf_engine_info(eng, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+    return dict(poses_done=a.value, batches=b.value, graph_replays=c.value, queued_poses=d.value)
+
+
+def cf_engine_destroy(eng):
+    load().cf_engine_destroy(eng)
 
 
 # ------------------------------------------------------------------ torch helpers

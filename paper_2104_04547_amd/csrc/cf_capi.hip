@@ -367,11 +367,14 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     int rc;
     if (c->bf16) {
       auto pk = pack_conv<bf16_t>(Wf, co, ci, k, cin_pad, L.cout_pad32);
+      L.wbytes = (int64_t)(pk.size() * sizeof(bf16_t));
       rc = alloc_weight(c, &L.wpk, pk.size() * sizeof(bf16_t), pk.data());
     } else {
       auto pk = pack_conv<float>(Wf, co, ci, k, cin_pad, L.cout_pad32);
+      L.wbytes = (int64_t)(pk.size() * sizeof(float));
       rc = alloc_weight(c, &L.wpk, pk.size() * sizeof(float), pk.data());
     }
+    if (L.wbytes >= ((int64_t)1 << 31)) return fail(CF_ERR_UNSUPPORTED, "conv layer weights exceed 2 GiB");
     if (rc) return rc;
     if ((rc = upload_f(c, &L.bias, bf.data(), bf.size()))) return rc;
     c->conv.push_back(L);

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, cons
                                                    const float *__restrict__ bias,
                                                    const T *__restrict__ res, T *__restrict__ out, int D,
                                                    int Do, int cin_pad, int cout_pad32, int cout,
-                                                   int cout_store, int nty, int ntx) {
+                                                   int cout_store, int nty, int ntx, int wbytes) {
   using C = ConvCfg<T, KS, S, TZ, TY, TX, NW, NT>;
   constexpr int CC = C::CC;
   __shared__ __attribute__((aligned(16))) char lds[C::LDS];
@@ -135,7 +135,9 @@ __global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, cons
       *reinterpret_cast<uint4 *>(lds + off + 16) = hi;
     }
   };
-  const int64_t tap_stride = (int64_t)nchunks * cout_pad32 * CC;
+  const int tap_bytes = nchunks * cout_pad32 * CC * (int)sizeof(T);
+  const __amdgpu_buffer_rsrc_t wrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(wpk), (short)0, wbytes, 0x00020000);
   for (int chunk = 0; chunk < nchunks; ++chunk) {
     if (chunk) __syncthreads();  // every wave is done reading the previous chunk's halo
     {
@@ -147,16 +149,20 @@ __global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, cons
     }
     __syncthreads();
     // Taps are consecutive in the packed weights, so the B fragments of tap t+1 and
-    // t+2 are in flight while tap t's MFMAs issue (the weight buffer carries two
-    // zero taps of padding for the prefetch past the last tap).
-    const T *wp = wpk + ((int64_t)chunk * cout_pad32 + n0 + lrow) * CC + khalf * (CC / 2);
+    // t+2 are in flight while tap t's MFMAs issue.  They are buffer loads with the
+    // tap offset in a scalar register (no per-tap address arithmetic); reads past
+    // the buffer return zero.
+    int vb[C::NB];
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb)
+      vb[nb] = (((chunk * cout_pad32 + n0 + nb * 32 + lrow) * CC) + khalf * (CC / 2)) * (int)sizeof(T);
     uint4 b1[C::NB], b2[C::NB];
 #pragma unroll
     for (int nb = 0; nb < C::NB; ++nb) {
-      b1[nb] = *reinterpret_cast<const uint4 *>(wp + nb * 32 * CC);
-      b2[nb] = *reinterpret_cast<const uint4 *>(wp + tap_stride + nb * 32 * CC);
+      b1[nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], 0, 0));
+      b2[nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], tap_bytes, 0));
     }
-    wp += 2 * tap_stride;
+    int soff = 2 * tap_bytes;
     for (int dz = 0; dz < KS; ++dz) {
       const int offz = (S == 1 ? dz : (dz & 1) * HZ2 + (dz >> 1)) * C::SLAB;
       for (int dy = 0; dy < KS; ++dy) {
@@ -169,9 +175,9 @@ __global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, cons
           for (int nb = 0; nb < C::NB; ++nb) {
             bfr[nb] = b1[nb];
             b1[nb] = b2[nb];
-            b2[nb] = *reinterpret_cast<const uint4 *>(wp + nb * 32 * CC);
+            b2[nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], soff, 0));
           }
-          wp += tap_stride;
+          soff += tap_bytes;
           uint4 afr[C::MB];
 #pragma unroll
           for (int mb = 0; mb < C::MB; ++mb) afr[mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + toff);
@@ -198,22 +204,66 @@ __global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, cons
 
   // ---- epilogue: bias, residual, ReLU, store ----
   const int64_t pose_out = (int64_t)pose * Do * Do * Do;
+  auto row_base = [&](int m, bool &valid) -> int64_t {
+    const int z = tz0 + m / (TY * TX), y = ty0 + (m / TX) % TY, x = tx0 + m % TX;
+    valid = z < Do && y < Do && x < Do;
+    return (pose_out + ((int64_t)z * Do + y) * Do + x) * cout_store;
+  };
+  if constexpr (sizeof(T) == 2 && C::MT * NT * 2 <= C::LDS) {
+    // bf16: the output tile goes through LDS so that residual reads and output
+    // writes are 16-byte row segments instead of 2-byte scatters.
+    bf16_t *ot = reinterpret_cast<bf16_t *>(lds);  // [MT][NT]
+    constexpr int SEG = NT / 8;                       // 16-byte segments per row
+    __syncthreads();                                  // halo no longer needed
+    if (res) {
+      for (int e = threadIdx.x; e < C::MT * SEG; e += NTH) {
+        const int m = e / SEG, q = e % SEG;
+        bool valid;
+        const int64_t ob = row_base(m, valid);
+        if (valid && n0 + q * 8 + 8 <= cout_store)
+          *reinterpret_cast<uint4 *>(ot + m * NT + q * 8) = *reinterpret_cast<const uint4 *>(res + ob + n0 + q * 8);
+      }
+      __syncthreads();
+    }
 #pragma unroll
-  for (int mb = 0; mb < C::MB; ++mb) {
+    for (int mb = 0; mb < C::MB; ++mb)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = wave * C::WM + mb * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
-      const int z = tz0 + m / (TY * TX), y = ty0 + (m / TX) % TY, x = tx0 + m % TX;
-      if (z >= Do || y >= Do || x >= Do) continue;
-      const int64_t ob = (pose_out + ((int64_t)z * Do + y) * Do + x) * cout_store;
+      for (int r = 0; r < 16; ++r) {
+        const int m = wave * C::WM + mb * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
 #pragma unroll
-      for (int nb = 0; nb < C::NB; ++nb) {
-        const int n = n0 + nb * 32 + lrow;
-        if (n >= cout) continue;
-        float v = acc[mb][nb][r] + bias[n];
-        if (res) v += (float)res[ob + n];
-        v = v > 0.0f ? v : 0.0f;
-        out[ob + n] = (T)v;
+        for (int nb = 0; nb < C::NB; ++nb) {
+          const int col = nb * 32 + lrow;
+          float v = acc[mb][nb][r] + bias[n0 + col];
+          if (res) v += (float)ot[m * NT + col];
+          ot[m * NT + col] = (bf16_t)(v > 0.0f ? v : 0.0f);
+        }
+      }
+    __syncthreads();
+    for (int e = threadIdx.x; e < C::MT * SEG; e += NTH) {
+      const int m = e / SEG, q = e % SEG;
+      bool valid;
+      const int64_t ob = row_base(m, valid);
+      if (valid && n0 + q * 8 + 8 <= cout_store)
+        *reinterpret_cast<uint4 *>(out + ob + n0 + q * 8) = *reinterpret_cast<const uint4 *>(ot + m * NT + q * 8);
+    }
+  } else {
+#pragma unroll
+    for (int mb = 0; mb < C::MB; ++mb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = wave * C::WM + mb * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
+        bool valid;
+        const int64_t ob = row_base(m, valid);
+        if (!valid) continue;
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) {
+          const int n = n0 + nb * 32 + lrow;
+          if (n >= cout) continue;
+          float v = acc[mb][nb][r] + bias[n];
+          if (res) v += (float)res[ob + n];
+          v = v > 0.0f ? v : 0.0f;
+          out[ob + n] = (T)v;
+        }
       }
     }
   }
@@ -235,7 +285,7 @@ hipError_t launch_t(const ConvLayer &L, const void *in, const void *res, void *o
   hipLaunchKernelGGL((k_conv<T, KS, S, TZ, TY, TX, NW, NT>), grid, dim3(NW * 64), 0, s,
                      reinterpret_cast<const T *>(in), reinterpret_cast<const T *>(L.wpk), L.bias,
                      reinterpret_cast<const T *>(res), reinterpret_cast<T *>(out), D, Do, L.cin_pad,
-                     L.cout_pad32, L.cout, L.cout_store, nty, ntx);
+                     L.cout_pad32, L.cout, L.cout_store, nty, ntx, (int)L.wbytes);
   return hipGetLastError();
 }
 

@@ -1,0 +1,383 @@
+// Serving engine: continuous batching of scoring requests on one GPU.
+//
+// The paper's screening jobs push batches of poses through the model on each
+// GPU and collect identifiers and predictions (Sec. 4.2); this engine is the
+// request-driven form of that loop.  Requests (one or more poses each, each with
+// its own grid size) are copied at submission and queued.  A host scheduler
+// thread owns `n_slots` device slots -- one stream, one scoring context with
+// resident weights and scratch, pinned staging buffers -- and whenever a slot is
+// free it packs queued requests of one grid size into a batch (continuous
+// batching: work that arrives while other batches run is admitted as slots free
+// up, and batches on different slots overlap on the device).  A batch is padded
+// with empty poses to a power-of-two bucket so its kernel sequence can be
+// captured once per (grid size, bucket) as a hipGraph and replayed.  Scores do
+// not depend on the batch a pose lands in: every kernel computes each pose
+// independently and in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "cf_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t id = 0;
+  int n_poses = 0, G = 0;
+  std::vector<int32_t> off, xyz;
+  std::vector<float> feat;
+  std::vector<uint8_t> lig;
+  Clock::time_point t_submit;
+  std::vector<float> scores;
+  int status = CF_OK;
+  bool done = false;
+  double latency_ms = 0.0;
+};
+
+struct Slot {
+  cf_ctx *ctx = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  int32_t *h_off = nullptr, *h_xyz = nullptr;
+  float *h_feat = nullptr, *h_scores = nullptr;
+  uint8_t *h_lig = nullptr;
+  int32_t *d_off = nullptr, *d_xyz = nullptr;
+  float *d_feat = nullptr, *d_scores = nullptr;
+  uint8_t *d_lig = nullptr;
+  bool busy = false;
+  std::vector<std::pair<Request *, int>> members;  // request, first pose in the batch
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+};
+
+}  // namespace
+
+struct cf_engine {
+  cf_engine_config cfg{};
+  int device = 0;
+  std::vector<Slot> slots;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request *> pending;
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+  uint64_t next_id = 1;
+  std::thread worker;
+  std::atomic<bool> stop{false};
+  std::atomic<int64_t> poses_done{0}, batches{0}, replays{0}, in_flight{0};
+  std::string last_error;
+};
+
+namespace {
+
+int bucket_for(int n, int cap) {
+  int b = 16;
+  while (b < n) b <<= 1;
+  return b < cap ? b : cap;
+}
+
+void free_slot(Slot &s) {
+  for (auto &kv : s.graphs) (void)hipGraphExecDestroy(kv.second);
+  if (s.ev) (void)hipEventDestroy(s.ev);
+  if (s.stream) (void)hipStreamDestroy(s.stream);
+  void *hp[] = {s.h_off, s.h_xyz, s.h_feat, s.h_scores, s.h_lig};
+  for (void *p : hp)
+    if (p) (void)hipHostFree(p);
+  void *dp[] = {s.d_off, s.d_xyz, s.d_feat, s.d_scores, s.d_lig};
+  for (void *p : dp)
+    if (p) (void)hipFree(p);
+  if (s.ctx) cf_destroy(s.ctx);
+}
+
+// Launch one packed batch on a free slot.  Called by the worker with mu held.
+int launch_batch(cf_engine *e, Slot &s, std::vector<Request *> &take, int G) {
+  const int cap_p = e->cfg.slot_poses;
+  int np = 0;
+  int64_t na = 0;
+  s.members.clear();
+  s.h_off[0] = 0;
+  for (Request *r : take) {
+    s.members.push_back({r, np});
+    const int64_t ra = r->off[r->n_poses];
+    memcpy(s.h_xyz + 3 * na, r->xyz.data(), sizeof(int32_t) * 3 * ra);
+    memcpy(s.h_feat + (size_t)CF_NCH * na, r->feat.data(), sizeof(float) * CF_NCH * ra);
+    memcpy(s.h_lig + na, r->lig.data(), ra);
+    for (int p = 0; p < r->n_poses; ++p) s.h_off[np + p + 1] = (int32_t)(na + r->off[p + 1]);
+    np += r->n_poses;
+    na += ra;
+  }
+  const int bucket = bucket_for(np, cap_p);
+  for (int p = np; p < bucket; ++p) s.h_off[p + 1] = (int32_t)na;  // empty padding poses
+  hipStream_t st = s.stream;
+  if (hipMemcpyAsync(s.d_off, s.h_off, sizeof(int32_t) * (bucket + 1), hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(s.d_xyz, s.h_xyz, sizeof(int32_t) * 3 * na, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(s.d_feat, s.h_feat, sizeof(float) * CF_NCH * na, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(s.d_lig, s.h_lig, na, hipMemcpyHostToDevice, st)) {
+    e->last_error = "engine H2D copy failed";
+    return CF_ERR_HIP;
+  }
+  // The batch descriptor uses the slot's capacity as n_atoms: buffers hold that
+  // many rows, and fixed arguments let one captured graph serve every batch of
+  // this (G, bucket).
+  cf_pose_batch b{};
+  b.n_poses = bucket;
+  b.n_atoms = (int32_t)e->cfg.slot_atoms;
+  b.atom_off = s.d_off;
+  b.xyz = s.d_xyz;
+  b.feat = s.d_feat;
+  b.is_lig = s.d_lig;
+  b.center = nullptr;
+  int rc = CF_OK;
+  if (e->cfg.use_graphs) {
+    auto key = std::make_pair(G, bucket);
+    auto it = s.graphs.find(key);
+    if (it == s.graphs.end()) {
+      // warm-up (allocates scratch, outside capture), then capture
+      if ((rc = cf_score_poses(s.ctx, &b, G, s.d_scores, st))) return rc;
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) return CF_ERR_HIP;
+      rc = cf_score_poses(s.ctx, &b, G, s.d_scores, st);
+      const hipError_t ce = hipStreamEndCapture(st, &g);
+      if (rc || ce != hipSuccess) return rc ? rc : CF_ERR_HIP;
+      hipGraphExec_t ex = nullptr;
+      if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return CF_ERR_HIP;
+      }
+      (void)hipGraphDestroy(g);
+      it = s.graphs.emplace(key, ex).first;
+    }
+    if (hipGraphLaunch(it->second, st) != hipSuccess) return CF_ERR_HIP;
+    e->replays++;
+  } else {
+    if ((rc = cf_score_poses(s.ctx, &b, G, s.d_scores, st))) return rc;
+  }
+  if (hipMemcpyAsync(s.h_scores, s.d_scores, sizeof(float) * np, hipMemcpyDeviceToHost, st) ||
+      hipEventRecord(s.ev, st))
+    return CF_ERR_HIP;
+  s.busy = true;
+  e->batches++;
+  e->in_flight += np;
+  return CF_OK;
+}
+
+void finish_slot(cf_engine *e, Slot &s) {
+  int64_t need_c = 0, need_n = 0;
+  const int st = cf_stream_status(s.ctx, s.stream, &need_c, &need_n);
+  const auto now = Clock::now();
+  int np = 0;
+  for (auto &m : s.members) {
+    Request *r = m.first;
+    r->scores.assign(s.h_scores + m.second, s.h_scores + m.second + r->n_poses);
+    r->status = st;
+    r->latency_ms = std::chrono::duration<double, std::milli>(now - r->t_submit).count();
+    r->done = true;
+    np += r->n_poses;
+  }
+  e->poses_done += np;
+  e->in_flight -= np;
+  s.members.clear();
+  s.busy = false;
+}
+
+void worker_main(cf_engine *e) {
+  (void)hipSetDevice(e->device);
+  std::unique_lock<std::mutex> lk(e->mu);
+  while (!e->stop) {
+    bool progressed = false;
+    for (Slot &s : e->slots)
+      if (s.busy && hipEventQuery(s.ev) == hipSuccess) {
+        finish_slot(e, s);
+        progressed = true;
+      }
+    for (Slot &s : e->slots) {
+      if (s.busy || e->pending.empty()) continue;
+      // pack queued requests with the head's grid size, in arrival order
+      const int G = e->pending.front()->G;
+      std::vector<Request *> take;
+      int np = 0;
+      int64_t na = 0;
+      for (auto it = e->pending.begin(); it != e->pending.end();) {
+        Request *r = *it;
+        const int64_t ra = r->off[r->n_poses];
+        if (r->G == G && np + r->n_poses <= e->cfg.slot_poses && na + ra <= e->cfg.slot_atoms) {
+          take.push_back(r);
+          np += r->n_poses;
+          na += ra;
+          it = e->pending.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      const int rc = launch_batch(e, s, take, G);
+      if (rc != CF_OK) {
+        for (Request *r : take) {
+          r->status = rc;
+          r->done = true;
+        }
+        s.busy = false;
+        (void)hipStreamSynchronize(s.stream);
+      }
+      progressed = true;
+    }
+    e->cv.notify_all();
+    if (!progressed) {
+      bool any_busy = false;
+      for (Slot &s : e->slots) any_busy |= s.busy;
+      // idle: sleep until work arrives; busy: poll the slots' events
+      if (any_busy)
+        e->cv.wait_for(lk, std::chrono::microseconds(20));
+      else
+        e->cv.wait_for(lk, std::chrono::milliseconds(5));
+    }
+  }
+}
+
+int efail(cf_engine *e, int code, const char *msg) {
+  if (e) e->last_error = msg;
+  return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cf_engine_create(const void *blob, size_t nbytes, int precision, const cf_engine_config *cfg, cf_engine **out) {
+  if (!out || !cfg) return CF_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (cfg->n_slots < 1 || cfg->n_slots > 8 || cfg->slot_poses < 1 || cfg->slot_poses > 512 || cfg->slot_atoms < 1 ||
+      cfg->slot_atoms > (int64_t)cfg->slot_poses * CF_MAX_POSE_ATOMS || cfg->slot_atoms > INT32_MAX)
+    return CF_ERR_INVALID_ARG;
+  auto e = std::make_unique<cf_engine>();
+  e->cfg = *cfg;
+  if (hipGetDevice(&e->device) != hipSuccess) return CF_ERR_HIP;
+  const int64_t budget = cfg->hbm_budget_bytes > 0 ? cfg->hbm_budget_bytes : ((int64_t)32 << 30);
+  const int64_t per_slot = budget / cfg->n_slots;
+  e->slots.resize(cfg->n_slots);
+  const size_t A = (size_t)cfg->slot_atoms, P = (size_t)cfg->slot_poses;
+  for (Slot &s : e->slots) {
+    int rc = cf_create(blob, nbytes, precision, per_slot, &s.ctx);
+    if (rc) {
+      for (Slot &t : e->slots) free_slot(t);
+      return rc;
+    }
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) ||
+        hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) ||
+        hipHostMalloc((void **)&s.h_off, sizeof(int32_t) * (P + 1), 0) ||
+        hipHostMalloc((void **)&s.h_xyz, sizeof(int32_t) * 3 * A, 0) ||
+        hipHostMalloc((void **)&s.h_feat, sizeof(float) * CF_NCH * A, 0) ||
+        hipHostMalloc((void **)&s.h_lig, A, 0) || hipHostMalloc((void **)&s.h_scores, sizeof(float) * P, 0) ||
+        hipMalloc(&s.d_off, sizeof(int32_t) * (P + 1)) || hipMalloc(&s.d_xyz, sizeof(int32_t) * 3 * A) ||
+        hipMalloc(&s.d_feat, sizeof(float) * CF_NCH * A) || hipMalloc(&s.d_lig, A) ||
+        hipMalloc(&s.d_scores, sizeof(float) * P)) {
+      for (Slot &t : e->slots) free_slot(t);
+      return CF_ERR_OOM;
+    }
+  }
+  cf_engine *raw = e.release();
+  raw->worker = std::thread(worker_main, raw);
+  *out = raw;
+  return CF_OK;
+}
+
+int cf_engine_submit(cf_engine *e, int32_t n_poses, const int32_t *atom_off, const int32_t *xyz, const float *feat,
+                     const uint8_t *is_lig, int32_t G, uint64_t *ticket) {
+  if (!e || !ticket || !atom_off || !xyz || !feat || !is_lig) return efail(e, CF_ERR_INVALID_ARG, "null argument");
+  if (n_poses < 1 || n_poses > e->cfg.slot_poses) return efail(e, CF_ERR_INVALID_ARG, "n_poses outside 1..slot_poses");
+  if (G < 8 || G > 96 || (G & 3)) return efail(e, CF_ERR_UNSUPPORTED, "grid size must be a multiple of 4 in 8..96");
+  if (atom_off[0] != 0) return efail(e, CF_ERR_INVALID_ARG, "atom_off[0] must be 0");
+  for (int p = 0; p < n_poses; ++p) {
+    const int32_t d = atom_off[p + 1] - atom_off[p];
+    if (d < 1 || d > CF_MAX_POSE_ATOMS) return efail(e, CF_ERR_INVALID_ARG, "each pose needs 1..4096 atoms");
+  }
+  const int64_t na = atom_off[n_poses];
+  if (na > e->cfg.slot_atoms) return efail(e, CF_ERR_INVALID_ARG, "request has more atoms than a slot holds");
+  auto r = std::make_unique<Request>();
+  r->n_poses = n_poses;
+  r->G = G;
+  r->off.assign(atom_off, atom_off + n_poses + 1);
+  r->xyz.assign(xyz, xyz + 3 * na);
+  r->feat.assign(feat, feat + (size_t)CF_NCH * na);
+  r->lig.assign(is_lig, is_lig + na);
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(e->mu);
+    r->id = e->next_id++;
+    *ticket = r->id;
+    e->pending.push_back(r.get());
+    e->reqs.emplace(r->id, std::move(r));
+  }
+  e->cv.notify_all();
+  return CF_OK;
+}
+
+int cf_engine_poll(cf_engine *e, uint64_t ticket, float *scores_out, int32_t *done, double *latency_ms) {
+  if (!e || !done) return efail(e, CF_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(e->mu);
+  auto it = e->reqs.find(ticket);
+  if (it == e->reqs.end()) return efail(e, CF_ERR_INVALID_ARG, "unknown ticket");
+  Request *r = it->second.get();
+  *done = r->done ? 1 : 0;
+  if (!r->done) return CF_OK;
+  if (scores_out) memcpy(scores_out, r->scores.data(), sizeof(float) * r->scores.size());
+  if (latency_ms) *latency_ms = r->latency_ms;
+  const int st = r->status;
+  e->reqs.erase(it);
+  return st;
+}
+
+int cf_engine_wait_all(cf_engine *e) {
+  if (!e) return CF_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(e->mu);
+  e->cv.wait(lk, [&] {
+    if (!e->pending.empty()) return false;
+    for (Slot &s : e->slots)
+      if (s.busy) return false;
+    return true;
+  });
+  return CF_OK;
+}
+
+int cf_engine_info(cf_engine *e, int64_t *poses_done, int64_t *batches, int64_t *graph_replays, int64_t *queued) {
+  if (!e) return CF_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(e->mu);
+  if (poses_done) *poses_done = e->poses_done;
+  if (batches) *batches = e->batches;
+  if (graph_replays) *graph_replays = e->replays;
+  if (queued) {
+    int64_t q = 0;
+    for (Request *r : e->pending) q += r->n_poses;
+    *queued = q;
+  }
+  return CF_OK;
+}
+
+const char *cf_engine_last_error(cf_engine *e) { return e ? e->last_error.c_str() : "engine is NULL"; }
+
+void cf_engine_destroy(cf_engine *e) {
+  if (!e) return;
+  {
+    std::lock_guard<std::mutex> lk(e->mu);
+    e->stop = true;
+  }
+  e->cv.notify_all();
+  if (e->worker.joinable()) e->worker.join();
+  for (Slot &s : e->slots) {
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    free_slot(s);
+  }
+  delete e;
+}
+
+}  // extern "C"

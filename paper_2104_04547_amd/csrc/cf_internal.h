@@ -51,6 +51,7 @@ struct ConvLayer {
   int cout_pad32;  // output channels rounded up to 32 (packed weight rows)
   int cout_store;  // output channel stride (multiple of 16)
   void *wpk;       // packed weights (precision dtype)
+  int64_t wbytes;  // size of the packed weights in bytes
   float *bias;     // folded bias [cout_pad32]
 };
 
