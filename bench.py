@@ -118,6 +118,48 @@ def cpu_baseline(batch, arch, w, G, n):
                 seconds=dt)
 
 
+def serve_leg(arch, w, res, seconds):
+    """Open-loop Poisson serving: requests of U{1..256} poses (200-1500 atoms),
+    grid 48^3 or 64^3 per request, continuous batching on 4 slots with hipGraph
+    replay.  Both forms at equal load (0.7 x the plain path's capacity for this
+    request mix), and the precision form at 0.7 x its own capacity."""
+    import numpy as np
+    import synth
+    from paper_2104_04547_amd.serve import Engine, make_requests, run_open_loop, warm_up
+    f48, f64 = arch.flops_per_pose(48), arch.flops_per_pose(64)
+    mix = 2.0 / (1.0 + f64 / f48)            # capacity at the 48/64 mix relative to 48^3
+    mean_req = 128.5
+    cap = {p: res[p]["poses_per_s"] * mix for p in res}
+    t0 = time.perf_counter()
+    pool = synth.make_poses("c5", 2048)
+    log(f"serving pool: {pool.n_poses} poses in {time.perf_counter() - t0:.1f}s")
+    runs = [("bf16", 0.7 * cap["fp32"], "equal_load"), ("fp32", 0.7 * cap["fp32"], "equal_load"),
+            ("bf16", 0.7 * cap["bf16"], "own_capacity")]
+    out = {}
+    engines = {}
+    try:
+        for prec, poses_rate, tag in runs:
+            if prec not in engines:
+                engines[prec] = Engine(arch, w, prec, n_slots=4, slot_poses=512, slot_atoms=512 * 1600,
+                                       hbm_budget_bytes=64 << 30)
+                t0 = time.perf_counter()
+                warm_up(engines[prec], pool)
+                log(f"serving {prec}: graphs captured in {time.perf_counter() - t0:.1f}s")
+            rps = poses_rate / mean_req
+            n_req = max(20, int(rps * seconds))
+            reqs = make_requests(pool, n_req, np.random.default_rng(7))
+            r = run_open_loop(engines[prec], reqs, rps, seed=11)
+            r["offered_poses_per_s"] = poses_rate
+            r.update(engines[prec].info())
+            out[f"{prec}_{tag}"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
+            log(f"serving {prec} {tag}: {r['poses_per_s']:.1f} poses/s, p50 {r['p50_ms']:.1f} ms, "
+                f"p99 {r['p99_ms']:.1f} ms over {r['requests']} requests")
+    finally:
+        for e in engines.values():
+            e.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +172,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=25.0)
     ap.add_argument("--json-out", default="")
     a = ap.parse_args()
 
@@ -197,6 +241,10 @@ def main():
                          **({"gbs": v["bytes"] / (v["total_ms"] * 1e-3) / 1e9} if v["bytes"] and not v["flop"] else {}))
                  for k, v in sorted(st.items())}
 
+    serving = None
+    if not a.no_serve and "fp32" in res:
+        serving = serve_leg(arch, w, res, a.serve_seconds)
+
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(batch, arch, w, G, a.cpu_poses)
@@ -247,6 +295,8 @@ def main():
                               "dominant_kernel": fdom, "achieved_tflops": round(f_ach, 2),
                               "frac_of_fp32_peak": round(f_ach / PEAK_FP32_TFLOPS, 4)}
         line["speedup_bf16_vs_fp32"] = round(bf["poses_per_s"] / f["poses_per_s"], 3)
+    if serving is not None:
+        line["serving"] = serving
     if a.json_out:
         json.dump(line, open(a.json_out, "w"), indent=1)
     print(json.dumps(line))

@@ -189,6 +189,13 @@ int cf_autotune(cf_ctx *ctx, int G, int32_t n_poses, void *stream);
 /* Chosen kernel variant per conv layer for grid size G (after cf_autotune or the
  * default table): variant_out[n_conv]. */
 int cf_conv_variants(const cf_ctx *ctx, int G, int32_t *variant_out, int32_t max_layers);
+/* Pin the conv kernel variant of every layer for grid size G (e.g. a cached
+ * autotuning result).  CF_ERR_UNSUPPORTED if a variant does not fit its layer. */
+int cf_set_conv_variants(cf_ctx *ctx, int G, const int32_t *variants, int32_t n_layers);
+/* Number of conv kernel variants in this build and the name of one (tile shape,
+ * waves, output-channel tile; "p8" = bf16 tap-pair kernel). */
+int cf_conv_variant_count(void);
+const char *cf_conv_variant_name(int32_t variant);
 
 /* Per-kernel timing (diagnostics).  While enabled, every kernel launch made by
  * the scoring entry points is bracketed by a pair of HIP events recorded on the
@@ -218,9 +225,10 @@ int cf_timing_read(cf_ctx *ctx, cf_kernel_stat *out, int32_t max_entries, int32_
  * poses to a power-of-two bucket and replays the hipGraph captured for that
  * (grid size, bucket) -- so requests that arrive while others run are admitted as
  * slots free up, and batches on different slots overlap on the device.  A pose's
- * score is bitwise the same whatever batch it lands in.  Slots whose scratch
- * would exceed hbm_budget_bytes fail creation (CF_ERR_OOM); queued work waits for
- * a free slot and is never rejected for lack of memory. */
+ * score is bitwise the same whatever batch it lands in.  Each slot's context
+ * gets an equal share of hbm_budget_bytes and splits a batch into chunks that
+ * fit it; queued work waits for a free slot and is never rejected for lack of
+ * memory. */
 typedef struct cf_engine cf_engine;
 typedef struct {
   int32_t n_slots;          /* 1..8 concurrent batches */

@@ -28,7 +28,8 @@ EXPORTS = ["cf_create", "cf_destroy", "cf_pose_centers", "cf_voxelize", "cf_buil
            "cf_sgcnn_fwd", "cf_score_poses", "cf_stream_status", "cf_last_error", "cf_model_info",
            "cf_autotune", "cf_conv_variants", "cf_timing_enable", "cf_timing_read",
            "cf_engine_create", "cf_engine_submit", "cf_engine_poll", "cf_engine_wait_all", "cf_engine_info",
-           "cf_engine_last_error", "cf_engine_destroy"]
+           "cf_engine_last_error", "cf_engine_destroy", "cf_set_conv_variants", "cf_conv_variant_count",
+           "cf_conv_variant_name"]
 
 
 class CfError(RuntimeError):
@@ -105,6 +106,9 @@ def load(path: str = LIB_PATH):
                            ctypes.c_int),
         "cf_engine_last_error": ([vp], ctypes.c_char_p),
         "cf_engine_destroy": ([vp], None),
+        "cf_set_conv_variants": ([vp, ctypes.c_int, ctypes.POINTER(i32), i32], ctypes.c_int),
+        "cf_conv_variant_count": ([], ctypes.c_int),
+        "cf_conv_variant_name": ([i32], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -231,6 +235,16 @@ def cf_conv_variants(ctx, G: int, n_layers: int):
     arr = (ctypes.c_int32 * n_layers)()
     _check(load().cf_conv_variants(ctx, G, arr, n_layers))
     return list(arr)
+
+
+def cf_set_conv_variants(ctx, G: int, variants):
+    arr = (ctypes.c_int32 * len(variants))(*variants)
+    _check(load().cf_set_conv_variants(ctx, G, arr, len(variants)))
+
+
+def cf_conv_variant_names():
+    lib = load()
+    return [lib.cf_conv_variant_name(i).decode() for i in range(lib.cf_conv_variant_count())]
 
 
 def cf_timing_enable(ctx, enable: bool = True):

@@ -138,12 +138,21 @@ int64_t pose_bytes(const cf_ctx *c, int G) {
   return b;
 }
 
-int chunk_poses(const cf_ctx *c, int G, int P) {
+// scratch bytes per atom of a chunk (neighbour lists, degrees, SG states)
+int64_t atom_bytes(const cf_ctx *c) { return 4 * (2 + 2 + 16 + 96) + 2 * 4 * (int64_t)c->desc.H; }
+
+// Poses per launch: at most 512, and the conv tensors of the chunk plus the
+// per-atom scratch of its atoms (at most n_atoms; 0 = no atom stages) must fit
+// the context's HBM budget.
+int chunk_poses(const cf_ctx *c, int G, int P, int64_t n_atoms = 0) {
   const int64_t avail = c->budget - c->weight_bytes - ((int64_t)64 << 20);
-  int64_t n = avail / (pose_bytes(c, G) + 4096);
-  if (n > 512) n = 512;
-  if (n < 1) n = 1;
-  return (int)std::min<int64_t>(n, P);
+  int n = std::min(512, P);
+  while (n > 1) {
+    const int64_t atoms = n_atoms > 0 ? std::min<int64_t>(n_atoms, (int64_t)n * CF_MAX_POSE_ATOMS) : 0;
+    if ((int64_t)n * (pose_bytes(c, G) + 4096) + atoms * atom_bytes(c) <= avail) break;
+    n = n > 64 ? n - 32 : n - 1;
+  }
+  return n < 1 ? 1 : n;
 }
 
 int validate_batch(const cf_pose_batch *b) {
@@ -270,6 +279,22 @@ std::vector<T> pack_conv(const std::vector<float> &W, int cout, int cin, int k, 
   return out;
 }
 
+// bf16 weights for the tap-pair kernel: [pair][chunk8][c_out (pad 32)][16], element
+// 8 h + c = W[n][8 chunk + c][tap 2 pair + h]; two zero pairs of padding.
+std::vector<bf16_t> pack_conv8(const std::vector<float> &W, int cout, int cin, int k, int cout_pad32) {
+  const int taps = k * k * k, pairs = (taps + 1) / 2, nch = (cin + 7) / 8;
+  std::vector<bf16_t> out((size_t)(pairs + 2) * nch * cout_pad32 * 16, (bf16_t)0.0f);
+  for (int p = 0; p < pairs; ++p)
+    for (int ch = 0; ch < nch; ++ch)
+      for (int n = 0; n < cout; ++n)
+        for (int e = 0; e < 16; ++e) {
+          const int tap = 2 * p + e / 8, c = ch * 8 + e % 8;
+          if (tap >= taps || c >= cin) continue;
+          out[(((size_t)p * nch + ch) * cout_pad32 + n) * 16 + e] = (bf16_t)W[((size_t)n * cin + c) * taps + tap];
+        }
+  return out;
+}
+
 std::vector<float> transpose(const float *w, int rows, int cols) {  // [rows][cols] -> [cols][rows]
   std::vector<float> t((size_t)rows * cols);
   for (int r = 0; r < rows; ++r)
@@ -375,6 +400,11 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
       rc = alloc_weight(c, &L.wpk, pk.size() * sizeof(float), pk.data());
     }
     if (L.wbytes >= ((int64_t)1 << 31)) return fail(CF_ERR_UNSUPPORTED, "conv layer weights exceed 2 GiB");
+    if (!rc && c->bf16) {
+      auto pk8 = pack_conv8(Wf, co, ci, k, L.cout_pad32);
+      L.wbytes8 = (int64_t)(pk8.size() * sizeof(bf16_t));
+      rc = alloc_weight(c, &L.wpk8, pk8.size() * sizeof(bf16_t), pk8.data());
+    }
     if (rc) return rc;
     if ((rc = upload_f(c, &L.bias, bf.data(), bf.size()))) return rc;
     c->conv.push_back(L);
@@ -638,7 +668,7 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
   if ((rc = validate_G(G))) return rc;
   if (!scores) return fail(CF_ERR_INVALID_ARG, "scores is NULL");
   hipStream_t s = (hipStream_t)stream;
-  const int chunk = chunk_poses(c, G, b->n_poses);
+  const int chunk = chunk_poses(c, G, b->n_poses, b->n_atoms);
   const int64_t acap = atoms_cap_for(b, chunk);
   if ((rc = ensure_act(c, G, chunk))) return rc;
   if ((rc = ensure_atoms(c, acap, chunk))) return rc;
@@ -749,6 +779,23 @@ int cf_conv_variants(const cf_ctx *c, int G, int32_t *variant_out, int32_t max_l
   for (int i = 0; i < (int)v.size() && i < max_layers; ++i) variant_out[i] = v[i];
   return CF_OK;
 }
+
+int cf_set_conv_variants(cf_ctx *c, int G, const int32_t *variants, int32_t n_layers) {
+  if (!c || !variants) return fail(CF_ERR_INVALID_ARG, "bad arguments");
+  int rc = validate_G(G);
+  if (rc) return rc;
+  if (n_layers != (int32_t)c->conv.size()) return fail(CF_ERR_INVALID_ARG, "one variant per conv layer is needed");
+  std::vector<int> v(variants, variants + n_layers);
+  for (int i = 0; i < n_layers; ++i)
+    if (!cf::conv_variant_ok(v[i], c->conv[i], c->bf16))
+      return fail(CF_ERR_UNSUPPORTED, "variant does not fit layer " + std::to_string(i));
+  c->variants[G] = v;
+  return CF_OK;
+}
+
+int cf_conv_variant_count(void) { return cf::conv_num_variants(); }
+
+const char *cf_conv_variant_name(int32_t variant) { return cf::conv_variant_name(variant); }
 
 int cf_autotune(cf_ctx *c, int G, int32_t n_poses, void *stream) {
   if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");

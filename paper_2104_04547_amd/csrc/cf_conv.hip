@@ -269,12 +269,231 @@ __global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, cons
   }
 }
 
+// ---- bf16 with 8-channel chunks and tap pairs ---------------------------------
+//
+// Same implicit GEMM, but the K walk pairs two consecutive taps of one 8-channel
+// chunk into each 16-deep MFMA step: lanes of the first K half read their row at
+// tap 2p, lanes of the second half at tap 2p+1.  The halo then needs 16 bytes per
+// voxel, so an 8x8x8 output tile (128 rows per wave, 8 MFMAs per step) fits twice
+// per CU, halving the weight traffic per FLOP of the 64-row tiles; and a 19-channel
+// input costs 3 chunks instead of the 2 x 16 = 32 padded channels.
+template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+struct Conv8Cfg {
+  static constexpr int PAD = (KS - 1) / 2;
+  static constexpr int HZ = TZ * S + KS - S, HY = TY * S + KS - S, HX = TX * S + KS - S;
+  static constexpr int ROW = HX * 16 + 16;  // bytes, padded
+  static constexpr int SLAB = HY * ROW;
+  static constexpr int HALO = HZ * SLAB;
+  static constexpr int MT = TZ * TY * TX;
+  static constexpr int WM = MT / NW;
+  static constexpr int MB = WM / 32, NB = NT / 32;
+  static constexpr int TAPS = KS * KS * KS, PAIRS = (TAPS + 1) / 2;
+  // epilogue: output rows go through LDS in groups of MBG 32-row blocks per wave
+  static constexpr int MBG = (NW * 32 * NT * 2 * MB <= HALO) ? MB : ((NW * 32 * NT * 2 * 2 <= HALO && MB % 2 == 0) ? 2 : 1);
+  static constexpr int EPI = NW * 32 * MBG * NT * 2;
+  static constexpr int LDS = HALO > EPI ? HALO : EPI;
+  static_assert(WM % 32 == 0, "rows per wave must be a multiple of 32");
+  static_assert(LDS <= 163840, "halo exceeds LDS");
+};
+
+template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_conv8(const bf16_t *__restrict__ in, const bf16_t *__restrict__ wpk,
+                                                    const float *__restrict__ bias, const bf16_t *__restrict__ res,
+                                                    bf16_t *__restrict__ out, int D, int Do, int cin_pad,
+                                                    int nchunks, int cout_pad32, int cout, int cout_store, int nty,
+                                                    int ntx, int wbytes) {
+  using C = Conv8Cfg<KS, S, TZ, TY, TX, NW, NT>;
+  __shared__ __attribute__((aligned(16))) char lds[C::LDS];
+  const int tile = blockIdx.x;
+  const int pose = blockIdx.y;
+  const int n0 = blockIdx.z * NT;
+  const int tz0 = (tile / (nty * ntx)) * TZ, ty0 = ((tile / ntx) % nty) * TY, tx0 = (tile % ntx) * TX;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int khalf = lane >> 5, lrow = lane & 31;
+  constexpr int NTH = NW * 64;
+
+  int rowoff[C::MB];
+#pragma unroll
+  for (int mb = 0; mb < C::MB; ++mb) {
+    const int m = wave * C::WM + mb * 32 + lrow;
+    const int z = m / (TY * TX), y = (m / TX) % TY, x = m % TX;
+    rowoff[mb] = z * C::SLAB + y * C::ROW + x * 16;
+  }
+  typedef float accv __attribute__((ext_vector_type(16)));
+  accv acc[C::MB][C::NB];
+#pragma unroll
+  for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
+
+  const int oz = tz0 * S - C::PAD, oy = ty0 * S - C::PAD, ox = tx0 * S - C::PAD;
+  const int64_t pose_in = (int64_t)pose * D * D * D;
+  constexpr int HZ2 = S == 1 ? 0 : (C::HZ + 1) / 2;
+  constexpr int HY2 = S == 1 ? 0 : (C::HY + 1) / 2;
+  constexpr int HX2 = S == 1 ? 0 : (C::HX + 1) / 2;
+  constexpr int NV = C::HZ * C::HY * C::HX;
+  constexpr int HITER = (NV + NTH - 1) / NTH;
+  auto tapoff = [&](int dz, int dy, int dx) {
+    return (S == 1 ? dz : (dz & 1) * HZ2 + (dz >> 1)) * C::SLAB +
+           (S == 1 ? dy : (dy & 1) * HY2 + (dy >> 1)) * C::ROW + (S == 1 ? dx : (dx & 1) * HX2 + (dx >> 1)) * 16;
+  };
+
+  const int pair_bytes = nchunks * cout_pad32 * 16 * 2;
+  const __amdgpu_buffer_rsrc_t wrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(wpk), (short)0, wbytes, 0x00020000);
+  for (int chunk = 0; chunk < nchunks; ++chunk) {
+    if (chunk) __syncthreads();
+    constexpr int HB = HITER < 6 ? HITER : 6;  // halo iterations in flight per batch
+#pragma unroll
+    for (int it0 = 0; it0 < HITER; it0 += HB) {
+      uint4 hv[HB];
+#pragma unroll
+      for (int it = it0; it < it0 + HB && it < HITER; ++it) {
+        const int v = it * NTH + (int)threadIdx.x;
+        hv[it - it0] = make_uint4(0, 0, 0, 0);
+        if (v < NV) {
+          const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
+          const int gz = oz + hz, gy = oy + hy, gx = ox + hx;
+          if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gx < (unsigned)D)
+            hv[it - it0] = *reinterpret_cast<const uint4 *>(
+                in + ((pose_in + ((int64_t)gz * D + gy) * D + gx) * cin_pad + chunk * 8));
+        }
+      }
+#pragma unroll
+      for (int it = it0; it < it0 + HB && it < HITER; ++it) {
+        const int v = it * NTH + (int)threadIdx.x;
+        if (v < NV) {
+          const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
+          const int off = stored_index(hz, C::HZ, S) * C::SLAB + stored_index(hy, C::HY, S) * C::ROW +
+                          stored_index(hx, C::HX, S) * 16;
+          *reinterpret_cast<uint4 *>(lds + off) = hv[it - it0];
+        }
+      }
+    }
+    __syncthreads();
+    int vb[C::NB];
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb) vb[nb] = ((chunk * cout_pad32 + n0 + nb * 32 + lrow) * 16 + khalf * 8) * 2;
+    uint4 b1[C::NB], b2[C::NB];
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb) {
+      b1[nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], 0, 0));
+      b2[nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], pair_bytes, 0));
+    }
+    int soff = 2 * pair_bytes;
+    int dz = 0, dy = 0, dx = 0;  // tap 2p
+    for (int p = 0; p < C::PAIRS; ++p) {
+      int ez = dz, ey = dy, ex = dx + 1;  // tap 2p + 1
+      if (ex == KS) {
+        ex = 0;
+        if (++ey == KS) {
+          ey = 0;
+          ++ez;
+        }
+      }
+      const int t0 = tapoff(dz, dy, dx);
+      const int t1 = (2 * p + 1 < C::TAPS) ? tapoff(ez, ey, ex) : t0;
+      const int toff = khalf ? t1 : t0;
+      uint4 bfr[C::NB];
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb) {
+        bfr[nb] = b1[nb];
+        b1[nb] = b2[nb];
+        b2[nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], soff, 0));
+      }
+      soff += pair_bytes;
+      uint4 afr[C::MB];
+#pragma unroll
+      for (int mb = 0; mb < C::MB; ++mb) afr[mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + toff);
+#pragma unroll
+      for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, afr[mb]),
+                                                                 __builtin_bit_cast(bf16x8, bfr[nb]), acc[mb][nb], 0, 0, 0);
+      dx += 2;
+      if (dx >= KS) {
+        dx -= KS;
+        if (++dy == KS) {
+          dy = 0;
+          ++dz;
+        }
+      }
+    }
+  }
+
+  // ---- epilogue through LDS, MBG row blocks per wave at a time ----
+  const int64_t pose_out = (int64_t)pose * Do * Do * Do;
+  auto row_base = [&](int m, bool &valid) -> int64_t {
+    const int z = tz0 + m / (TY * TX), y = ty0 + (m / TX) % TY, x = tx0 + m % TX;
+    valid = z < Do && y < Do && x < Do;
+    return (pose_out + ((int64_t)z * Do + y) * Do + x) * cout_store;
+  };
+  bf16_t *ot = reinterpret_cast<bf16_t *>(lds);  // [NW][MBG*32][NT]
+  constexpr int SEG = NT / 8;
+  constexpr int GR = C::MBG * 32;  // rows per wave per group
+  // local row lr of group g -> tile row (wave lr / GR)*WM + (g + (lr % GR) / 32) * 32 + lr % 32
+#pragma unroll
+  for (int g = 0; g < C::MB; g += C::MBG) {
+    __syncthreads();
+    if (res) {
+      for (int e = threadIdx.x; e < NW * GR * SEG; e += NTH) {
+        const int lr = e / SEG, q = e % SEG;
+        const int m = (lr / GR) * C::WM + g * 32 + lr % GR;
+        bool valid;
+        const int64_t ob = row_base(m, valid);
+        if (valid && n0 + q * 8 + 8 <= cout_store)
+          *reinterpret_cast<uint4 *>(ot + lr * NT + q * 8) = *reinterpret_cast<const uint4 *>(res + ob + n0 + q * 8);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int mb = g; mb < g + C::MBG; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int lr = wave * GR + (mb - g) * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) {
+          const int col = nb * 32 + lrow;
+          float v = acc[mb][nb][r] + bias[n0 + col];
+          if (res) v += (float)ot[lr * NT + col];
+          ot[lr * NT + col] = (bf16_t)(v > 0.0f ? v : 0.0f);
+        }
+      }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NW * GR * SEG; e += NTH) {
+      const int lr = e / SEG, q = e % SEG;
+      const int m = (lr / GR) * C::WM + g * 32 + lr % GR;
+      bool valid;
+      const int64_t ob = row_base(m, valid);
+      if (valid && n0 + q * 8 + 8 <= cout_store)
+        *reinterpret_cast<uint4 *>(out + ob + n0 + q * 8) = *reinterpret_cast<const uint4 *>(ot + lr * NT + q * 8);
+    }
+  }
+}
+
 struct Variant {
   const char *name;
   int ks, s, tz, ty, tx, nw, nt;
+  int pairs;  // 1: bf16 8-channel tap-pair kernel (k_conv8, weights in wpk8)
   hipError_t (*launch_bf16)(const ConvLayer &, const void *, const void *, void *, int, int, hipStream_t);
   hipError_t (*launch_f32)(const ConvLayer &, const void *, const void *, void *, int, int, hipStream_t);
 };
+
+template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+hipError_t launch_p(const ConvLayer &L, const void *in, const void *res, void *out, int n_poses, int D,
+                    hipStream_t s) {
+  const int Do = (D + 2 * ((KS - 1) / 2) - KS) / S + 1;
+  const int ntz = (Do + TZ - 1) / TZ, nty = (Do + TY - 1) / TY, ntx = (Do + TX - 1) / TX;
+  const dim3 grid(ntz * nty * ntx, n_poses, L.cout_pad32 / NT);
+  hipLaunchKernelGGL((k_conv8<KS, S, TZ, TY, TX, NW, NT>), grid, dim3(NW * 64), 0, s,
+                     reinterpret_cast<const bf16_t *>(in), reinterpret_cast<const bf16_t *>(L.wpk8), L.bias,
+                     reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), D, Do, L.cin_pad,
+                     (L.cin + 7) / 8, L.cout_pad32, L.cout, L.cout_store, nty, ntx, (int)L.wbytes8);
+  return hipGetLastError();
+}
 
 template <typename T, int KS, int S, int TZ, int TY, int TX, int NW, int NT>
 hipError_t launch_t(const ConvLayer &L, const void *in, const void *res, void *out, int n_poses, int D,
@@ -289,10 +508,15 @@ hipError_t launch_t(const ConvLayer &L, const void *in, const void *res, void *o
   return hipGetLastError();
 }
 
-#define CF_VARIANT(KS, S, TZ, TY, TX, NW, NT)                                              \
-  Variant {                                                                                \
-    "k" #KS "s" #S "_t" #TZ "x" #TY "x" #TX "_w" #NW "_n" #NT, KS, S, TZ, TY, TX, NW, NT, \
+#define CF_VARIANT(KS, S, TZ, TY, TX, NW, NT)                                                 \
+  Variant {                                                                                   \
+    "k" #KS "s" #S "_t" #TZ "x" #TY "x" #TX "_w" #NW "_n" #NT, KS, S, TZ, TY, TX, NW, NT, 0,   \
         &launch_t<bf16_t, KS, S, TZ, TY, TX, NW, NT>, &launch_t<float, KS, S, TZ, TY, TX, NW, NT> \
+  }
+#define CF_VARIANT8(KS, S, TZ, TY, TX, NW, NT)                                                   \
+  Variant {                                                                                      \
+    "p8k" #KS "s" #S "_t" #TZ "x" #TY "x" #TX "_w" #NW "_n" #NT, KS, S, TZ, TY, TX, NW, NT, 1,   \
+        &launch_p<KS, S, TZ, TY, TX, NW, NT>, nullptr                                            \
   }
 
 const Variant kVariants[] = {
@@ -308,6 +532,16 @@ const Variant kVariants[] = {
     CF_VARIANT(7, 2, 4, 4, 8, 2, 64),   // 9
     CF_VARIANT(7, 2, 4, 4, 8, 2, 128),  // 10
     CF_VARIANT(7, 2, 2, 8, 8, 2, 64),   // 11
+    CF_VARIANT8(7, 1, 8, 8, 8, 4, 64),  // 12: tap pairs, 128 rows per wave
+    CF_VARIANT8(7, 1, 4, 8, 8, 4, 64),  // 13
+    CF_VARIANT8(7, 1, 4, 8, 8, 2, 64),  // 14
+    CF_VARIANT8(7, 2, 4, 4, 8, 4, 64),  // 15
+    CF_VARIANT8(7, 2, 4, 8, 8, 4, 64),  // 16
+    CF_VARIANT8(7, 2, 4, 4, 8, 4, 128), // 17
+    CF_VARIANT8(7, 2, 4, 8, 8, 4, 128), // 18
+    CF_VARIANT8(5, 1, 8, 8, 8, 4, 32),  // 19
+    CF_VARIANT8(7, 2, 8, 8, 8, 4, 64),  // 20: stride-2 first layer, 512-row tile
+    CF_VARIANT8(7, 1, 8, 8, 8, 8, 64),  // 21
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -319,13 +553,16 @@ const char *conv_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVa
 bool conv_variant_ok(int v, const ConvLayer &L, int bf16) {
   if (v < 0 || v >= kNumVariants) return false;
   const Variant &V = kVariants[v];
+  if (V.pairs) return bf16 && L.wpk8 && V.ks == L.k && V.s == L.stride && L.cout_pad32 % V.nt == 0 && L.cin_pad % 8 == 0;
   const int cc = bf16 ? 16 : 8;
   return V.ks == L.k && V.s == L.stride && L.cout_pad32 % V.nt == 0 && L.cin_pad % cc == 0;
 }
 
 int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
   (void)D_in;
-  const int pref[] = {1, 4, 3, 6, 0, 2, 5, 7, 8, 9, 10, 11};
+  // measured on MI355X at 48^3 (bf16: tap pairs for stride 1 and the 128-column
+  // stride-2 layer; fp32 has no tap-pair kernel)
+  const int pref[] = {12, 17, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 19, 20, 21};
   for (int v : pref)
     if (conv_variant_ok(v, L, bf16)) return v;
   return -1;

@@ -15,6 +15,7 @@
 // independently and in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -132,7 +133,7 @@ int launch_batch(cf_engine *e, Slot &s, std::vector<Request *> &take, int G) {
   // this (G, bucket).
   cf_pose_batch b{};
   b.n_poses = bucket;
-  b.n_atoms = (int32_t)e->cfg.slot_atoms;
+  b.n_atoms = (int32_t)std::min<int64_t>(e->cfg.slot_atoms, (int64_t)bucket * CF_MAX_POSE_ATOMS);
   b.atom_off = s.d_off;
   b.xyz = s.d_xyz;
   b.feat = s.d_feat;
@@ -175,6 +176,7 @@ int launch_batch(cf_engine *e, Slot &s, std::vector<Request *> &take, int G) {
 void finish_slot(cf_engine *e, Slot &s) {
   int64_t need_c = 0, need_n = 0;
   const int st = cf_stream_status(s.ctx, s.stream, &need_c, &need_n);
+  if (st != CF_OK) e->last_error = std::string("device status: ") + cf_last_error();
   const auto now = Clock::now();
   int np = 0;
   for (auto &m : s.members) {
@@ -222,6 +224,7 @@ void worker_main(cf_engine *e) {
       }
       const int rc = launch_batch(e, s, take, G);
       if (rc != CF_OK) {
+        e->last_error = std::string("batch launch failed: ") + cf_last_error();
         for (Request *r : take) {
           r->status = rc;
           r->done = true;

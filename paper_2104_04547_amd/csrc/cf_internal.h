@@ -52,6 +52,8 @@ struct ConvLayer {
   int cout_store;  // output channel stride (multiple of 16)
   void *wpk;       // packed weights (precision dtype)
   int64_t wbytes;  // size of the packed weights in bytes
+  void *wpk8;      // bf16 only: weights packed for the tap-pair kernel
+  int64_t wbytes8;
   float *bias;     // folded bias [cout_pad32]
 };
 

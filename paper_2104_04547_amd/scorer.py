@@ -105,3 +105,6 @@ class Scorer:
 
     def variants(self, G: int):
         return cfabi.cf_conv_variants(self.ctx, G, len(self.arch.conv))
+
+    def set_variants(self, G: int, variants):
+        cfabi.cf_set_conv_variants(self.ctx, G, list(variants))

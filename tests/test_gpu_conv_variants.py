@@ -1,0 +1,73 @@
+"""Every conv kernel variant (tile shape, waves, channel chunking) must give the
+oracle's CNN latents: each variant is pinned onto every layer it fits and the
+3D-CNN head is compared with the FP64 oracle, including ragged output tiles."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import weights
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cases():
+    out = {}
+    for arch_name, G in (("tiny", 24), ("full", 24), ("full", 40)):
+        arch, w = weights(arch_name)
+        b = synth.make_poses("c1" if G == 24 else "c2", 2)
+        cen = np.stack([oracle.pose_center(b.xyz[b.atom_off[p]:b.atom_off[p + 1]][
+            b.is_lig[b.atom_off[p]:b.atom_off[p + 1]].astype(bool)]) for p in range(b.n_poses)])
+        grids = oracle.splat_batch(b, cen, G)
+        want = np.stack([oracle.cnn3d_forward(g, w, arch)[0] for g in grids])
+        out[(arch_name, G)] = (arch, w, grids, want)
+    return out
+
+
+@pytest.mark.parametrize("arch_name,G", [("tiny", 24), ("full", 24), ("full", 40)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_every_conv_variant_matches_oracle(cases, arch_name, G, prec):
+    import torch
+    from paper_2104_04547_amd import Scorer, cfabi
+    arch, w, grids, want = cases[(arch_name, G)]
+    s = Scorer(arch, w, prec)
+    try:
+        default = s.variants(G)
+        names = cfabi.cf_conv_variant_names()
+        tried = 0
+        x = torch.from_numpy(grids.astype(np.float32)).cuda()
+        if prec == "bf16":
+            x = x.to(torch.bfloat16)
+        for v in range(len(names)):
+            sel = list(default)
+            fits = False
+            for i in range(len(arch.conv)):
+                try:
+                    trial = list(sel)
+                    trial[i] = v
+                    s.set_variants(G, trial)
+                    sel = trial
+                    fits = True
+                except cfabi.CfError:
+                    s.set_variants(G, sel)
+            if not fits:
+                continue
+            tried += 1
+            _say(f"cf_cnn3d_fwd {prec} arch={arch_name} G={G} variant {v} {names[v]} layers={sel}")
+            got = s.cnn3d(x, G).cpu().numpy()
+            scale = np.abs(want).max()
+            if prec == "fp32":
+                np.testing.assert_allclose(got, want, rtol=1e-4, atol=1e-4 * scale, err_msg=names[v])
+            else:
+                np.testing.assert_allclose(got, want, rtol=3e-2, atol=3e-2 * scale, err_msg=names[v])
+        assert tried >= 2
+    finally:
+        s.close()
