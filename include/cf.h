@@ -215,6 +215,22 @@ typedef struct {
 int cf_timing_enable(cf_ctx *ctx, int enable);
 int cf_timing_read(cf_ctx *ctx, cf_kernel_stat *out, int32_t max_entries, int32_t *n_out);
 
+/* ---- Selection after scoring --------------------------------------------------
+ * Per-compound aggregation: the paper represents each compound by its strongest
+ * prediction over all its docked poses (the maximum Coherent Fusion pK; up to 10
+ * poses per site, Sec. 5.1).  Segment c covers scores[compound_off[c] ..
+ * compound_off[c+1]); best_score[c] is its maximum and best_pose[c] the lowest
+ * index attaining it.  NaN scores are ignored; an empty (or all-NaN) segment gives
+ * -inf and -1.  Offsets outside [0, n_scores] are reported by cf_stream_status.
+ * All pointers are device pointers. */
+int cf_compound_max(cf_ctx *ctx, const float *scores, int32_t n_scores, const int32_t *compound_off,
+                    int32_t n_compounds, float *best_score, int32_t *best_pose, void *stream);
+/* Top-k selection (the paper's example: the best 100 of a million screened
+ * compounds, Sec. 3.4): the k largest values in descending order, ties by lower
+ * index, NaN last; idx_out [k], val_out [k] or NULL.  0 <= k <= min(n, 1024). */
+int cf_top_k(cf_ctx *ctx, const float *values, int32_t n, int32_t k, int32_t *idx_out, float *val_out,
+             void *stream);
+
 /* ---- Serving engine (continuous batching) ------------------------------------
  * The request-driven form of the paper's per-GPU scoring loop (Sec. 4.2): each
  * request carries one or more poses (host arrays, copied before submit returns)

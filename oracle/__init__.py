@@ -14,9 +14,10 @@ from .cf_oracle import (U_PER_A, SPLAT_RCUT_U, SPLAT_TWO_SIGMA2_U2, SELU_LAMBDA,
                         pose_center, voxel_center, splat_pose, splat_batch, conv3d, batchnorm,
                         cnn3d_forward, radius_graph_pose, radius_graph_batch, gru_cell,
                         sgcnn_pose, sgcnn_batch, selu, fusion_head, late_fusion, score_pose,
-                        score_batch)
+                        score_batch, compound_best, top_k)
 
 __all__ = ["U_PER_A", "SPLAT_RCUT_U", "SPLAT_TWO_SIGMA2_U2", "SELU_LAMBDA", "SELU_ALPHA",
            "pose_center", "voxel_center", "splat_pose", "splat_batch", "conv3d", "batchnorm",
            "cnn3d_forward", "radius_graph_pose", "radius_graph_batch", "gru_cell", "sgcnn_pose",
-           "sgcnn_batch", "selu", "fusion_head", "late_fusion", "score_pose", "score_batch"]
+           "sgcnn_batch", "selu", "fusion_head", "late_fusion", "score_pose", "score_batch",
+           "compound_best", "top_k"]

@@ -288,8 +288,8 @@ def late_fusion(pk_cnn: np.ndarray, pk_sg: np.ndarray) -> np.ndarray:
 def score_pose(xyz, feat, is_lig, w, arch, G: int, center: Optional[np.ndarray] = None,
                detail: bool = False):
     is_lig = np.asarray(is_lig).astype(bool)
-    if center is None:
-        center = pose_center(np.asarray(xyz)[is_lig])
+    if center is None:   # grid centre: ligand centroid, or all atoms' if the pose has no ligand atom
+        center = pose_center(np.asarray(xyz)[is_lig] if is_lig.any() else np.asarray(xyz))
     grid = splat_pose(xyz, feat, center, G)
     cnn_lat, _ = cnn3d_forward(grid, w, arch)
     cov = radius_graph_pose(xyz, arch.r_cov_u)
@@ -321,3 +321,32 @@ def score_batch(batch, w, arch, G: int, poses: Optional[Sequence[int]] = None,
 
 def _score_one(x, f, l, w, arch, G):
     return score_pose(x, f, l, w, arch, G)
+
+
+# --------------------------------------------------------------------------------
+# Selection after scoring (Sec. 5.1: a compound is represented by its strongest
+# prediction over all its docked poses -- the maximum Fusion pK; Sec. 3.4: the best
+# 100 of a million screened compounds are bought)
+# --------------------------------------------------------------------------------
+
+def compound_best(scores, compound_off):
+    """Per segment [off[c], off[c+1]): (max score, lowest index attaining it);
+    NaN scores are ignored; an empty or all-NaN segment gives (-inf, -1)."""
+    best, idx = [], []
+    for c in range(len(compound_off) - 1):
+        b, i = -np.inf, -1
+        for p in range(int(compound_off[c]), int(compound_off[c + 1])):
+            v = float(scores[p])
+            if v == v and (i < 0 or v > b):
+                b, i = v, p
+        best.append(b)
+        idx.append(i)
+    return np.array(best), np.array(idx, dtype=np.int64)
+
+
+def top_k(values, k: int):
+    """Indices of the k largest values in descending order; equal values by lower
+    index; NaN after every number."""
+    v = np.asarray(values, dtype=np.float64)
+    keyed = sorted(range(len(v)), key=lambda i: (1, 0.0, i) if v[i] != v[i] else (0, -v[i], i))
+    return np.array(keyed[:k], dtype=np.int64)

@@ -29,7 +29,7 @@ EXPORTS = ["cf_create", "cf_destroy", "cf_pose_centers", "cf_voxelize", "cf_buil
            "cf_autotune", "cf_conv_variants", "cf_timing_enable", "cf_timing_read",
            "cf_engine_create", "cf_engine_submit", "cf_engine_poll", "cf_engine_wait_all", "cf_engine_info",
            "cf_engine_last_error", "cf_engine_destroy", "cf_set_conv_variants", "cf_conv_variant_count",
-           "cf_conv_variant_name"]
+           "cf_conv_variant_name", "cf_compound_max", "cf_top_k"]
 
 
 class CfError(RuntimeError):
@@ -109,6 +109,8 @@ def load(path: str = LIB_PATH):
         "cf_set_conv_variants": ([vp, ctypes.c_int, ctypes.POINTER(i32), i32], ctypes.c_int),
         "cf_conv_variant_count": ([], ctypes.c_int),
         "cf_conv_variant_name": ([i32], ctypes.c_char_p),
+        "cf_compound_max": ([vp, vp, i32, vp, i32, vp, vp, vp], ctypes.c_int),
+        "cf_top_k": ([vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -245,6 +247,15 @@ def cf_set_conv_variants(ctx, G: int, variants):
 def cf_conv_variant_names():
     lib = load()
     return [lib.cf_conv_variant_name(i).decode() for i in range(lib.cf_conv_variant_count())]
+
+
+def cf_compound_max(ctx, scores_ptr: int, n_scores: int, off_ptr: int, n_compounds: int, best_ptr: int,
+                    best_idx_ptr: int, stream: int = 0):
+    _check(load().cf_compound_max(ctx, scores_ptr, n_scores, off_ptr, n_compounds, best_ptr, best_idx_ptr, stream))
+
+
+def cf_top_k(ctx, values_ptr: int, n: int, k: int, idx_ptr: int, val_ptr, stream: int = 0):
+    _check(load().cf_top_k(ctx, values_ptr, n, k, idx_ptr, val_ptr, stream))
 
 
 def cf_timing_enable(ctx, enable: bool = True):

@@ -72,7 +72,7 @@ struct cf_ctx {
   std::map<std::string, Stat> stats;
 
   // scratch
-  DevBuf grid, centers, cnn_lat, sg_lat, deg, pose_tot, cov_row, cov_col, nc_row, nc_col, hbuf;
+  DevBuf grid, centers, cnn_lat, sg_lat, deg, pose_tot, cov_row, cov_col, nc_row, nc_col, hbuf, sel;
   std::vector<DevBuf> act;  // t_1 .. t_L
   std::map<int, std::vector<int>> variants;  // per G
 };
@@ -508,7 +508,7 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
 void free_ctx(cf_ctx *c) {
   for (void *p : c->weight_allocs) (void)hipFree(p);
   DevBuf *bufs[] = {&c->grid, &c->centers, &c->cnn_lat, &c->sg_lat, &c->deg, &c->pose_tot,
-                    &c->cov_row, &c->cov_col, &c->nc_row, &c->nc_col, &c->hbuf};
+                    &c->cov_row, &c->cov_col, &c->nc_row, &c->nc_col, &c->hbuf, &c->sel};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto &b : c->act)
@@ -711,6 +711,26 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
                              c->desc.fusion_hidden, c->fus_w2, c->fus_b2, np, scores + p0, s));
     tend(c, s, e, "fusion", 0.0, 0.0);
   }
+  return CF_OK;
+}
+
+int cf_compound_max(cf_ctx *c, const float *scores, int32_t n_scores, const int32_t *compound_off,
+                    int32_t n_compounds, float *best_score, int32_t *best_pose, void *stream) {
+  if (!c || !scores || !compound_off || !best_score || !best_pose) return fail(CF_ERR_INVALID_ARG, "null argument");
+  if (n_scores < 0 || n_compounds < 0) return fail(CF_ERR_INVALID_ARG, "negative size");
+  CF_HIP(cf::launch_segmax(scores, n_scores, compound_off, n_compounds, best_score, best_pose, c->status,
+                           (hipStream_t)stream));
+  return CF_OK;
+}
+
+int cf_top_k(cf_ctx *c, const float *values, int32_t n, int32_t k, int32_t *idx_out, float *val_out, void *stream) {
+  if (!c || !values || !idx_out) return fail(CF_ERR_INVALID_ARG, "null argument");
+  if (n < 0 || k < 0 || k > n) return fail(CF_ERR_INVALID_ARG, "need 0 <= k <= n");
+  if (k > 1024) return fail(CF_ERR_UNSUPPORTED, "k must be <= 1024");
+  if (k == 0) return CF_OK;
+  int rc = ensure(c, c->sel, 1088 + 8 * (size_t)1024);
+  if (rc) return rc;
+  CF_HIP(cf::launch_topk(values, n, k, idx_out, val_out, c->sel.p, (hipStream_t)stream));
   return CF_OK;
 }
 

@@ -107,6 +107,11 @@ hipError_t launch_sgcnn(const SgWeights &W, int bf16, const int32_t *atom_off, i
                         const int32_t *nc_col, int64_t nc_cap, int csr_global, float *hbuf,
                         int64_t hcap_atoms, float *sg_latent, int64_t *status, hipStream_t s);
 
+hipError_t launch_segmax(const float *scores, int n_scores, const int32_t *off, int n_seg, float *best,
+                         int32_t *best_idx, int64_t *status, hipStream_t s);
+// scratch: 1088 + 8 k bytes
+hipError_t launch_topk(const float *v, int n, int k, int32_t *idx_out, float *val_out, void *scratch, hipStream_t s);
+
 hipError_t launch_fusion(const float *cnn_lat, int lc, const float *sg_lat, int H, const float *w1,
                          const float *b1, int hidden, const float *w2, const float *b2, int n_poses,
                          float *scores, hipStream_t s);

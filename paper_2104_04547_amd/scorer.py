@@ -106,5 +106,23 @@ class Scorer:
     def variants(self, G: int):
         return cfabi.cf_conv_variants(self.ctx, G, len(self.arch.conv))
 
+    def compound_max(self, scores, compound_off):
+        """Best score and pose index per compound segment (device tensors)."""
+        import torch
+        off = compound_off.to(device="cuda", dtype=torch.int32).contiguous()
+        n = off.numel() - 1
+        best = torch.empty(n, dtype=torch.float32, device="cuda")
+        idx = torch.empty(n, dtype=torch.int32, device="cuda")
+        cfabi.cf_compound_max(self.ctx, scores.data_ptr(), scores.numel(), off.data_ptr(), n, best.data_ptr(),
+                              idx.data_ptr(), self._stream())
+        return best, idx
+
+    def top_k(self, values, k: int):
+        import torch
+        idx = torch.empty(k, dtype=torch.int32, device="cuda")
+        val = torch.empty(k, dtype=torch.float32, device="cuda")
+        cfabi.cf_top_k(self.ctx, values.data_ptr(), values.numel(), k, idx.data_ptr(), val.data_ptr(), self._stream())
+        return idx, val
+
     def set_variants(self, G: int, variants):
         cfabi.cf_set_conv_variants(self.ctx, G, list(variants))
