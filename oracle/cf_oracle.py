@@ -260,7 +260,8 @@ def sgcnn_batch(batch, w, arch) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------------
-# Fusion (Coherent Fusion, Sec. 2.2 / 3.3.3, Table V: SELU fusion layers)
+# Fusion heads (Coherent Fusion, Sec. 2.2, Table V; Mid-level and Late Fusion,
+# Sec. 2.1, Table IV)
 # --------------------------------------------------------------------------------
 
 def selu(x):
@@ -268,15 +269,50 @@ def selu(x):
     return np.where(x > 0, SELU_LAMBDA * x, SELU_LAMBDA * SELU_ALPHA * np.expm1(np.minimum(x, 0.0)))
 
 
+def _dense(w, name, x):
+    return np.asarray(w[name + ".w"], np.float64) @ x + np.asarray(w[name + ".b"], np.float64)
+
+
+def fusion_block(z: np.ndarray, w, arch) -> float:
+    """The fusion dense layers (Fig. 1, fusion block; Tables IV-V): n_fusion - 1
+    hidden SELU layers of width fusion_hidden -- with residual fusion layers, each
+    hidden layer after the first adds its own input to its output -- then a linear
+    layer to one pK.  Dropout is the identity at inference."""
+    for l in range(arch.n_fusion - 1):
+        y = selu(_dense(w, "fusion.hidden" if l == 0 else f"fusion.hidden{l}", z))
+        z = y + z if (arch.fusion_residual and l > 0) else y
+    return float(_dense(w, "fusion.out", z)[0])
+
+
 def fusion_head(cnn_lat: np.ndarray, sg_lat: np.ndarray, w, arch) -> float:
-    """Concatenate [cnn latent; sg latent]; optional SELU hidden layer; linear to pK."""
-    z = np.concatenate([np.asarray(cnn_lat, np.float64), np.asarray(sg_lat, np.float64)])
-    if arch.fusion_hidden:
-        z = selu(np.asarray(w["fusion.hidden.w"], np.float64) @ z + np.asarray(w["fusion.hidden.b"], np.float64))
-    return float((np.asarray(w["fusion.out.w"], np.float64) @ z)[0] + np.float64(w["fusion.out.b"][0]))
+    """pK of one pose from its two latents, per the model's fusion form.
+
+    coherent (Sec. 2.2, Table V): fusion block over [cnn; sg].
+    mid (Mid-level Fusion, Sec. 2.1, Table IV): each latent first passes through
+        its own model-specific SELU dense layer (same width); those outputs are
+        concatenated with the raw latents, [u_cnn; u_sg; cnn; sg], and fed to the
+        fusion block.
+    late (Late Fusion, Sec. 2.1): each branch predicts a pK on its own -- the
+        3D-CNN by a linear layer on its latent, the SG-CNN by its ReLU dense layers
+        and a linear layer -- and the score is the unweighted mean of the two.
+    """
+    cnn = np.asarray(cnn_lat, np.float64)
+    sg = np.asarray(sg_lat, np.float64)
+    if arch.head == "late":
+        pk_cnn = _dense(w, "late.cnn_out", cnn)[0]
+        x = sg
+        for j in range(len(arch.sg_dense)):
+            x = np.maximum(_dense(w, f"late.sg_dense{j}", x), 0.0)
+        pk_sg = _dense(w, "late.sg_out", x)[0]
+        return float(late_fusion(pk_cnn, pk_sg))
+    if arch.head == "mid":
+        z = np.concatenate([selu(_dense(w, "mid.cnn", cnn)), selu(_dense(w, "mid.sg", sg)), cnn, sg])
+    else:
+        z = np.concatenate([cnn, sg])
+    return fusion_block(z, w, arch)
 
 
-def late_fusion(pk_cnn: np.ndarray, pk_sg: np.ndarray) -> np.ndarray:
+def late_fusion(pk_cnn, pk_sg):
     """Late Fusion (Sec. 2.1): unweighted arithmetic mean of the two heads' pK."""
     return (np.asarray(pk_cnn, np.float64) + np.asarray(pk_sg, np.float64)) / 2.0
 

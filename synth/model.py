@@ -73,7 +73,25 @@ class ModelArch:
     K_n: int                # non-covalent propagation rounds
     r_cov_u: int            # covalent cutoff, units of 2^-10 A
     r_nc_u: int             # non-covalent cutoff, units of 2^-10 A
-    fusion_hidden: int      # 0: linear fusion head; else one SELU hidden layer
+    fusion_hidden: int      # width of the fusion block's hidden SELU layers (0: none)
+    fusion_layers: int = 0  # dense layers of the fusion block incl. the output layer
+                            # (0: one hidden layer if fusion_hidden, else linear)
+    fusion_residual: bool = False   # hidden layers after the first add their input
+    head: str = "coherent"  # "coherent" / "mid": fusion block over the latents
+                            # ("mid" first passes each latent through its own SELU
+                            # dense layer and concatenates those with the raw
+                            # latents); "late": each branch predicts its own pK
+                            # and the score is their mean
+    sg_dense: Tuple[int, ...] = ()  # late head: SG-CNN dense layers (ReLU) before its output
+
+    @property
+    def n_fusion(self) -> int:
+        return self.fusion_layers if self.fusion_layers else (2 if self.fusion_hidden else 1)
+
+    @property
+    def head_outputs(self) -> Tuple[str, ...]:
+        """Parameter prefixes of the layers that produce a pK (calibrated)."""
+        return ("late.cnn_out", "late.sg_out") if self.head == "late" else ("fusion.out",)
 
     @property
     def c_last(self) -> int:
@@ -85,7 +103,7 @@ class ModelArch:
 
     @property
     def fusion_in(self) -> int:
-        return self.cnn_latent + self.H
+        return (2 if self.head == "mid" else 1) * (self.cnn_latent + self.H)
 
     def out_dims(self, G: int) -> List[int]:
         dims = [G]
@@ -114,6 +132,15 @@ ARCHS: Dict[str, ModelArch] = {
                        (64, 64, 7, 1, -1), (64, 64, 7, 1, 3), (64, 128, 7, 2, -1)),
                       True, 10, 64, 3, 3, R_COV_U, R_NC_U, 64),
 }
+# The same trunk (identical conv / SG-CNN weights: head parameters are drawn
+# last) under the two earlier fusion forms the paper compares against (Sec. 2.1,
+# Sec. 3.3.2, Table IV): Mid-level Fusion with model-specific layers and five
+# residual fusion layers, and Late Fusion with the SG-CNN's own dense layers
+# (gather width reduced by 1.5, then by 2).
+ARCHS["full_mid"] = dataclasses.replace(ARCHS["full"], name="full_mid", head="mid", fusion_layers=5,
+                                        fusion_residual=True)
+ARCHS["full_late"] = dataclasses.replace(ARCHS["full"], name="full_late", head="late", fusion_hidden=0,
+                                         sg_dense=(42, 21))
 
 # Workloads.  mode 0: n_lig ~ U{lim0..lim1}, n_pocket ~ U{lim2..lim3};
 # mode 1: total ~ log-U[lim0, lim1] split into ligand / pocket.
@@ -153,12 +180,30 @@ def param_shapes(arch: ModelArch) -> List[Tuple[str, Tuple[int, ...], str]]:
     out.append(("sg.gate.b", (H,), "bias"))
     out.append(("sg.val.w", (H, H), "he"))
     out.append(("sg.val.b", (H,), "bias"))
-    if arch.fusion_hidden:
-        out.append(("fusion.hidden.w", (arch.fusion_hidden, arch.fusion_in), "he"))
-        out.append(("fusion.hidden.b", (arch.fusion_hidden,), "bias"))
-        out.append(("fusion.out.w", (1, arch.fusion_hidden), "he"))
-    else:
-        out.append(("fusion.out.w", (1, arch.fusion_in), "he"))
+    lc = arch.cnn_latent
+    if arch.head == "late":
+        out.append(("late.cnn_out.w", (1, lc), "he"))
+        out.append(("late.cnn_out.b", (1,), "bias"))
+        prev = H
+        for j, d in enumerate(arch.sg_dense):
+            out.append((f"late.sg_dense{j}.w", (d, prev), "he"))
+            out.append((f"late.sg_dense{j}.b", (d,), "bias"))
+            prev = d
+        out.append(("late.sg_out.w", (1, prev), "he"))
+        out.append(("late.sg_out.b", (1,), "bias"))
+        return out
+    if arch.head == "mid":
+        out.append(("mid.cnn.w", (lc, lc), "he"))
+        out.append(("mid.cnn.b", (lc,), "bias"))
+        out.append(("mid.sg.w", (H, H), "he"))
+        out.append(("mid.sg.b", (H,), "bias"))
+    prev = arch.fusion_in
+    for l in range(arch.n_fusion - 1):
+        name = "fusion.hidden" if l == 0 else f"fusion.hidden{l}"
+        out.append((f"{name}.w", (arch.fusion_hidden, prev), "he"))
+        out.append((f"{name}.b", (arch.fusion_hidden,), "bias"))
+        prev = arch.fusion_hidden
+    out.append(("fusion.out.w", (1, prev), "he"))
     out.append(("fusion.out.b", (1,), "bias"))
     return out
 
@@ -197,6 +242,11 @@ def apply_calibration(w: Dict[str, np.ndarray], scale: float, shift: float) -> D
     test fixtures and applied here to the last layer only.
     """
     out = dict(w)
-    out["fusion.out.w"] = (w["fusion.out.w"].astype(np.float64) * scale).astype(np.float32)
-    out["fusion.out.b"] = (w["fusion.out.b"].astype(np.float64) * scale + shift).astype(np.float32)
+    for o in _outputs_of(w):   # Late Fusion: both branch outputs, so their mean maps the same way
+        out[o + ".w"] = (w[o + ".w"].astype(np.float64) * scale).astype(np.float32)
+        out[o + ".b"] = (w[o + ".b"].astype(np.float64) * scale + shift).astype(np.float32)
     return out
+
+
+def _outputs_of(w: Dict[str, np.ndarray]) -> Tuple[str, ...]:
+    return ("late.cnn_out", "late.sg_out") if "late.cnn_out.w" in w else ("fusion.out",)

@@ -13,6 +13,10 @@ the HIP path.  Outputs (JSON, floats written with repr so they round-trip):
 Usage:  python tests/golden/make_golden.py c1 24 64
         python tests/golden/make_golden.py c2 48 64 --calibrate
         python tests/golden/make_golden.py c4 32 8
+        python tests/golden/make_golden.py c2 48 64 --head-arch full_mid
+            (calibration only, for an architecture that shares the config's trunk
+             -- same conv / SG-CNN weights, another fusion head -- computed from
+             the stored oracle latents of that config)
 """
 import argparse
 import json
@@ -52,11 +56,16 @@ def main():
     ap.add_argument("n", type=int)
     ap.add_argument("--calibrate", action="store_true")
     ap.add_argument("--workers", type=int, default=os.cpu_count())
+    ap.add_argument("--head-arch", default=None)
     a = ap.parse_args()
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     import numpy as np
     import oracle
     import synth
+
+    if a.head_arch:
+        calibrate_head(a.cfg, a.G, a.head_arch)
+        return
 
     t0 = time.time()
     with get_context("spawn").Pool(a.workers) as pool:
@@ -84,6 +93,27 @@ def main():
     path = os.path.join(HERE, f"{a.cfg}_G{a.G}_oracle.json")
     json.dump(out, open(path, "w"))
     print(f"wrote {path} ({a.n} poses) in {time.time() - t0:.1f}s")
+
+
+def calibrate_head(cfg, G, head_arch):
+    import numpy as np
+    import oracle
+    import synth
+    base = synth.ARCHS[synth.CONFIGS[cfg]["arch"]]
+    arch = synth.ARCHS[head_arch]
+    wb, w = synth.make_weights(base), synth.make_weights(arch)
+    trunk = [k for k in wb if not k.startswith("fusion.")]
+    assert all(k in w and np.array_equal(wb[k], w[k]) for k in trunk), "architecture does not share the trunk"
+    rows = json.load(open(os.path.join(HERE, f"{cfg}_G{G}_oracle.json")))["poses"][:64]
+    assert len(rows) == 64
+    raw = np.array([oracle.fusion_head(np.array(r["cnn_lat"]), np.array(r["sg_lat"]), w, arch) for r in rows])
+    calib_path = os.path.join(HERE, "calib.json")
+    calib = json.load(open(calib_path))
+    scale = 1.5 / raw.std()
+    calib[head_arch] = dict(scale=float(scale), shift=float(6.0 - raw.mean() * scale), raw_mean=float(raw.mean()),
+                            raw_std=float(raw.std()), source=f"{cfg} poses 0..63, G={G}, stored oracle latents")
+    json.dump(calib, open(calib_path, "w"), indent=1)
+    print(f"calibrated {head_arch}: {calib[head_arch]}")
 
 
 if __name__ == "__main__":
