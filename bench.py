@@ -98,6 +98,22 @@ def cnn_latent_error(scorer, batch, gd, G, n):
     return float(np.abs(lat - want).max() / np.abs(want).max())
 
 
+def conv_traffic(kernel):
+    """HBM bytes per launch of the dominant conv kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by a plain copy's
+    reading), or None when there is none for this kernel or the conv source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "conv_traffic.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2104_04547_amd", "csrc", "cf_conv.hip")
+    if t.get("kernel") != kernel or t.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return round(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"], 0)
+
+
 def cpu_baseline(batch, arch, w, G, n):
     """The FP64 oracle as it stands, on the first n poses, on this host's cores."""
     import numpy as np
@@ -116,6 +132,40 @@ def cpu_baseline(batch, arch, w, G, n):
                 sample=f"first {n} of the workload's poses, full path per pose (splat, conv stack, "
                        f"graphs, SG-CNN, fusion) in float64 numpy; {dt:.1f} s",
                 seconds=dt)
+
+
+def batching_leg(arch, w, n_poses, steps):
+    """Batching form: ragged poses whose total atom counts are log-uniform in
+    [200, 1500], packed CSR-style and scored 512 per launch in the precision form,
+    with the conv variants autotuned per grid size (32^3, 48^3, 64^3)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2104_04547_amd import Scorer, cfabi
+    t0 = time.perf_counter()
+    batch = synth.make_poses("c4", n_poses)
+    log(f"batching: generated {n_poses} poses ({batch.n_atoms} atoms) in {time.perf_counter() - t0:.1f}s")
+    db = cfabi.DeviceBatch.from_pose_batch(batch)
+    out = torch.empty(n_poses, dtype=torch.float32, device="cuda")
+    s = Scorer(arch, w, "bf16")
+    res = {}
+    try:
+        for G in (32, 48, 64):
+            t0 = time.perf_counter()
+            v = s.autotune(G, 512)
+            tune_s = time.perf_counter() - t0
+            sec, _ = time_steps(s, db, G, steps, 1, out)
+            r = dict(poses_per_s=round(n_poses / sec, 2), ms_per_step=round(sec * 1e3, 3), conv_variants=v,
+                     autotune_s=round(tune_s, 2),
+                     conv_tflops=round(arch.flops_per_pose(G) * n_poses / sec / 1e12, 1))
+            gd = load_golden("c4", G)
+            if gd is not None:
+                r["error"] = error_stats(out.cpu().numpy().astype(np.float64), gd, min(len(gd["poses"]), n_poses))
+            res[f"G{G}"] = r
+            log(f"batching G={G}: {r['poses_per_s']:.1f} poses/s, variants {v}, tuned in {tune_s:.1f}s")
+    finally:
+        s.close()
+    return dict(poses=n_poses, atoms=int(batch.n_atoms), steps=steps, **res)
 
 
 def serve_leg(arch, w, res, seconds):
@@ -174,6 +224,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=25.0)
+    ap.add_argument("--batch-poses", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 10 device copies of MIB MiB (calibrates HBM byte counters) and exit")
     ap.add_argument("--json-out", default="")
     a = ap.parse_args()
 
@@ -186,6 +241,16 @@ def main():
     import torch
     import synth
     from paper_2104_04547_amd import Scorer, cfabi
+
+    if a.copy_probe:
+        n = a.copy_probe << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 10 copies of {n} bytes")
+        return
 
     cfg = "c2"
     G = a.G
@@ -241,6 +306,10 @@ def main():
                          **({"gbs": v["bytes"] / (v["total_ms"] * 1e-3) / 1e9} if v["bytes"] and not v["flop"] else {}))
                  for k, v in sorted(st.items())}
 
+    batching = None
+    if not a.no_batching:
+        batching = batching_leg(arch, w, a.batch_poses, a.batch_steps)
+
     serving = None
     if not a.no_serve and "fp32" in res:
         serving = serve_leg(arch, w, res, a.serve_seconds)
@@ -273,7 +342,7 @@ def main():
         },
         "roofline": {
             "bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": conv_traffic(dom),
             "avg_launch_ms": round(avg_ms, 4), "flop_per_launch": flop_per_launch,
             "conv_stack_tflops": round(conv_flop / (conv_ms * 1e-3) / 1e12, 2),
             "conv_share_of_step": round(conv_ms / total_ms, 4),
@@ -295,6 +364,8 @@ def main():
                               "dominant_kernel": fdom, "achieved_tflops": round(f_ach, 2),
                               "frac_of_fp32_peak": round(f_ach / PEAK_FP32_TFLOPS, 4)}
         line["speedup_bf16_vs_fp32"] = round(bf["poses_per_s"] / f["poses_per_s"], 3)
+    if batching is not None:
+        line["batching"] = batching
     if serving is not None:
         line["serving"] = serving
     if a.json_out:

@@ -66,6 +66,13 @@ typedef enum {
 #define CF_MAX_POSE_ATOMS 4096
 #define CF_MODEL_MAGIC 0x314D4643u /* "CFM1" */
 
+/* Fusion head forms (Sec. 2.1-2.2; Tables IV-V).  Coherent: SELU fusion layers
+ * over the concatenated latents.  Mid-level: each latent first passes through its
+ * own SELU dense layer, whose output joins the raw latents before the fusion
+ * layers (optionally residual).  Late: each branch predicts a pK on its own and
+ * the score is their unweighted mean.  Dropout is the identity at inference. */
+typedef enum { CF_HEAD_COHERENT = 0, CF_HEAD_MID = 1, CF_HEAD_LATE = 2 } cf_head_kind;
+
 typedef struct cf_ctx cf_ctx;
 
 /* A ragged batch of poses, packed CSR-style: atoms of pose p are rows
@@ -99,8 +106,15 @@ typedef struct {
  *       K rounds, then GRU w_ih [3H][H], w_hh [3H][H], b_ih [3H], b_hh [3H]
  *       (gate rows stacked r, z, n);
  *       readout gate W [H][H+19], b [H]; readout value W [H][H], b [H];
- *   fusion: if fusion_hidden: W [fusion_hidden][latent_cnn + H], b [fusion_hidden];
- *       output W [1][fusion_hidden or latent_cnn + H], b [1].
+ *   head CF_HEAD_LATE: 3D-CNN output W [1][latent_cnn], b [1]; for each
+ *       sg_dense[j] > 0: W [sg_dense[j]][previous width], b [sg_dense[j]];
+ *       SG-CNN output W [1][last width], b [1];
+ *   head CF_HEAD_MID: model-specific W [latent_cnn][latent_cnn], b [latent_cnn],
+ *       then W [H][H], b [H]; then the fusion block below, its input being
+ *       [specific cnn; specific sg; cnn latent; sg latent] (2 (latent_cnn + H));
+ *   head CF_HEAD_COHERENT: the fusion block over [cnn latent; sg latent];
+ *   fusion block: fusion_layers - 1 hidden layers W [fusion_hidden][input width],
+ *       b [fusion_hidden], then output W [1][fusion_hidden or input width], b [1].
  * Conv i reads tensor t_i and writes t_{i+1} (t_0 = voxel grid); res_src >= 0
  * adds t_{res_src} before the ReLU of conv i. */
 typedef struct {
@@ -114,7 +128,13 @@ typedef struct {
   int32_t K_c, K_n;      /* covalent / non-covalent propagation rounds (<= 8 each) */
   int32_t r_cov_u;       /* covalent cutoff, 2^-10 A */
   int32_t r_nc_u;        /* non-covalent cutoff, 2^-10 A */
-  int32_t fusion_hidden; /* 0: linear fusion head; else width of one SELU layer */
+  int32_t fusion_hidden; /* width of the fusion block's hidden SELU layers */
+  int32_t head;          /* cf_head_kind */
+  int32_t fusion_layers; /* dense layers of the fusion block incl. the output, 1..8;
+                            > 1 requires fusion_hidden > 0 (unused by CF_HEAD_LATE) */
+  int32_t fusion_residual; /* 1: hidden layers after the first add their input */
+  int32_t sg_dense[2];   /* CF_HEAD_LATE: SG-CNN dense (ReLU) widths before its
+                            output, 0 = absent (a 0 ends the list) */
 } cf_model_desc;
 
 /* Create a scoring context on the current device.  Copies the weights (the blob
@@ -162,10 +182,17 @@ int cf_cnn3d_fwd(cf_ctx *ctx, const void *grid, int32_t n_poses, int G, float *c
 int cf_sgcnn_fwd(cf_ctx *ctx, const cf_pose_batch *batch, const cf_csr *cov, const cf_csr *nc,
                  float *sg_latent, void *stream);
 
+/* Fusion head alone (Eq. 1; Sec. 2.1-2.2, Tables IV-V, per the model's
+ * cf_head_kind): one pK per pose from its two latents.  cnn_latent: device
+ * [P][latent_cnn] float32; sg_latent: device [P][H] float32; scores: device [P]
+ * float32.  Computed in float32 in both precision forms. */
+int cf_fusion_fwd(cf_ctx *ctx, const float *cnn_latent, const float *sg_latent, int32_t n_poses, float *scores,
+                  void *stream);
+
 /* Whole path: centres (unless given), voxelisation, 3D-CNN, neighbour lists,
- * SG-CNN and the Coherent Fusion head (Sec. 2.2, 3.3.3, Table V: SELU fusion
- * layers, inference without dropout).  scores: device [P] float32 pK, in batch
- * order.  Uses context-owned scratch; poses are processed in chunks. */
+ * SG-CNN and the model's fusion head (Coherent Fusion by default, Sec. 2.2,
+ * 3.3.3, Table V; inference without dropout).  scores: device [P] float32 pK, in
+ * batch order.  Uses context-owned scratch; poses are processed in chunks. */
 int cf_score_poses(cf_ctx *ctx, const cf_pose_batch *batch, int G, float *scores, void *stream);
 
 /* Synchronise `stream`, then report and clear the context's device status word:

@@ -29,7 +29,10 @@ EXPORTS = ["cf_create", "cf_destroy", "cf_pose_centers", "cf_voxelize", "cf_buil
            "cf_autotune", "cf_conv_variants", "cf_timing_enable", "cf_timing_read",
            "cf_engine_create", "cf_engine_submit", "cf_engine_poll", "cf_engine_wait_all", "cf_engine_info",
            "cf_engine_last_error", "cf_engine_destroy", "cf_set_conv_variants", "cf_conv_variant_count",
-           "cf_conv_variant_name", "cf_compound_max", "cf_top_k"]
+           "cf_conv_variant_name", "cf_compound_max", "cf_top_k", "cf_fusion_fwd"]
+
+
+HEAD_KINDS = {"coherent": 0, "mid": 1, "late": 2}   # cf_head_kind
 
 
 class CfError(RuntimeError):
@@ -52,7 +55,9 @@ class cf_model_desc(ctypes.Structure):
     _fields_ = [("magic", ctypes.c_uint32), ("n_ch", ctypes.c_int32), ("n_conv", ctypes.c_int32),
                 ("conv", (ctypes.c_int32 * 5) * 8), ("bn", ctypes.c_int32), ("cnn_dense", ctypes.c_int32),
                 ("H", ctypes.c_int32), ("K_c", ctypes.c_int32), ("K_n", ctypes.c_int32),
-                ("r_cov_u", ctypes.c_int32), ("r_nc_u", ctypes.c_int32), ("fusion_hidden", ctypes.c_int32)]
+                ("r_cov_u", ctypes.c_int32), ("r_nc_u", ctypes.c_int32), ("fusion_hidden", ctypes.c_int32),
+                ("head", ctypes.c_int32), ("fusion_layers", ctypes.c_int32), ("fusion_residual", ctypes.c_int32),
+                ("sg_dense", ctypes.c_int32 * 2)]
 
 
 class cf_kernel_stat(ctypes.Structure):
@@ -140,6 +145,13 @@ def model_desc(arch) -> cf_model_desc:
     d.H, d.K_c, d.K_n = arch.H, arch.K_c, arch.K_n
     d.r_cov_u, d.r_nc_u = arch.r_cov_u, arch.r_nc_u
     d.fusion_hidden = arch.fusion_hidden
+    d.head = HEAD_KINDS[arch.head]
+    d.fusion_layers = arch.n_fusion
+    d.fusion_residual = int(arch.fusion_residual)
+    if len(arch.sg_dense) > 2:
+        raise ValueError("at most two SG-CNN dense layers")
+    for j, v in enumerate(arch.sg_dense):
+        d.sg_dense[j] = int(v)
     return d
 
 
@@ -157,10 +169,17 @@ def blob_param_order(arch):
         names += [f"sg.{stage}.msg{t}.w" for t in range(K)]
         names += [f"sg.{stage}.gru.w_ih", f"sg.{stage}.gru.w_hh", f"sg.{stage}.gru.b_ih", f"sg.{stage}.gru.b_hh"]
     names += ["sg.gate.w", "sg.gate.b", "sg.val.w", "sg.val.b"]
-    if arch.fusion_hidden:
-        names += ["fusion.hidden.w", "fusion.hidden.b"]
-    names += ["fusion.out.w", "fusion.out.b"]
-    return names
+    if arch.head == "late":
+        names += ["late.cnn_out.w", "late.cnn_out.b"]
+        for j in range(len(arch.sg_dense)):
+            names += [f"late.sg_dense{j}.w", f"late.sg_dense{j}.b"]
+        return names + ["late.sg_out.w", "late.sg_out.b"]
+    if arch.head == "mid":
+        names += ["mid.cnn.w", "mid.cnn.b", "mid.sg.w", "mid.sg.b"]
+    for l in range(arch.n_fusion - 1):
+        n = "fusion.hidden" if l == 0 else f"fusion.hidden{l}"
+        names += [n + ".w", n + ".b"]
+    return names + ["fusion.out.w", "fusion.out.b"]
 
 
 def pack_model(arch, params: Dict[str, np.ndarray]) -> bytes:
@@ -206,6 +225,10 @@ def cf_cnn3d_fwd(ctx, grid_ptr: int, n_poses: int, G: int, cnn_latent_ptr: int, 
 def cf_sgcnn_fwd(ctx, batch: cf_pose_batch, cov: cf_csr, nc: cf_csr, sg_latent_ptr: int, stream: int = 0):
     _check(load().cf_sgcnn_fwd(ctx, ctypes.byref(batch), ctypes.byref(cov), ctypes.byref(nc), sg_latent_ptr,
                                stream))
+
+
+def cf_fusion_fwd(ctx, cnn_latent_ptr: int, sg_latent_ptr: int, n_poses: int, scores_ptr: int, stream: int = 0):
+    _check(load().cf_fusion_fwd(ctx, cnn_latent_ptr, sg_latent_ptr, n_poses, scores_ptr, stream))
 
 
 def cf_score_poses(ctx, batch: cf_pose_batch, G: int, scores_ptr: int, stream: int = 0):

@@ -53,7 +53,8 @@ struct cf_ctx {
   int c_last = 0;
   float *dense_w = nullptr, *dense_b = nullptr;
   cf::SgWeights sg{};
-  float *fus_w1 = nullptr, *fus_b1 = nullptr, *fus_w2 = nullptr, *fus_b2 = nullptr;
+  cf::HeadProgram head{};  // fusion head compiled to dense layers
+  float *head_prm = nullptr;
   int64_t *status = nullptr;
   std::vector<void *> weight_allocs;
 
@@ -327,6 +328,76 @@ int upload_split(cf_ctx *c, const float *W, int N, int K, const bf16_t **hi, con
   return CF_OK;
 }
 
+static_assert(sizeof(cf_model_desc) == 4 * (3 + 40 + 8 + 5), "cf_model_desc layout");
+
+// Compile the model's fusion head (Coherent, Mid-level or Late Fusion) into a
+// list of dense layers over the per-pose buffer [cnn latent | sg latent | ...]
+// and upload its parameters as one array.
+int build_head(cf_ctx *c, BlobReader &R) {
+  const cf_model_desc &d = c->desc;
+  const int lc = c->lc, H = d.H;
+  cf::HeadProgram &hp = c->head;
+  hp = cf::HeadProgram{};
+  std::vector<float> prm;
+  int top = lc + H;  // next free slot of the buffer
+  // one dense layer reading [slice (src, n_in) ; slice (src1, n1)], writing a new slice
+  auto dense = [&](int src, int n_in, int n_out, int act, int res, const char *what, int src1 = 0,
+                   int n1 = 0) -> int {
+    if (hp.n_ops >= cf::kHeadMaxOps) return fail(CF_ERR_UNSUPPORTED, "fusion head has too many layers");
+    if (n_out < 1 || top + n_out > cf::kHeadBuf) return fail(CF_ERR_UNSUPPORTED, "fusion head layers too wide");
+    n_in += n1;
+    const float *w = R.take((size_t)n_out * n_in), *b = R.take(n_out);
+    if (!w || !b) return fail(CF_ERR_INVALID_ARG, std::string("blob truncated (") + what + ")");
+    cf::HeadOp &op = hp.op[hp.n_ops++];
+    op = cf::HeadOp{src, n_in - n1, src1, n1, top, n_out, act, res, (int)prm.size(), 0};
+    prm.insert(prm.end(), w, w + (size_t)n_out * n_in);
+    op.b = (int)prm.size();
+    prm.insert(prm.end(), b, b + n_out);
+    top += n_out;
+    return CF_OK;
+  };
+  int rc;
+  if (d.head == CF_HEAD_LATE) {
+    if ((rc = dense(0, lc, 1, cf::kActNone, -1, "3D-CNN output"))) return rc;
+    const int out_cnn = hp.op[hp.n_ops - 1].dst;
+    int src = lc, width = H;
+    for (int j = 0; j < 2 && d.sg_dense[j] > 0; ++j) {
+      if ((rc = dense(src, width, d.sg_dense[j], cf::kActRelu, -1, "SG-CNN dense"))) return rc;
+      src = hp.op[hp.n_ops - 1].dst;
+      width = d.sg_dense[j];
+    }
+    if ((rc = dense(src, width, 1, cf::kActNone, -1, "SG-CNN output"))) return rc;
+    hp.n_out = 2;
+    hp.out_slot[0] = out_cnn;
+    hp.out_slot[1] = hp.op[hp.n_ops - 1].dst;
+    hp.out_scale = 0.5f;
+  } else {
+    // the first fusion layer reads [u_cnn | u_sg] (Mid-level: the model-specific
+    // outputs, written next to each other) followed by the raw [cnn | sg]
+    int src = 0, width = lc + H, src1 = 0, n1 = 0;
+    if (d.head == CF_HEAD_MID) {
+      if ((rc = dense(0, lc, lc, cf::kActSelu, -1, "model-specific 3D-CNN"))) return rc;
+      const int u0 = hp.op[hp.n_ops - 1].dst;
+      if ((rc = dense(lc, H, H, cf::kActSelu, -1, "model-specific SG-CNN"))) return rc;
+      src = u0;
+      src1 = 0;
+      n1 = lc + H;
+    }
+    for (int l = 0; l + 1 < d.fusion_layers; ++l) {
+      const int res = (d.fusion_residual && l > 0) ? src : -1;
+      if ((rc = dense(src, width, d.fusion_hidden, cf::kActSelu, res, "fusion layer", src1, n1))) return rc;
+      src = hp.op[hp.n_ops - 1].dst;
+      width = d.fusion_hidden;
+      n1 = 0;
+    }
+    if ((rc = dense(src, width, 1, cf::kActNone, -1, "fusion output", src1, n1))) return rc;
+    hp.n_out = 1;
+    hp.out_slot[0] = hp.op[hp.n_ops - 1].dst;
+    hp.out_scale = 1.0f;
+  }
+  return upload_f(c, &c->head_prm, prm.data(), prm.size());
+}
+
 int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
   if (!blob || nbytes < sizeof(cf_model_desc)) return fail(CF_ERR_INVALID_ARG, "model blob too small");
   memcpy(&c->desc, blob, sizeof(cf_model_desc));
@@ -339,8 +410,15 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
   if (d.r_cov_u <= 0 || d.r_nc_u <= 0 || d.r_cov_u > 65536 || d.r_nc_u > 65536)
     return fail(CF_ERR_INVALID_ARG, "cutoffs must be 1..65536 u");
   if (d.r_cov_u > d.r_nc_u) return fail(CF_ERR_UNSUPPORTED, "covalent cutoff must not exceed the non-covalent one");
-  if (d.cnn_dense < 0 || d.cnn_dense > 256 || d.fusion_hidden < 0 || d.fusion_hidden > 4096)
+  if (d.cnn_dense < 0 || d.cnn_dense > 256 || d.fusion_hidden < 0 || d.fusion_hidden > 512)
     return fail(CF_ERR_INVALID_ARG, "bad dense sizes");
+  if (d.head < CF_HEAD_COHERENT || d.head > CF_HEAD_LATE) return fail(CF_ERR_INVALID_ARG, "unknown head kind");
+  if (d.head != CF_HEAD_LATE &&
+      (d.fusion_layers < 1 || d.fusion_layers > 8 || (d.fusion_layers > 1) != (d.fusion_hidden > 0)))
+    return fail(CF_ERR_INVALID_ARG, "fusion_layers must be 1..8, and > 1 exactly when fusion_hidden > 0");
+  if (d.fusion_residual != 0 && d.fusion_residual != 1) return fail(CF_ERR_INVALID_ARG, "fusion_residual must be 0 or 1");
+  if (d.sg_dense[0] < 0 || d.sg_dense[1] < 0 || d.sg_dense[0] > 512 || d.sg_dense[1] > 512)
+    return fail(CF_ERR_INVALID_ARG, "bad SG-CNN dense sizes");
   BlobReader R{reinterpret_cast<const float *>(reinterpret_cast<const char *>(blob) + sizeof(cf_model_desc)),
                (nbytes - sizeof(cf_model_desc)) / sizeof(float)};
   if ((nbytes - sizeof(cf_model_desc)) % sizeof(float)) return fail(CF_ERR_INVALID_ARG, "blob size not float-aligned");
@@ -484,22 +562,7 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     if ((rc = upload_f(c, &p, vb, H))) return rc;
     S.val_b = p;
   }
-  const int nin = c->lc + H;
-  if (nin > 512) return fail(CF_ERR_UNSUPPORTED, "fusion input wider than 512");
-  if (d.fusion_hidden) {
-    const float *w1 = R.take((size_t)d.fusion_hidden * nin), *b1 = R.take(d.fusion_hidden);
-    const float *w2 = R.take(d.fusion_hidden), *b2 = R.take(1);
-    if (!w1 || !b1 || !w2 || !b2) return fail(CF_ERR_INVALID_ARG, "blob truncated (fusion)");
-    if ((rc = upload_f(c, &c->fus_w1, w1, (size_t)d.fusion_hidden * nin))) return rc;
-    if ((rc = upload_f(c, &c->fus_b1, b1, d.fusion_hidden))) return rc;
-    if ((rc = upload_f(c, &c->fus_w2, w2, d.fusion_hidden))) return rc;
-    if ((rc = upload_f(c, &c->fus_b2, b2, 1))) return rc;
-  } else {
-    const float *w2 = R.take(nin), *b2 = R.take(1);
-    if (!w2 || !b2) return fail(CF_ERR_INVALID_ARG, "blob truncated (fusion)");
-    if ((rc = upload_f(c, &c->fus_w2, w2, nin))) return rc;
-    if ((rc = upload_f(c, &c->fus_b2, b2, 1))) return rc;
-  }
+  if ((rc = build_head(c, R))) return rc;
   if (R.left != 0) return fail(CF_ERR_INVALID_ARG, "blob has trailing data");
   c->n_params = (int64_t)total_floats;
   return CF_OK;
@@ -661,6 +724,15 @@ int cf_sgcnn_fwd(cf_ctx *c, const cf_pose_batch *b, const cf_csr *cov, const cf_
   return CF_OK;
 }
 
+int cf_fusion_fwd(cf_ctx *c, const float *cnn_latent, const float *sg_latent, int32_t n_poses, float *scores,
+                  void *stream) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  if (!cnn_latent || !sg_latent || !scores || n_poses < 1) return fail(CF_ERR_INVALID_ARG, "bad arguments");
+  CF_HIP(cf::launch_head(cnn_latent, c->lc, sg_latent, c->desc.H, c->head_prm, c->head, n_poses, scores,
+                         (hipStream_t)stream));
+  return CF_OK;
+}
+
 int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void *stream) {
   if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
   int rc = validate_batch(b);
@@ -707,8 +779,8 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
       tend(c, s, e, "sgcnn", atoms * (2.0 * CF_NCH * Hd + rounds * 2.0 * (Hd * Hd + 6.0 * Hd * Hd)), atoms * 4.0 * CF_NCH);
     }
     e = tbegin(c, s);
-    CF_HIP(cf::launch_fusion((float *)c->cnn_lat.p, c->lc, (float *)c->sg_lat.p, H, c->fus_w1, c->fus_b1,
-                             c->desc.fusion_hidden, c->fus_w2, c->fus_b2, np, scores + p0, s));
+    CF_HIP(cf::launch_head((float *)c->cnn_lat.p, c->lc, (float *)c->sg_lat.p, H, c->head_prm, c->head, np,
+                           scores + p0, s));
     tend(c, s, e, "fusion", 0.0, 0.0);
   }
   return CF_OK;

@@ -542,6 +542,8 @@ const Variant kVariants[] = {
     CF_VARIANT8(5, 1, 8, 8, 8, 4, 32),  // 19
     CF_VARIANT8(7, 2, 8, 8, 8, 4, 64),  // 20: stride-2 first layer, 512-row tile
     CF_VARIANT8(7, 1, 8, 8, 8, 8, 64),  // 21
+    CF_VARIANT8(7, 2, 4, 4, 12, 6, 128), // 22: 12^3 outputs of a 24^3 input in 9 whole tiles
+    CF_VARIANT8(7, 2, 4, 4, 12, 3, 128), // 23
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -562,7 +564,7 @@ int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
   (void)D_in;
   // measured on MI355X at 48^3 (bf16: tap pairs for stride 1 and the 128-column
   // stride-2 layer; fp32 has no tap-pair kernel)
-  const int pref[] = {12, 17, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 19, 20, 21};
+  const int pref[] = {12, 17, 20, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 19, 21, 22, 23};
   for (int v : pref)
     if (conv_variant_ok(v, L, bf16)) return v;
   return -1;

@@ -1,10 +1,14 @@
 // Global average pooling + dense head of the 3D-CNN, and the fusion head.
 //
 // Pooling and the CNN dense layer close the 3D-CNN (Sec. 3.3.1, Table III: dense
-// nodes); the fusion head concatenates the two latents and applies the fusion
-// dense layers with SELU (Coherent Fusion, Sec. 2.2 / 3.3.3, Table V) to give one
-// pK (Eq. 1).  Inference applies no dropout.  Reductions run in a fixed order,
-// so a pose's result does not depend on the batch it is scored in.
+// nodes).  The fusion head turns the two latents into one pK (Eq. 1) in any of the
+// paper's three forms: Coherent Fusion (concatenation + SELU fusion layers, Sec.
+// 2.2, Table V), Mid-level Fusion (model-specific SELU layers whose outputs join
+// the raw latents, residual fusion layers, Sec. 2.1, Table IV) and Late Fusion
+// (the mean of the two branches' own predictions, Sec. 2.1).  The host compiles
+// the model's head into a short list of dense layers that one kernel runs.
+// Inference applies no dropout.  Reductions run in a fixed order, so a pose's
+// result does not depend on the batch it is scored in.
 #include "cf_internal.h"
 
 namespace cf {
@@ -52,31 +56,36 @@ __global__ __launch_bounds__(256) void k_pool_dense(const T *__restrict__ act, i
 
 __device__ inline float selu(float x) { return x > 0.f ? kSeluLambda * x : kSeluLambda * kSeluAlpha * expm1f(x); }
 
-// One wavefront per pose.
-__global__ __launch_bounds__(64) void k_fusion(const float *__restrict__ cnn, int lc, const float *__restrict__ sg,
-                                               int H, const float *__restrict__ w1, const float *__restrict__ b1,
-                                               int hidden, const float *__restrict__ w2,
-                                               const float *__restrict__ b2, float *__restrict__ scores) {
-  __shared__ float z[512];
+// One wavefront per pose; the feature buffer lives in LDS.
+__global__ __launch_bounds__(64) void k_head(const float *__restrict__ cnn, int lc, const float *__restrict__ sg,
+                                             int H, const float *__restrict__ prm, HeadProgram hp,
+                                             float *__restrict__ scores) {
+  __shared__ float z[kHeadBuf];
   const int pose = blockIdx.x;
   const int lane = threadIdx.x;
-  const int nin = lc + H;
-  for (int k = lane; k < nin; k += 64)
+  for (int k = lane; k < lc + H; k += 64)
     z[k] = k < lc ? cnn[(int64_t)pose * lc + k] : sg[(int64_t)pose * H + (k - lc)];
   __syncthreads();
-  float part = 0.f;
-  if (hidden > 0) {
-    for (int o = lane; o < hidden; o += 64) {
-      float acc = b1[o];
-      for (int k = 0; k < nin; ++k) acc += w1[o * nin + k] * z[k];
-      part += w2[o] * selu(acc);
+  for (int i = 0; i < hp.n_ops; ++i) {
+    const HeadOp op = hp.op[i];
+    const float *W = prm + op.w;
+    for (int o = lane; o < op.n_out; o += 64) {
+      float acc = prm[op.b + o];
+      const float *row = W + (int64_t)o * (op.n0 + op.n1);
+      for (int k = 0; k < op.n0; ++k) acc += row[k] * z[op.src0 + k];
+      for (int k = 0; k < op.n1; ++k) acc += row[op.n0 + k] * z[op.src1 + k];
+      if (op.act == kActRelu) acc = acc > 0.f ? acc : 0.f;
+      else if (op.act == kActSelu) acc = selu(acc);
+      if (op.res >= 0) acc += z[op.res + o];
+      z[op.dst + o] = acc;
     }
-  } else {
-    for (int k = lane; k < nin; k += 64) part += w2[k] * z[k];
+    __syncthreads();
   }
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
-  if (lane == 0) scores[pose] = part + b2[0];
+  if (lane == 0) {
+    float s = z[hp.out_slot[0]];
+    if (hp.n_out == 2) s += z[hp.out_slot[1]];
+    scores[pose] = hp.out_scale * s;
+  }
 }
 
 }  // namespace
@@ -95,13 +104,11 @@ hipError_t launch_pool_dense(const void *act, int bf16, int n_poses, int vox, in
   return hipGetLastError();
 }
 
-hipError_t launch_fusion(const float *cnn_lat, int lc, const float *sg_lat, int H, const float *w1,
-                         const float *b1, int hidden, const float *w2, const float *b2, int n_poses,
-                         float *scores, hipStream_t s) {
+hipError_t launch_head(const float *cnn_lat, int lc, const float *sg_lat, int H, const float *params,
+                       const HeadProgram &hp, int n_poses, float *scores, hipStream_t s) {
   if (n_poses <= 0) return hipSuccess;
-  if (lc + H > 512) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_fusion, dim3(n_poses), dim3(64), 0, s, cnn_lat, lc, sg_lat, H, w1, b1, hidden, w2, b2,
-                     scores);
+  if (lc + H > kHeadBuf || hp.n_ops < 1 || hp.n_ops > kHeadMaxOps) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_head, dim3(n_poses), dim3(64), 0, s, cnn_lat, lc, sg_lat, H, params, hp, scores);
   return hipGetLastError();
 }
 

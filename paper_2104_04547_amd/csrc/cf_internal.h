@@ -112,8 +112,30 @@ hipError_t launch_segmax(const float *scores, int n_scores, const int32_t *off, 
 // scratch: 1088 + 8 k bytes
 hipError_t launch_topk(const float *v, int n, int k, int32_t *idx_out, float *val_out, void *scratch, hipStream_t s);
 
-hipError_t launch_fusion(const float *cnn_lat, int lc, const float *sg_lat, int H, const float *w1,
-                         const float *b1, int hidden, const float *w2, const float *b2, int n_poses,
-                         float *scores, hipStream_t s);
+// A fusion head as a list of dense layers over a per-pose feature buffer that
+// starts as [cnn latent (lc) | sg latent (H)]; each layer reads the concatenation
+// of two slices, writes a new slice, applies its activation and optionally adds
+// another slice (a skip connection).  The score is out_scale * the sum of the out
+// slots (Late Fusion: the mean of the two branch predictions).
+constexpr int kHeadMaxOps = 12;
+constexpr int kHeadBuf = 1024;  // floats per pose
+enum HeadAct : int { kActNone = 0, kActRelu = 1, kActSelu = 2 };
+struct HeadOp {
+  int src0, n0;    // input = [slice (src0, n0) ; slice (src1, n1)], n1 may be 0
+  int src1, n1;
+  int dst, n_out;  // output slice (disjoint from the inputs and res)
+  int act;         // HeadAct
+  int res;         // >= 0: add slice [res, res + n_out) after the activation
+  int w, b;        // offsets (floats) of W [n_out][n0 + n1] and b [n_out] in the parameter array
+};
+struct HeadProgram {
+  int n_ops;
+  HeadOp op[kHeadMaxOps];
+  int n_out;       // 1 or 2
+  int out_slot[2];
+  float out_scale;
+};
+hipError_t launch_head(const float *cnn_lat, int lc, const float *sg_lat, int H, const float *params,
+                       const HeadProgram &hp, int n_poses, float *scores, hipStream_t s);
 
 }  // namespace cf

@@ -106,6 +106,15 @@ class Scorer:
     def variants(self, G: int):
         return cfabi.cf_conv_variants(self.ctx, G, len(self.arch.conv))
 
+    def fusion(self, cnn_latent, sg_latent):
+        """Fusion head alone: one pK per pose from device float32 latents."""
+        import torch
+        n = cnn_latent.shape[0]
+        out = torch.empty(n, dtype=torch.float32, device="cuda")
+        cfabi.cf_fusion_fwd(self.ctx, cnn_latent.contiguous().data_ptr(), sg_latent.contiguous().data_ptr(), n,
+                            out.data_ptr(), self._stream())
+        return out
+
     def compound_max(self, scores, compound_off):
         """Best score and pose index per compound segment (device tensors)."""
         import torch

@@ -39,13 +39,13 @@ def test_library_exports_every_declared_function():
 
 def test_struct_layouts_match_header():
     from paper_2104_04547_amd import cfabi
-    # cf_model_desc: 3 + 8*5 + 8 four-byte fields
-    assert ctypes.sizeof(cfabi.cf_model_desc) == 4 * (3 + 40 + 8)
+    # cf_model_desc: 3 + 8*5 + 8 + 5 four-byte fields
+    assert ctypes.sizeof(cfabi.cf_model_desc) == 4 * (3 + 40 + 8 + 5)
     assert ctypes.sizeof(cfabi.cf_pose_batch) == 8 + 5 * 8
     assert ctypes.sizeof(cfabi.cf_csr) == 24
 
 
-@pytest.mark.parametrize("arch_name", ["tiny", "full"])
+@pytest.mark.parametrize("arch_name", ["tiny", "full", "full_mid", "full_late"])
 def test_model_blob_size_and_order(arch_name):
     from paper_2104_04547_amd import cfabi
     arch = synth.ARCHS[arch_name]
@@ -57,6 +57,10 @@ def test_model_blob_size_and_order(arch_name):
     assert d.magic == cfabi.CF_MODEL_MAGIC and d.n_conv == len(arch.conv) and d.H == arch.H
     first = np.frombuffer(blob, dtype="<f4", count=8, offset=ctypes.sizeof(cfabi.cf_model_desc))
     np.testing.assert_array_equal(first, w["conv0.w"].reshape(-1)[:8])
+    # the head's parameters close the blob, in the header's documented order
+    last = arch.head_outputs[-1]
+    np.testing.assert_array_equal(np.frombuffer(blob[-4:], dtype="<f4"), w[last + ".b"])
+    assert d.head == cfabi.HEAD_KINDS[arch.head] and d.fusion_layers == arch.n_fusion
 
 
 def test_last_error_is_callable_without_device():

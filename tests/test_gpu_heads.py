@@ -1,0 +1,72 @@
+"""The three fusion forms on the GPU against the oracle: Coherent, Mid-level and
+Late Fusion (cf_fusion_fwd on latents, and the whole path through
+cf_score_poses for the head variants of the full model, whose trunk is the full
+model's, so the stored oracle latents of the full model apply).
+
+Plain form (float32): |s_gpu - s_oracle| <= 1e-4 * max(1, |s_oracle|) per pose.
+Precision form: |error| <= 2e-2 pK.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import BF16_PK_TOL, golden, score_tol, weights
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name", ["tiny", "full", "full_mid", "full_late"])
+def test_fusion_fwd_matches_oracle(name):
+    import torch
+    from paper_2104_04547_amd import Scorer
+    _say(f"cf_fusion_fwd {name} 300 poses")
+    arch, w = weights(name)
+    rng = np.random.default_rng(17)
+    n = 300
+    # latent scales of real poses: non-negative CNN latents (ReLU), signed SG latents
+    cnn = np.abs(rng.normal(0.0, 2.0, size=(n, arch.cnn_latent))).astype(np.float32)
+    sg = rng.normal(0.0, 8.0, size=(n, arch.H)).astype(np.float32)
+    cnn[0] = 0.0
+    sg[1] = 0.0
+    s = Scorer(arch, w, "fp32")
+    try:
+        got = s.fusion(torch.from_numpy(cnn).cuda(), torch.from_numpy(sg).cuda()).cpu().numpy().astype(np.float64)
+        s.check()
+    finally:
+        s.close()
+    want = np.array([oracle.fusion_head(cnn[i].astype(np.float64), sg[i].astype(np.float64), w, arch)
+                     for i in range(n)])
+    err = np.abs(got - want)
+    assert np.all(err <= score_tol(want)), f"max |err| {err.max():.3e}"
+
+
+@pytest.mark.parametrize("name", ["full_mid", "full_late"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_score_poses_head_variants(name, prec):
+    from paper_2104_04547_amd import Scorer, cfabi
+    _say(f"cf_score_poses {name} {prec} c2 G=48 poses 0..15")
+    arch, w = weights(name)
+    g = golden("c2", 48)
+    n = 16
+    want = np.array([oracle.fusion_head(np.array(p["cnn_lat"]), np.array(p["sg_lat"]), w, arch)
+                     for p in g["poses"][:n]])
+    b = synth.make_poses("c2", n)
+    s = Scorer(arch, w, prec)
+    try:
+        got = s.score(cfabi.DeviceBatch.from_pose_batch(b), 48).cpu().numpy().astype(np.float64)
+        s.check()
+    finally:
+        s.close()
+    err = np.abs(got - want)
+    if prec == "fp32":
+        assert np.all(err <= score_tol(want)), f"max |err| {err.max():.3e}"
+    else:
+        assert err.max() <= BF16_PK_TOL, f"max |err| {err.max():.3e} pK"
