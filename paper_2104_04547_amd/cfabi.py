@@ -116,7 +116,11 @@ def load(path: str = LIB_PATH):
         "cf_conv_variant_name": ([i32], ctypes.c_char_p),
         "cf_compound_max": ([vp, vp, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "cf_top_k": ([vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
+        "cf_fusion_fwd": ([vp, vp, vp, i32, vp, vp], ctypes.c_int),
     }
+    missing = set(EXPORTS) - set(sig)
+    if missing:   # an undeclared signature would pass pointers as 32-bit ints
+        raise ImportError(f"no ctypes signature for {sorted(missing)}")
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
         f.argtypes = args

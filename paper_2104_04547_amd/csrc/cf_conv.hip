@@ -279,6 +279,7 @@ __global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, cons
 // input costs 3 chunks instead of the 2 x 16 = 32 padded channels.
 template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
 struct Conv8Cfg {
+  static_assert(KS >= 3 && KS % 2 == 1, "odd kernel of at least 3 taps per axis");
   static constexpr int PAD = (KS - 1) / 2;
   static constexpr int HZ = TZ * S + KS - S, HY = TY * S + KS - S, HX = TX * S + KS - S;
   static constexpr int ROW = HX * 16 + 16;  // bytes, padded
@@ -340,6 +341,25 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
            (S == 1 ? dy : (dy & 1) * HY2 + (dy >> 1)) * C::ROW + (S == 1 ? dx : (dx & 1) * HX2 + (dx >> 1)) * 16;
   };
 
+  // LDS offset of this lane's tap in pair p whose first tap is (z, y, x): lanes of
+  // the first K half read tap 2p, the second half tap 2p + 1 (the first tap again
+  // past the last tap, whose weights are zero)
+  auto pair_toff = [&](int p, int z, int y, int x) {
+    int ez = z, ey = y, ex = x + 1;
+    if (ex == KS) {
+      ex = 0;
+      if (++ey == KS) {
+        ey = 0;
+        ++ez;
+      }
+    }
+    const int t0 = tapoff(z, y, x);
+    const int t1 = (2 * p + 1 < C::TAPS) ? tapoff(ez, ey, ex) : t0;
+    return khalf ? t1 : t0;
+  };
+  // weight prefetch distance in pairs, even (the row fragments ping-pong inside
+  // the unrolled pair loop); the packed weights carry 4 zero pairs past the end
+  constexpr int kPF = C::NB <= 2 ? 4 : 2;
   const int pair_bytes = nchunks * cout_pad32 * 16 * 2;
   const __amdgpu_buffer_rsrc_t wrs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(wpk), (short)0, wbytes, 0x00020000);
@@ -376,49 +396,54 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     int vb[C::NB];
 #pragma unroll
     for (int nb = 0; nb < C::NB; ++nb) vb[nb] = ((chunk * cout_pad32 + n0 + nb * 32 + lrow) * 16 + khalf * 8) * 2;
-    uint4 b1[C::NB], b2[C::NB];
+    // software pipeline: the weight fragments of pair p + kPF and the LDS row
+    // fragments of pair p + 1 are in flight while the MFMAs of pair p issue.  The
+    // pair loop is unrolled by kPF so that both rings are indexed at compile time
+    // (no register moves, so no wait on the newest loads).
+    uint4 bq[kPF][C::NB];
 #pragma unroll
-    for (int nb = 0; nb < C::NB; ++nb) {
-      b1[nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], 0, 0));
-      b2[nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], pair_bytes, 0));
+    for (int q = 0; q < kPF; ++q)
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb)
+        bq[q][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], q * pair_bytes, 0));
+    int soff = kPF * pair_bytes;
+    uint4 ar[2][C::MB];
+    {
+      const int t0 = pair_toff(0, 0, 0, 0);
+#pragma unroll
+      for (int mb = 0; mb < C::MB; ++mb) ar[0][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + t0);
     }
-    int soff = 2 * pair_bytes;
-    int dz = 0, dy = 0, dx = 0;  // tap 2p
-    for (int p = 0; p < C::PAIRS; ++p) {
-      int ez = dz, ey = dy, ex = dx + 1;  // tap 2p + 1
-      if (ex == KS) {
-        ex = 0;
-        if (++ey == KS) {
-          ey = 0;
-          ++ez;
-        }
-      }
-      const int t0 = tapoff(dz, dy, dx);
-      const int t1 = (2 * p + 1 < C::TAPS) ? tapoff(ez, ey, ex) : t0;
-      const int toff = khalf ? t1 : t0;
-      uint4 bfr[C::NB];
+    int dz = 0, dy = 0, dx = 2;  // first tap of pair 1
+    for (int p0 = 0; p0 < C::PAIRS; p0 += kPF) {
 #pragma unroll
-      for (int nb = 0; nb < C::NB; ++nb) {
-        bfr[nb] = b1[nb];
-        b1[nb] = b2[nb];
-        b2[nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], soff, 0));
-      }
-      soff += pair_bytes;
-      uint4 afr[C::MB];
+      for (int ph = 0; ph < kPF; ++ph) {
+        const int p = p0 + ph;
+        if (p < C::PAIRS) {
+          // the last pair re-reads offset 0 of its rows (inside the halo) instead
+          const int tn = (p + 1 < C::PAIRS) ? pair_toff(p + 1, dz, dy, dx) : 0;
 #pragma unroll
-      for (int mb = 0; mb < C::MB; ++mb) afr[mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + toff);
+          for (int mb = 0; mb < C::MB; ++mb)
+            ar[(ph + 1) & 1][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + tn);
+          __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this pair's MFMAs
+          dx += 2;
+          if (dx >= KS) {
+            dx -= KS;
+            if (++dy == KS) {
+              dy = 0;
+              ++dz;
+            }
+          }
 #pragma unroll
-      for (int mb = 0; mb < C::MB; ++mb)
+          for (int mb = 0; mb < C::MB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < C::NB; ++nb)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, afr[mb]),
-                                                                 __builtin_bit_cast(bf16x8, bfr[nb]), acc[mb][nb], 0, 0, 0);
-      dx += 2;
-      if (dx >= KS) {
-        dx -= KS;
-        if (++dy == KS) {
-          dy = 0;
-          ++dz;
+            for (int nb = 0; nb < C::NB; ++nb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ar[ph & 1][mb]),
+                                                                     __builtin_bit_cast(bf16x8, bq[ph][nb]),
+                                                                     acc[mb][nb], 0, 0, 0);
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb)
+            bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], soff, 0));
+          soff += pair_bytes;
         }
       }
     }
@@ -543,7 +568,6 @@ const Variant kVariants[] = {
     CF_VARIANT8(7, 2, 8, 8, 8, 4, 64),  // 20: stride-2 first layer, 512-row tile
     CF_VARIANT8(7, 1, 8, 8, 8, 8, 64),  // 21
     CF_VARIANT8(7, 2, 4, 4, 12, 6, 128), // 22: 12^3 outputs of a 24^3 input in 9 whole tiles
-    CF_VARIANT8(7, 2, 4, 4, 12, 3, 128), // 23
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -564,7 +588,7 @@ int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
   (void)D_in;
   // measured on MI355X at 48^3 (bf16: tap pairs for stride 1 and the 128-column
   // stride-2 layer; fp32 has no tap-pair kernel)
-  const int pref[] = {12, 17, 20, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 19, 21, 22, 23};
+  const int pref[] = {12, 17, 20, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 19, 21, 22};
   for (int v : pref)
     if (conv_variant_ok(v, L, bf16)) return v;
   return -1;
