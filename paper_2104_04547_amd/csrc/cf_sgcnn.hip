@@ -65,14 +65,16 @@ __device__ inline void sg_aggregate(const float *__restrict__ cur, const int32_t
         dev_fail(status, kDevBadGraph);
         e0 = e1;
       }
+      // branch-free body (a column outside the pose reads the atom's own row and
+      // adds nothing) so that several neighbour rows are in flight at once
+#pragma unroll 4
       for (int64_t q = e0; q < e1; ++q) {
         int64_t j = colp[q];
         if (csr_global) j -= base;
-        if (j < lb || j >= lb + n) {
-          dev_fail(status, kDevBadGraph);
-          continue;
-        }
-        s += cur[j * H + oo];
+        const bool bad = j < lb || j >= lb + n;
+        if (bad) dev_fail(status, kDevBadGraph);
+        const float v = cur[(bad ? lb + i : j) * H + oo];
+        s += bad ? 0.0f : v;
       }
       hc = cur[(lb + i) * H + oo];
     }
@@ -275,15 +277,21 @@ struct SgMfmaShared {
   static constexpr int FB = H / 32;     // 32-feature blocks
   static constexpr int MBK = 4 / FB;    // 32-atom blocks per workgroup block
   static constexpr int BLK = 32 * MBK;  // atoms per block
-  float A[BLK * LD];
-  float M[BLK * LD];
-  float Hc[BLK * LD];
-  float Wg[(H + CF_NCH) * H];
-  float Wv[H * H];
+  // rounds: A | M | Hc; readout (after the rounds): Wg | Wv | red, in the same
+  // space, so that several poses share a CU
+  float buf[3 * BLK * LD];
+  static_assert((H + CF_NCH) * H + H * H + kThreads <= 3 * BLK * LD, "readout staging must fit");
+  __device__ float *A() { return buf; }
+  __device__ float *M() { return buf + BLK * LD; }
+  __device__ float *Hc() { return buf + 2 * BLK * LD; }
+  __device__ float *Wg() { return buf; }
+  __device__ float *Wv() { return buf + (H + CF_NCH) * H; }
+  __device__ float *red() { return buf + (H + CF_NCH) * H + H * H; }
 };
 
 template <int H>
-__global__ __launch_bounds__(kThreads) void k_sgcnn_mfma(SgWeights W, const int32_t *__restrict__ atom_off,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_sgcnn_mfma(
+    SgWeights W, const int32_t *__restrict__ atom_off,
                                                          int n_atoms, const float *__restrict__ feat,
                                                          const uint8_t *__restrict__ is_lig, int p0,
                                                          const int32_t *__restrict__ cov_row,
@@ -330,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn_mfma(SgWeights W, const int3
     const float bir = bih[ocol], biz = bih[H + ocol], bin = bih[2 * H + ocol];
     const float bhr = bhh[ocol], bhz = bhh[H + ocol], bhn = bhh[2 * H + ocol];
     for (int blk = 0; blk < n; blk += BLK) {
-      sg_aggregate<H>(cur, rowp, colp, cap, csr_global, a0, base, lb, n, blk, BLK, LD, S.A, S.Hc, status);
+      sg_aggregate<H>(cur, rowp, colp, cap, csr_global, a0, base, lb, n, blk, BLK, LD, S.A(), S.Hc(), status);
       __syncthreads();
       // messages: M[atoms, ocol] = sum_k A[atoms, k] W_t[ocol, k]
       {
@@ -338,7 +346,7 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn_mfma(SgWeights W, const int3
 #pragma unroll
         for (int ks = 0; ks < H / 16; ++ks) {
           bf16x8 ah, al;
-          split8(&S.A[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], ah, al);
+          split8(&S.A()[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], ah, al);
           const int64_t wo = ((int64_t)ks * H + ocol) * 16 + khalf * 8;
           const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(mh + wo);
           const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(ml + wo);
@@ -347,7 +355,7 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn_mfma(SgWeights W, const int3
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           const int row = mb * 32 + 8 * (j >> 2) + 4 * khalf + (j & 3);
-          S.M[row * LD + ocol] = acc[j];
+          S.M()[row * LD + ocol] = acc[j];
         }
       }
       __syncthreads();
@@ -357,8 +365,8 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn_mfma(SgWeights W, const int3
 #pragma unroll
         for (int ks = 0; ks < H / 16; ++ks) {
           bf16x8 mhi, mlo, hhi, hlo;
-          split8(&S.M[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], mhi, mlo);
-          split8(&S.Hc[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], hhi, hlo);
+          split8(&S.M()[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], mhi, mlo);
+          split8(&S.Hc()[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], hhi, hlo);
           const int64_t w0 = ((int64_t)ks * 3 * H + ocol) * 16 + khalf * 8;
           const int64_t gs = (int64_t)H * 16;  // next gate's rows
           gir = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0), *reinterpret_cast<const bf16x8 *>(il + w0), gir);
@@ -376,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn_mfma(SgWeights W, const int3
             const float rr = sigm(gir[j] + bir + ghr[j] + bhr);
             const float zz = sigm(giz[j] + biz + ghz[j] + bhz);
             const float nn = tanhf(gin[j] + bin + rr * (ghn[j] + bhn));
-            nxt[(lb + i) * H + ocol] = (1.0f - zz) * nn + zz * S.Hc[row * LD + ocol];
+            nxt[(lb + i) * H + ocol] = (1.0f - zz) * nn + zz * S.Hc()[row * LD + ocol];
           }
         }
       }
@@ -388,10 +396,10 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn_mfma(SgWeights W, const int3
     cur = nxt;
     nxt = tmp;
   }
-  for (int e = t; e < (H + CF_NCH) * H; e += kThreads) S.Wg[e] = W.gate_wT[e];
-  for (int e = t; e < H * H; e += kThreads) S.Wv[e] = W.val_wT[e];
+  for (int e = t; e < (H + CF_NCH) * H; e += kThreads) S.Wg()[e] = W.gate_wT[e];
+  for (int e = t; e < H * H; e += kThreads) S.Wv()[e] = W.val_wT[e];
   __syncthreads();
-  sg_readout<H>(W, cur, feat, is_lig, a0, n, lb, S.Wg, S.Wv, S.A, sg_latent + (int64_t)pl * H);
+  sg_readout<H>(W, cur, feat, is_lig, a0, n, lb, S.Wg(), S.Wv(), S.red(), sg_latent + (int64_t)pl * H);
 }
 
 template <typename K>
