@@ -114,7 +114,7 @@ def conv_traffic(kernel):
     return round(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"], 0)
 
 
-def cpu_baseline(batch, arch, w, G, n):
+def cpu_baseline(batch, arch, w, G, n, one_core=True):
     """The FP64 oracle as it stands, on the first n poses, on this host's cores."""
     import numpy as np
     import oracle
@@ -123,15 +123,28 @@ def cpu_baseline(batch, arch, w, G, n):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
-    t0 = time.perf_counter()
-    for p in range(n):
-        a, b = int(batch.atom_off[p]), int(batch.atom_off[p + 1])
-        oracle.score_pose(batch.xyz[a:b], batch.feat[a:b], batch.is_lig[a:b], w, arch, G)
-    dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit="poses/s", cores=int(threads), kind="oracle",
-                sample=f"first {n} of the workload's poses, full path per pose (splat, conv stack, "
-                       f"graphs, SG-CNN, fusion) in float64 numpy; {dt:.1f} s",
-                seconds=dt)
+    def run(poses):
+        t0 = time.perf_counter()
+        for p in poses:
+            a, b = int(batch.atom_off[p]), int(batch.atom_off[p + 1])
+            oracle.score_pose(batch.xyz[a:b], batch.feat[a:b], batch.is_lig[a:b], w, arch, G)
+        return time.perf_counter() - t0
+
+    dt = run(range(n))
+    out = dict(value=n / dt, unit="poses/s", cores=int(threads), kind="oracle",
+               sample=f"first {n} of the workload's poses, full path per pose (splat, conv stack, "
+                      f"graphs, SG-CNN, fusion) in float64 numpy; {dt:.1f} s",
+               seconds=dt)
+    if one_core:
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(1):
+                d1 = run([n])
+            out["value_1core"] = 1.0 / d1
+            out["sample_1core"] = f"pose {n} on one thread; {d1:.1f} s"
+        except ImportError:
+            pass
+    return out
 
 
 def batching_leg(arch, w, n_poses, steps):
@@ -317,7 +330,8 @@ def main():
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(batch, arch, w, G, a.cpu_poses)
-        log(f"cpu oracle: {cpu['value']:.4f} poses/s on {cpu['cores']} threads")
+        log(f"cpu oracle: {cpu['value']:.4f} poses/s on {cpu['cores']} threads, "
+            f"{cpu.get('value_1core', float('nan')):.4f} poses/s on one")
 
     bf = res["bf16"]
     line = {

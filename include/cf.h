@@ -139,8 +139,10 @@ typedef struct {
 
 /* Create a scoring context on the current device.  Copies the weights (the blob
  * may be freed afterwards), folds BatchNorm into the conv weights and bias in
- * float32, and repacks weights for the kernels.  hbm_budget_bytes bounds the
- * scratch the context may allocate (0 = 16 GiB); batches larger than the budget
+ * double precision (stored float32), and repacks weights for the kernels.
+ * hbm_budget_bytes bounds the
+ * scratch the context may allocate (0 = half of the
+ * device memory, at most 64 GiB); batches larger than the budget
  * allows are scored in chunks.  Section refs: model structure Sec. 2.2, 3.3. */
 int cf_create(const void *host_model_blob, size_t nbytes, int precision,
               int64_t hbm_budget_bytes, cf_ctx **out);

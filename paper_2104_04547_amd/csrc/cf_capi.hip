@@ -139,18 +139,48 @@ int64_t pose_bytes(const cf_ctx *c, int G) {
   return b;
 }
 
-// scratch bytes per atom of a chunk (neighbour lists, degrees, SG states)
-int64_t atom_bytes(const cf_ctx *c) { return 4 * (2 + 2 + 16 + 96) + 2 * 4 * (int64_t)c->desc.H; }
 
-// Poses per launch: at most 512, and the conv tensors of the chunk plus the
-// per-atom scratch of its atoms (at most n_atoms; 0 = no atom stages) must fit
-// the context's HBM budget.
+// Scratch the context will hold after a call that needs buffers for n poses at
+// grid size G and, when atoms > 0, per-atom buffers for that many atoms: the
+// buffers only grow (ensure keeps a larger allocation), so each one counts as
+// the larger of what it holds and what the call needs.
+int64_t scratch_after(const cf_ctx *c, int G, int64_t n, int64_t atoms) {
+  int64_t t = c->scratch_bytes;
+  auto grow = [&](const DevBuf &b, int64_t need) {
+    if (need > (int64_t)b.n) t += need - (int64_t)b.n;
+  };
+  grow(c->grid, n * G * G * G * grid_cpad(c) * (int64_t)elem_size(c));
+  int D = G;
+  for (size_t i = 0; i < c->conv.size(); ++i) {
+    D = conv_out_dim(D, c->conv[i].k, c->conv[i].stride);
+    const int64_t need = n * D * D * D * c->conv[i].cout_store * (int64_t)elem_size(c);
+    if (i < c->act.size()) grow(c->act[i], need);
+    else t += need;
+  }
+  grow(c->centers, n * 3 * 4);
+  grow(c->cnn_lat, n * c->lc * 4);
+  grow(c->sg_lat, n * c->desc.H * 4);
+  if (atoms > 0) {
+    grow(c->deg, 2 * atoms * 4);
+    grow(c->pose_tot, 4 * n * 8);
+    grow(c->cov_row, (atoms + 1) * 4);
+    grow(c->nc_row, (atoms + 1) * 4);
+    grow(c->cov_col, atoms * 16 * 4);
+    grow(c->nc_col, atoms * 96 * 4);
+    grow(c->hbuf, 2 * atoms * c->desc.H * 4);
+  }
+  return t;
+}
+
+// Poses per launch: at most 512, such that everything the call allocates (conv
+// tensors of the chunk and, with atom stages, the per-atom scratch of at most
+// n_atoms atoms) fits the context's HBM budget next to what it already holds.
 int chunk_poses(const cf_ctx *c, int G, int P, int64_t n_atoms = 0) {
   const int64_t avail = c->budget - c->weight_bytes - ((int64_t)64 << 20);
   int n = std::min(512, P);
   while (n > 1) {
     const int64_t atoms = n_atoms > 0 ? std::min<int64_t>(n_atoms, (int64_t)n * CF_MAX_POSE_ATOMS) : 0;
-    if ((int64_t)n * (pose_bytes(c, G) + 4096) + atoms * atom_bytes(c) <= avail) break;
+    if (scratch_after(c, G, n, atoms) <= avail) break;
     n = n > 64 ? n - 32 : n - 1;
   }
   return n < 1 ? 1 : n;
@@ -612,7 +642,14 @@ int cf_create(const void *blob, size_t nbytes, int precision, int64_t hbm_budget
   cf_ctx *c = new (std::nothrow) cf_ctx();
   if (!c) return fail(CF_ERR_OOM, "host allocation failed");
   c->bf16 = precision == CF_PREC_BF16;
-  c->budget = hbm_budget_bytes > 0 ? hbm_budget_bytes : ((int64_t)16 << 30);
+  if (hbm_budget_bytes > 0) {
+    c->budget = hbm_budget_bytes;
+  } else {  // default: half of the device's memory, at most 64 GiB
+    size_t free_b = 0, total_b = 0;
+    c->budget = (int64_t)16 << 30;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && total_b > 0)
+      c->budget = std::min<int64_t>((int64_t)64 << 30, (int64_t)(total_b / 2));
+  }
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return fail(CF_ERR_HIP, "no HIP device");
