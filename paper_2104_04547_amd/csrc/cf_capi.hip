@@ -47,6 +47,7 @@ struct cf_ctx {
   int64_t n_params = 0;
   int64_t weight_bytes = 0;
   int64_t scratch_bytes = 0;
+  int64_t scratch_gen = 0;  // bumped whenever a scratch buffer is (re)allocated
 
   std::vector<cf::ConvLayer> conv;
   int lc = 0;  // CNN latent width
@@ -100,6 +101,7 @@ int ensure(cf_ctx *c, DevBuf &b, size_t bytes) {
     b.p = nullptr;
     b.n = 0;
   }
+  c->scratch_gen++;
   if (hipMalloc(&b.p, bytes) != hipSuccess) return fail(CF_ERR_OOM, "scratch allocation failed");
   b.n = bytes;
   c->scratch_bytes += (int64_t)bytes;
@@ -983,3 +985,7 @@ int cf_autotune(cf_ctx *c, int G, int32_t n_poses, void *stream) {
 }
 
 }  // extern "C"
+
+namespace cf {
+int64_t scratch_generation(const cf_ctx *c) { return c ? c->scratch_gen : 0; }
+}  // namespace cf

@@ -61,7 +61,18 @@ struct Slot {
   bool busy = false;
   std::vector<std::pair<Request *, int>> members;  // request, first pose in the batch
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  int64_t graphs_gen = -1;  // scratch generation of the context the graphs were captured against
 };
+
+// Captured graphs hold the context's scratch pointers; once the context has
+// reallocated any scratch buffer they must be dropped (and captured again).
+void drop_stale_graphs(Slot &s) {
+  const int64_t gen = cf::scratch_generation(s.ctx);
+  if (gen == s.graphs_gen) return;
+  for (auto &kv : s.graphs) (void)hipGraphExecDestroy(kv.second);
+  s.graphs.clear();
+  s.graphs_gen = gen;
+}
 
 }  // namespace
 
@@ -142,10 +153,12 @@ int launch_batch(cf_engine *e, Slot &s, std::vector<Request *> &take, int G) {
   int rc = CF_OK;
   if (e->cfg.use_graphs) {
     auto key = std::make_pair(G, bucket);
+    drop_stale_graphs(s);
     auto it = s.graphs.find(key);
     if (it == s.graphs.end()) {
       // warm-up (allocates scratch, outside capture), then capture
       if ((rc = cf_score_poses(s.ctx, &b, G, s.d_scores, st))) return rc;
+      drop_stale_graphs(s);  // the warm-up may have grown scratch other graphs point into
       hipGraph_t g = nullptr;
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) return CF_ERR_HIP;
       rc = cf_score_poses(s.ctx, &b, G, s.d_scores, st);

@@ -135,6 +135,11 @@ struct HeadProgram {
   int out_slot[2];
   float out_scale;
 };
+// Counter that changes whenever the context (re)allocates a scratch buffer: work
+// captured into a graph before a change refers to freed memory and must not be
+// replayed.
+int64_t scratch_generation(const cf_ctx *c);
+
 hipError_t launch_head(const float *cnn_lat, int lc, const float *sg_lat, int H, const float *params,
                        const HeadProgram &hp, int n_poses, float *scores, hipStream_t s);
 

@@ -64,6 +64,36 @@ def test_alone_equals_in_the_mix_equals_direct(setup):
     assert info["batches"] >= 2 and info["graph_replays"] >= 2
 
 
+def test_graphs_survive_scratch_growth():
+    # a graph captured for a small batch must not be replayed after a larger
+    # batch has made the slot's context reallocate its scratch: the engine drops
+    # and re-captures it, and the result stays bitwise the same
+    from paper_2104_04547_amd import Scorer, cfabi
+    from paper_2104_04547_amd.serve import Engine
+    arch, w = weights("full")
+    pool = synth.make_poses("c5", 80)
+    small = pool.select(list(range(3)))
+    big = pool.select(list(range(3, 80)))
+    eng = Engine(arch, w, "bf16", n_slots=1, slot_poses=128, slot_atoms=128 * 1600, hbm_budget_bytes=16 << 30)
+    try:
+        _say("engine: small batch at G=32 (graph captured)")
+        first, _ = eng.result(eng.submit(small, 32), 3)
+        _say("engine: 77 poses at G=64 (scratch grows)")
+        eng.result(eng.submit(big, 64), big.n_poses)
+        _say("engine: small batch at G=32 again (graph captured again)")
+        again, _ = eng.result(eng.submit(small, 32), 3)
+    finally:
+        eng.close()
+    assert np.array_equal(first, again)
+    sc = Scorer(arch, w, "bf16")
+    try:
+        direct = sc.score(cfabi.DeviceBatch.from_pose_batch(small), 32).cpu().numpy()
+        sc.check()
+    finally:
+        sc.close()
+    assert np.array_equal(first, direct)
+
+
 def test_engine_scores_meet_the_oracle_bound(setup):
     arch, w, pool, eng = setup
     sub = pool.select([0, 1])
