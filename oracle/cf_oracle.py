@@ -148,7 +148,7 @@ def relu(x):
 def cnn3d_forward(grid: np.ndarray, w: Dict[str, np.ndarray], arch) -> Tuple[np.ndarray, list]:
     """grid [G,G,G,C] -> (latent, per-layer activations).  Each conv is followed by
     BN (if enabled) and ReLU; a residual conv adds its block input before the
-    ReLU; global average pooling; optional dense + ReLU."""
+    ReLU; global average pooling; up to two dense + ReLU layers."""
     t = [np.moveaxis(np.asarray(grid, np.float64), -1, 0)]
     for i, (ci, co, k, s, r) in enumerate(arch.conv):
         y = conv3d(t[-1], w[f"conv{i}.w"], w[f"conv{i}.b"], s)
@@ -158,10 +158,10 @@ def cnn3d_forward(grid: np.ndarray, w: Dict[str, np.ndarray], arch) -> Tuple[np.
             y = y + t[r]
         t.append(relu(y))
     pooled = t[-1].mean(axis=(1, 2, 3))
-    if arch.cnn_dense:
-        lat = relu(np.asarray(w["cnn_dense.w"], np.float64) @ pooled + np.asarray(w["cnn_dense.b"], np.float64))
-    else:
-        lat = pooled
+    lat = pooled
+    for name in ("cnn_dense", "cnn_dense2"):
+        if getattr(arch, name):
+            lat = relu(np.asarray(w[name + ".w"], np.float64) @ lat + np.asarray(w[name + ".b"], np.float64))
     return lat, t
 
 
@@ -231,18 +231,30 @@ def sgcnn_pose(feat: np.ndarray, is_lig: np.ndarray, cov, nc, w: Dict[str, np.nd
                return_h: bool = False):
     """One pose: embed, K_c covalent rounds then K_n non-covalent rounds of
     a = sum of neighbour states, m = W_t a, h <- GRU_stage(m, h), then the gated
-    readout over ligand atoms s = sum_i sigma(W_g [h_i; x_i] + b_g) * (W_v h_i + b_v).
-    cov / nc are local CSR pairs (row_ptr, col)."""
+    readout over ligand atoms s = sum_i sigma(W_g [h_i; u_i] + b_g) * (W_v h_i + b_v),
+    where u is the stage input (the raw features x).
+
+    With PotentialNet staging (arch.H_nc > 0, Sec. 3.3.1 / Table II gather widths),
+    the covalent stage closes with a per-atom gated gather
+    g_i = sigma(W_g1 [h_i; x_i] + b_g1) * (W_v1 h_i + b_v1) (width H); the
+    non-covalent stage starts from a linear embedding of g (width H_nc), and the
+    final readout's gate reads [h_i; g_i].  cov / nc are local CSR pairs."""
     x = np.asarray(feat, np.float64)
     f64 = lambda k: np.asarray(w[k], np.float64)
     h = x @ f64("sg.embed.w").T + f64("sg.embed.b")
+    u = x
     for stage, K, (rp, col) in (("cov", arch.K_c, cov), ("nc", arch.K_n, nc)):
+        if stage == "nc" and arch.H_nc:
+            g = sigmoid(np.concatenate([h, x], axis=1) @ f64("sg.mid.gate.w").T + f64("sg.mid.gate.b")) \
+                * (h @ f64("sg.mid.val.w").T + f64("sg.mid.val.b"))
+            h = g @ f64("sg.embed2.w").T + f64("sg.embed2.b")
+            u = g
         for t in range(K):
             a = aggregate(h, rp, col)
             m = a @ f64(f"sg.{stage}.msg{t}.w").T
             h = gru_cell(m, h, w[f"sg.{stage}.gru.w_ih"], w[f"sg.{stage}.gru.w_hh"],
                          w[f"sg.{stage}.gru.b_ih"], w[f"sg.{stage}.gru.b_hh"])
-    gate = sigmoid(np.concatenate([h, x], axis=1) @ f64("sg.gate.w").T + f64("sg.gate.b"))
+    gate = sigmoid(np.concatenate([h, u], axis=1) @ f64("sg.gate.w").T + f64("sg.gate.b"))
     val = h @ f64("sg.val.w").T + f64("sg.val.b")
     lig = np.asarray(is_lig).astype(bool)
     s = (gate[lig] * val[lig]).sum(axis=0)
@@ -250,7 +262,7 @@ def sgcnn_pose(feat: np.ndarray, is_lig: np.ndarray, cov, nc, w: Dict[str, np.nd
 
 
 def sgcnn_batch(batch, w, arch) -> np.ndarray:
-    out = np.zeros((batch.n_poses, arch.H))
+    out = np.zeros((batch.n_poses, arch.sg_latent))
     for p in range(batch.n_poses):
         a, b = int(batch.atom_off[p]), int(batch.atom_off[p + 1])
         cov = radius_graph_pose(batch.xyz[a:b], arch.r_cov_u)

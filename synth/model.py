@@ -83,6 +83,10 @@ class ModelArch:
                             # latents); "late": each branch predicts its own pK
                             # and the score is their mean
     sg_dense: Tuple[int, ...] = ()  # late head: SG-CNN dense layers (ReLU) before its output
+    cnn_dense2: int = 0     # second 3D-CNN dense layer (ReLU) after cnn_dense, 0 = none
+    H_nc: int = 0           # > 0: PotentialNet staging -- the covalent stage runs at width H,
+                            # a per-atom gated gather closes it, and the non-covalent stage
+                            # runs at width H_nc on a linear embedding of that gather
 
     @property
     def n_fusion(self) -> int:
@@ -99,11 +103,15 @@ class ModelArch:
 
     @property
     def cnn_latent(self) -> int:
-        return self.cnn_dense if self.cnn_dense else self.c_last
+        return self.cnn_dense2 or self.cnn_dense or self.c_last
+
+    @property
+    def sg_latent(self) -> int:
+        return self.H_nc or self.H
 
     @property
     def fusion_in(self) -> int:
-        return (2 if self.head == "mid" else 1) * (self.cnn_latent + self.H)
+        return (2 if self.head == "mid" else 1) * (self.cnn_latent + self.sg_latent)
 
     def out_dims(self, G: int) -> List[int]:
         dims = [G]
@@ -123,6 +131,8 @@ class ModelArch:
 
 R_COV_U = int(round(1.6 * 1024))   # 1638
 R_NC_U = int(round(4.5 * 1024))    # 4608
+R_COV_PAPER_U = int(round(2.24 * 1024))   # 2294 (Table II)
+R_NC_PAPER_U = int(round(5.22 * 1024))    # 5345 (Table II)
 
 ARCHS: Dict[str, ModelArch] = {
     "tiny": ModelArch("tiny", 19, ((19, 16, 5, 1, -1), (16, 16, 5, 1, -1)), True, 0,
@@ -141,6 +151,17 @@ ARCHS["full_mid"] = dataclasses.replace(ARCHS["full"], name="full_mid", head="mi
                                         fusion_residual=True)
 ARCHS["full_late"] = dataclasses.replace(ARCHS["full"], name="full_late", head="late", fusion_hidden=0,
                                          sg_dense=(42, 21))
+
+# The paper's own tuned sizes as a second workload (Sec. 3.3.1, Tables II, III, V):
+# 3D-CNN with 32 filters of 5^3 then 64 of 3^3, residual connections around the
+# stride-1 pairs, no BatchNorm, dense layers of 128 and 128 / 2 nodes; SG-CNN with
+# 6 covalent rounds at gather width 24 and 3 non-covalent rounds at width 128,
+# cutoffs 2.24 / 5.22 A; Coherent Fusion head of 4 fusion layers.
+ARCHS["paper"] = ModelArch("paper", 19,
+                           ((19, 32, 5, 2, -1), (32, 32, 5, 1, -1), (32, 32, 5, 1, 1),
+                            (32, 64, 3, 2, -1), (64, 64, 3, 1, -1), (64, 64, 3, 1, 4)),
+                           False, 128, 24, 6, 3, R_COV_PAPER_U, R_NC_PAPER_U, 64,
+                           fusion_layers=4, cnn_dense2=64, H_nc=128)
 
 # Workloads.  mode 0: n_lig ~ U{lim0..lim1}, n_pocket ~ U{lim2..lim3};
 # mode 1: total ~ log-U[lim0, lim1] split into ligand / pocket.
@@ -166,17 +187,29 @@ def param_shapes(arch: ModelArch) -> List[Tuple[str, Tuple[int, ...], str]]:
     if arch.cnn_dense:
         out.append(("cnn_dense.w", (arch.cnn_dense, arch.c_last), "he"))
         out.append(("cnn_dense.b", (arch.cnn_dense,), "bias"))
+    if arch.cnn_dense2:
+        out.append(("cnn_dense2.w", (arch.cnn_dense2, arch.cnn_dense), "he"))
+        out.append(("cnn_dense2.b", (arch.cnn_dense2,), "bias"))
     H = arch.H
     out.append(("sg.embed.w", (H, arch.n_ch), "he"))
     out.append(("sg.embed.b", (H,), "bias"))
     for stage, K in (("cov", arch.K_c), ("nc", arch.K_n)):
+        if stage == "nc" and arch.H_nc:
+            out.append(("sg.mid.gate.w", (H, H + arch.n_ch), "he"))
+            out.append(("sg.mid.gate.b", (H,), "bias"))
+            out.append(("sg.mid.val.w", (H, H), "he"))
+            out.append(("sg.mid.val.b", (H,), "bias"))
+            out.append(("sg.embed2.w", (arch.H_nc, H), "he"))
+            out.append(("sg.embed2.b", (arch.H_nc,), "bias"))
+            H = arch.H_nc
         for t in range(K):
             out.append((f"sg.{stage}.msg{t}.w", (H, H), "he"))
         out.append((f"sg.{stage}.gru.w_ih", (3 * H, H), "he"))
         out.append((f"sg.{stage}.gru.w_hh", (3 * H, H), "he"))
         out.append((f"sg.{stage}.gru.b_ih", (3 * H,), "bias"))
         out.append((f"sg.{stage}.gru.b_hh", (3 * H,), "bias"))
-    out.append(("sg.gate.w", (H, H + arch.n_ch), "he"))
+    # the final gate reads [h; stage input]: the raw features, or the covalent gather
+    out.append(("sg.gate.w", (H, H + (arch.H if arch.H_nc else arch.n_ch)), "he"))
     out.append(("sg.gate.b", (H,), "bias"))
     out.append(("sg.val.w", (H, H), "he"))
     out.append(("sg.val.b", (H,), "bias"))
@@ -184,7 +217,7 @@ def param_shapes(arch: ModelArch) -> List[Tuple[str, Tuple[int, ...], str]]:
     if arch.head == "late":
         out.append(("late.cnn_out.w", (1, lc), "he"))
         out.append(("late.cnn_out.b", (1,), "bias"))
-        prev = H
+        prev = arch.sg_latent
         for j, d in enumerate(arch.sg_dense):
             out.append((f"late.sg_dense{j}.w", (d, prev), "he"))
             out.append((f"late.sg_dense{j}.b", (d,), "bias"))
@@ -193,10 +226,11 @@ def param_shapes(arch: ModelArch) -> List[Tuple[str, Tuple[int, ...], str]]:
         out.append(("late.sg_out.b", (1,), "bias"))
         return out
     if arch.head == "mid":
+        Hs = arch.sg_latent
         out.append(("mid.cnn.w", (lc, lc), "he"))
         out.append(("mid.cnn.b", (lc,), "bias"))
-        out.append(("mid.sg.w", (H, H), "he"))
-        out.append(("mid.sg.b", (H,), "bias"))
+        out.append(("mid.sg.w", (Hs, Hs), "he"))
+        out.append(("mid.sg.b", (Hs,), "bias"))
     prev = arch.fusion_in
     for l in range(arch.n_fusion - 1):
         name = "fusion.hidden" if l == 0 else f"fusion.hidden{l}"

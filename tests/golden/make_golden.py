@@ -13,6 +13,8 @@ the HIP path.  Outputs (JSON, floats written with repr so they round-trip):
 Usage:  python tests/golden/make_golden.py c1 24 64
         python tests/golden/make_golden.py c2 48 64 --calibrate
         python tests/golden/make_golden.py c4 32 8
+        python tests/golden/make_golden.py c2 48 64 --arch paper --calibrate
+            (the paper-shaped model on the config's poses)
         python tests/golden/make_golden.py c2 48 64 --head-arch full_mid
             (calibration only, for an architecture that shares the config's trunk
              -- same conv / SG-CNN weights, another fusion head -- computed from
@@ -35,8 +37,8 @@ def _latents(args):
     import numpy as np
     import oracle
     import synth
-    cfg, G, p = args
-    arch = synth.ARCHS[synth.CONFIGS[cfg]["arch"]]
+    cfg, G, p, arch_name = args
+    arch = synth.ARCHS[arch_name]
     w = synth.make_weights(arch)
     b = synth.make_poses(cfg, 1, pose0=p, threads=1)
     lig = b.is_lig.astype(bool)
@@ -57,6 +59,7 @@ def main():
     ap.add_argument("--calibrate", action="store_true")
     ap.add_argument("--workers", type=int, default=os.cpu_count())
     ap.add_argument("--head-arch", default=None)
+    ap.add_argument("--arch", default=None, help="another architecture on the config's poses")
     a = ap.parse_args()
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     import numpy as np
@@ -68,9 +71,9 @@ def main():
         return
 
     t0 = time.time()
+    arch_name = a.arch or synth.CONFIGS[a.cfg]["arch"]
     with get_context("spawn").Pool(a.workers) as pool:
-        rows = sorted(pool.map(_latents, [(a.cfg, a.G, p) for p in range(a.n)], chunksize=1))
-    arch_name = synth.CONFIGS[a.cfg]["arch"]
+        rows = sorted(pool.map(_latents, [(a.cfg, a.G, p, arch_name) for p in range(a.n)], chunksize=1))
     arch = synth.ARCHS[arch_name]
     w = synth.make_weights(arch)
     calib_path = os.path.join(HERE, "calib.json")
@@ -90,7 +93,8 @@ def main():
         s = oracle.fusion_head(np.array(cnn), np.array(sg), cw, arch)
         out["poses"].append(dict(pose=p, center=c, cnn_lat=cnn, sg_lat=sg, score=float(s),
                                  n_cov_edges=ecov, n_nc_edges=enc))
-    path = os.path.join(HERE, f"{a.cfg}_G{a.G}_oracle.json")
+    tag = "" if arch_name == synth.CONFIGS[a.cfg]["arch"] else f"_{arch_name}"
+    path = os.path.join(HERE, f"{a.cfg}_G{a.G}{tag}_oracle.json")
     json.dump(out, open(path, "w"))
     print(f"wrote {path} ({a.n} poses) in {time.time() - t0:.1f}s")
 

@@ -17,7 +17,8 @@ import synth
 
 # ---------------------------------------------------------------- conv3d / CNN
 
-@pytest.mark.parametrize("C,O,k,s,D", [(3, 4, 3, 1, 6), (5, 2, 5, 2, 9), (19, 6, 7, 2, 12), (4, 3, 7, 1, 5)])
+@pytest.mark.parametrize("C,O,k,s,D", [(3, 4, 3, 1, 6), (5, 2, 5, 2, 9), (19, 6, 7, 2, 12), (4, 3, 7, 1, 5),
+                                       (6, 5, 3, 2, 8), (19, 4, 5, 2, 10)])
 def test_conv3d_matches_torch_float64(C, O, k, s, D):
     rng = np.random.default_rng(C * 100 + k)
     x = rng.standard_normal((C, D, D + 1, D + 2))
@@ -82,18 +83,28 @@ class _TorchCNN(torch.nn.Module):
             c = torch.nn.Conv3d(ci, co, k, stride=s, padding=(k - 1) // 2).double()
             c.weight.data = torch.from_numpy(w[f"conv{i}.w"].astype(np.float64))
             c.bias.data = torch.from_numpy(w[f"conv{i}.b"].astype(np.float64))
-            bn = torch.nn.BatchNorm3d(co, eps=1e-5).double().eval()
-            bn.weight.data = torch.from_numpy(w[f"bn{i}.gamma"].astype(np.float64))
-            bn.bias.data = torch.from_numpy(w[f"bn{i}.beta"].astype(np.float64))
-            bn.running_mean = torch.from_numpy(w[f"bn{i}.mean"].astype(np.float64))
-            bn.running_var = torch.from_numpy(w[f"bn{i}.var"].astype(np.float64))
+            if arch.bn:
+                bn = torch.nn.BatchNorm3d(co, eps=1e-5).double().eval()
+                bn.weight.data = torch.from_numpy(w[f"bn{i}.gamma"].astype(np.float64))
+                bn.bias.data = torch.from_numpy(w[f"bn{i}.beta"].astype(np.float64))
+                bn.running_mean = torch.from_numpy(w[f"bn{i}.mean"].astype(np.float64))
+                bn.running_var = torch.from_numpy(w[f"bn{i}.var"].astype(np.float64))
+            else:
+                bn = torch.nn.Identity()
             self.convs.append(c)
             self.bns.append(bn)
         self.dense = None
-        if arch.cnn_dense:
-            self.dense = torch.nn.Linear(arch.c_last, arch.cnn_dense).double()
-            self.dense.weight.data = torch.from_numpy(w["cnn_dense.w"].astype(np.float64))
-            self.dense.bias.data = torch.from_numpy(w["cnn_dense.b"].astype(np.float64))
+        layers, prev = [], arch.c_last
+        for name in ("cnn_dense", "cnn_dense2"):
+            width = getattr(arch, name)
+            if width:
+                lin = torch.nn.Linear(prev, width).double()
+                lin.weight.data = torch.from_numpy(w[name + ".w"].astype(np.float64))
+                lin.bias.data = torch.from_numpy(w[name + ".b"].astype(np.float64))
+                layers += [lin, torch.nn.ReLU()]
+                prev = width
+        if layers:
+            self.dense = torch.nn.Sequential(*layers)
 
     def forward(self, x):
         ts = [x]
@@ -103,10 +114,10 @@ class _TorchCNN(torch.nn.Module):
                 y = y + ts[r]
             ts.append(torch.relu(y))
         pooled = torch.nn.functional.adaptive_avg_pool3d(ts[-1], 1).flatten(1)
-        return torch.relu(self.dense(pooled)) if self.dense is not None else pooled
+        return self.dense(pooled) if self.dense is not None else pooled
 
 
-@pytest.mark.parametrize("arch_name,G", [("tiny", 12), ("full", 16)])
+@pytest.mark.parametrize("arch_name,G", [("tiny", 12), ("full", 16), ("paper", 16)])
 def test_cnn3d_forward_matches_torch_model(arch_name, G):
     arch = synth.ARCHS[arch_name]
     w = synth.make_weights(arch)
@@ -205,7 +216,7 @@ def _local_graphs(xyz, arch):
     return oracle.radius_graph_pose(xyz, arch.r_cov_u), oracle.radius_graph_pose(xyz, arch.r_nc_u)
 
 
-@pytest.mark.parametrize("arch_name", ["tiny", "full"])
+@pytest.mark.parametrize("arch_name", ["tiny", "full", "paper"])
 def test_sgcnn_invariant_to_atom_order(arch_name):
     arch = synth.ARCHS[arch_name]
     w = synth.make_weights(arch)
@@ -305,3 +316,109 @@ def test_score_pose_composes_the_stages():
     cnn, _ = oracle.cnn3d_forward(oracle.splat_pose(b.xyz, b.feat, d["center"], 24), w, arch)
     sg = oracle.sgcnn_pose(b.feat, b.is_lig, *_local_graphs(b.xyz, arch), w, arch)
     assert s == oracle.fusion_head(cnn, sg, w, arch)
+
+
+# ---------------------------------------------------------------- PotentialNet staging
+
+def _staged(width, K_c=2, K_n=2):
+    """Small staged / unstaged architecture pair with equal stage widths."""
+    import dataclasses
+    base = dataclasses.replace(synth.ARCHS["tiny"], name="t_unstaged", H=width, K_c=K_c, K_n=K_n)
+    return base, dataclasses.replace(base, name="t_staged", H_nc=width)
+
+
+def test_staged_sgcnn_with_pass_through_gather_is_the_unstaged_model():
+    # gate 0 -> sigmoid = 1/2, value 2 I -> the covalent gather returns h exactly,
+    # embedding I -> the non-covalent stage starts from h; with the second block of
+    # the final gate zeroed in both models they compute the same function, so any
+    # misplaced stage, gather or embedding shows up here
+    unst, st = _staged(16)
+    wu = synth.make_weights(unst)
+    ws = dict(synth.make_weights(st))
+    for k, v in wu.items():
+        if k.startswith("sg.") and k in ws and ws[k].shape == v.shape:
+            ws[k] = v
+    H = 16
+    ws["sg.mid.gate.w"] = np.zeros((H, H + 19), np.float32)
+    ws["sg.mid.gate.b"] = np.zeros(H, np.float32)
+    ws["sg.mid.val.w"] = (2 * np.eye(H)).astype(np.float32)
+    ws["sg.mid.val.b"] = np.zeros(H, np.float32)
+    ws["sg.embed2.w"] = np.eye(H, dtype=np.float32)
+    ws["sg.embed2.b"] = np.zeros(H, np.float32)
+    wu = dict(wu)
+    wu["sg.gate.w"] = wu["sg.gate.w"].copy()
+    wu["sg.gate.w"][:, H:] = 0.0
+    ws["sg.gate.w"] = np.concatenate([wu["sg.gate.w"][:, :H], np.zeros((H, H), np.float32)], axis=1)
+    b = synth.make_poses("c1", 1, pose0=2)
+    su = oracle.sgcnn_pose(b.feat, b.is_lig, *_local_graphs(b.xyz, unst), wu, unst)
+    ss = oracle.sgcnn_pose(b.feat, b.is_lig, *_local_graphs(b.xyz, st), ws, st)
+    np.testing.assert_allclose(ss, su, rtol=1e-13, atol=1e-13)
+    # and the gather matters once it is not a pass-through
+    ws["sg.mid.val.b"] = np.full(H, 0.5, np.float32)
+    s2 = oracle.sgcnn_pose(b.feat, b.is_lig, *_local_graphs(b.xyz, st), ws, st)
+    assert np.abs(s2 - su).max() > 1e-6
+
+
+def test_staged_sgcnn_is_unchanged_by_zero_padding_the_covalent_width():
+    # padding the covalent stage from 24 to 32 features with zero weights and
+    # biases leaves the latent unchanged (pad features stay exactly 0 through the
+    # GRU: r = z = 1/2, n = tanh(0) = 0); the GPU path relies on this
+    import dataclasses
+    arch = synth.ARCHS["paper"]
+    w = synth.make_weights(arch)
+    P = 32
+    H, N = arch.H, arch.H_nc
+    wp = dict(w)
+
+    def pad(a, rows=None, cols=None):
+        a = np.asarray(a, np.float32)
+        out = np.zeros((rows if rows else a.shape[0],) + ((cols,) if cols else a.shape[1:]), np.float32)
+        out[tuple(slice(0, d) for d in a.shape)] = a
+        return out
+
+    def pad_gates(a, cols=None):   # [3H, ...] stacked gates r, z, n -> [3P, ...]
+        parts = [pad(a[g * H:(g + 1) * H], P, cols) for g in range(3)]
+        return np.concatenate(parts, axis=0)
+
+    wp["sg.embed.w"] = pad(w["sg.embed.w"], P)
+    wp["sg.embed.b"] = pad(w["sg.embed.b"], P)
+    for t in range(arch.K_c):
+        wp[f"sg.cov.msg{t}.w"] = pad(w[f"sg.cov.msg{t}.w"], P, P)
+    wp["sg.cov.gru.w_ih"] = pad_gates(w["sg.cov.gru.w_ih"], P)
+    wp["sg.cov.gru.w_hh"] = pad_gates(w["sg.cov.gru.w_hh"], P)
+    wp["sg.cov.gru.b_ih"] = pad_gates(w["sg.cov.gru.b_ih"])
+    wp["sg.cov.gru.b_hh"] = pad_gates(w["sg.cov.gru.b_hh"])
+    g = w["sg.mid.gate.w"]
+    gp = np.zeros((P, P + 19), np.float32)
+    gp[:H, :H] = g[:, :H]
+    gp[:H, P:] = g[:, H:]
+    wp["sg.mid.gate.w"] = gp
+    wp["sg.mid.gate.b"] = pad(w["sg.mid.gate.b"], P)
+    wp["sg.mid.val.w"] = pad(w["sg.mid.val.w"], P, P)
+    wp["sg.mid.val.b"] = pad(w["sg.mid.val.b"], P)
+    wp["sg.embed2.w"] = pad(w["sg.embed2.w"], N, P)
+    gg = w["sg.gate.w"]
+    ggp = np.zeros((N, N + P), np.float32)
+    ggp[:, :N] = gg[:, :N]
+    ggp[:, N:N + H] = gg[:, N:]
+    wp["sg.gate.w"] = ggp
+    arch_p = dataclasses.replace(arch, H=P)
+    b = synth.make_poses("c2", 1, pose0=1)
+    s0 = oracle.sgcnn_pose(b.feat, b.is_lig, *_local_graphs(b.xyz, arch), w, arch)
+    s1 = oracle.sgcnn_pose(b.feat, b.is_lig, *_local_graphs(b.xyz, arch_p), wp, arch_p)
+    np.testing.assert_allclose(s1, s0, rtol=1e-12, atol=1e-12 * np.abs(s0).max())
+
+
+def test_second_dense_layer_selecting_units_truncates_the_latent():
+    # dense2 = [I | 0] with zero bias keeps the first units of the (non-negative)
+    # first dense layer's output
+    import dataclasses
+    arch = synth.ARCHS["paper"]
+    w = dict(synth.make_weights(arch))
+    w["cnn_dense2.w"] = np.eye(arch.cnn_dense2, arch.cnn_dense, dtype=np.float32)
+    w["cnn_dense2.b"] = np.zeros(arch.cnn_dense2, np.float32)
+    rng = np.random.default_rng(4)
+    grid = np.abs(rng.standard_normal((12, 12, 12, 19))) * (rng.random((12, 12, 12, 19)) < 0.2)
+    lat2, _ = oracle.cnn3d_forward(grid, w, arch)
+    lat1, _ = oracle.cnn3d_forward(grid, w, dataclasses.replace(arch, cnn_dense2=0))
+    np.testing.assert_array_equal(lat2, lat1[:arch.cnn_dense2])
