@@ -32,8 +32,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def load_golden(cfg, G):
-    path = os.path.join(ROOT, "tests", "golden", f"{cfg}_G{G}_oracle.json")
+def load_golden(cfg, G, tag=""):
+    path = os.path.join(ROOT, "tests", "golden", f"{cfg}_G{G}{tag}_oracle.json")
     if not os.path.exists(path):
         return None
     return json.load(open(path))
@@ -181,6 +181,39 @@ def batching_leg(arch, w, n_poses, steps):
     return dict(poses=n_poses, atoms=int(batch.n_atoms), steps=steps, **res)
 
 
+def paper_leg(db, n_poses, steps):
+    """The paper-shaped model (Sec. 3.3.1, Tables II, III, V) on the same poses:
+    both forms, conv variants autotuned, error against its stored oracle scores."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2104_04547_amd import Scorer
+    arch = synth.ARCHS["paper"]
+    w = synth.make_weights(arch)
+    calib = json.load(open(os.path.join(ROOT, "tests", "golden", "calib.json")))["paper"]
+    w = synth.apply_calibration(w, calib["scale"], calib["shift"])
+    gd = load_golden("c2", 48, "_paper")
+    out = torch.empty(n_poses, dtype=torch.float32, device="cuda")
+    res = {}
+    for prec in ("bf16", "fp32"):
+        s = Scorer(arch, w, prec)
+        try:
+            v = s.autotune(48, 512)
+            sec, stats = time_steps(s, db, 48, steps, 1, out, timing=True)
+            r = dict(poses_per_s=round(n_poses / sec, 2), ms_per_step=round(sec * 1e3, 3), conv_variants=v)
+            st = by_kernel(stats)
+            conv_ms = sum(x["total_ms"] for k, x in st.items() if k.startswith("conv"))
+            r["conv_share"] = round(conv_ms / sum(x["total_ms"] for x in st.values()), 4)
+            r["sgcnn_ms_per_step"] = round(st["sgcnn"]["total_ms"] / steps, 3)
+            if gd is not None:
+                r["error"] = error_stats(out.cpu().numpy().astype(np.float64), gd, min(len(gd["poses"]), n_poses))
+            res[prec] = r
+            log(f"paper model {prec}: {r['poses_per_s']:.1f} poses/s, variants {v}, error {r.get('error')}")
+        finally:
+            s.close()
+    return res
+
+
 def serve_leg(arch, w, res, seconds):
     """Open-loop Poisson serving: requests of U{1..256} poses (200-1500 atoms),
     grid 48^3 or 64^3 per request, continuous batching on 4 slots with hipGraph
@@ -240,6 +273,8 @@ def main():
     ap.add_argument("--batch-poses", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-paper", action="store_true")
+    ap.add_argument("--paper-steps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 10 device copies of MIB MiB (calibrates HBM byte counters) and exit")
     ap.add_argument("--json-out", default="")
@@ -319,6 +354,10 @@ def main():
                          **({"gbs": v["bytes"] / (v["total_ms"] * 1e-3) / 1e9} if v["bytes"] and not v["flop"] else {}))
                  for k, v in sorted(st.items())}
 
+    paper = None
+    if not a.no_paper:
+        paper = paper_leg(db, a.poses, a.paper_steps)
+
     batching = None
     if not a.no_batching:
         batching = batching_leg(arch, w, a.batch_poses, a.batch_steps)
@@ -378,6 +417,8 @@ def main():
                               "dominant_kernel": fdom, "achieved_tflops": round(f_ach, 2),
                               "frac_of_fp32_peak": round(f_ach / PEAK_FP32_TFLOPS, 4)}
         line["speedup_bf16_vs_fp32"] = round(bf["poses_per_s"] / f["poses_per_s"], 3)
+    if paper is not None:
+        line["paper_model"] = paper
     if batching is not None:
         line["batching"] = batching
     if serving is not None:

@@ -101,17 +101,22 @@ typedef struct {
  *   for each conv i: W [c_out][c_in][k][k][k], b [c_out], and if bn:
  *       gamma, beta, running_mean, running_var (each [c_out]);
  *   if cnn_dense: W [cnn_dense][c_out_last], b [cnn_dense];
- *   SG-CNN: embed W [H][19], b [H];
- *       for stage in (covalent, non-covalent): message W_t [H][H] for each of its
- *       K rounds, then GRU w_ih [3H][H], w_hh [3H][H], b_ih [3H], b_hh [3H]
- *       (gate rows stacked r, z, n);
- *       readout gate W [H][H+19], b [H]; readout value W [H][H], b [H];
+ *   if cnn_dense2: W [cnn_dense2][cnn_dense], b [cnn_dense2];
+ *   SG-CNN (S = the SG latent width: H_nc if H_nc > 0, else H):
+ *       embed W [H][19], b [H];
+ *       covalent stage: message W_t [H][H] for each of its K_c rounds, then GRU
+ *       w_ih [3H][H], w_hh [3H][H], b_ih [3H], b_hh [3H] (gate rows stacked r, z, n);
+ *       if H_nc > 0 (PotentialNet staging): covalent gather gate W [H][H+19], b [H],
+ *       value W [H][H], b [H]; embedding W [H_nc][H], b [H_nc];
+ *       non-covalent stage: as the covalent one at width S (K_n rounds);
+ *       readout gate W [S][S+U], b [S] (U = 19, or H with staging: the gate reads
+ *       [h; covalent gather]); readout value W [S][S], b [S];
  *   head CF_HEAD_LATE: 3D-CNN output W [1][latent_cnn], b [1]; for each
  *       sg_dense[j] > 0: W [sg_dense[j]][previous width], b [sg_dense[j]];
  *       SG-CNN output W [1][last width], b [1];
  *   head CF_HEAD_MID: model-specific W [latent_cnn][latent_cnn], b [latent_cnn],
- *       then W [H][H], b [H]; then the fusion block below, its input being
- *       [specific cnn; specific sg; cnn latent; sg latent] (2 (latent_cnn + H));
+ *       then W [S][S], b [S]; then the fusion block below, its input being
+ *       [specific cnn; specific sg; cnn latent; sg latent] (2 (latent_cnn + S));
  *   head CF_HEAD_COHERENT: the fusion block over [cnn latent; sg latent];
  *   fusion block: fusion_layers - 1 hidden layers W [fusion_hidden][input width],
  *       b [fusion_hidden], then output W [1][fusion_hidden or input width], b [1].
@@ -121,10 +126,10 @@ typedef struct {
   uint32_t magic;        /* CF_MODEL_MAGIC */
   int32_t n_ch;          /* must be 19 */
   int32_t n_conv;        /* 1..8 */
-  int32_t conv[8][5];    /* c_in, c_out, k (odd, <= 7), stride (1|2), res_src */
+  int32_t conv[8][5];    /* c_in, c_out, k (3, 5 or 7), stride (1|2), res_src */
   int32_t bn;            /* 1: inference BatchNorm after every conv */
   int32_t cnn_dense;     /* 0: CNN latent = pooled features; else dense + ReLU width */
-  int32_t H;             /* SG-CNN width: 16, 32 or 64 */
+  int32_t H;             /* SG-CNN width: 16, 32 or 64 (covalent stage: 1..64 with H_nc) */
   int32_t K_c, K_n;      /* covalent / non-covalent propagation rounds (<= 8 each) */
   int32_t r_cov_u;       /* covalent cutoff, 2^-10 A */
   int32_t r_nc_u;        /* non-covalent cutoff, 2^-10 A */
@@ -135,6 +140,11 @@ typedef struct {
   int32_t fusion_residual; /* 1: hidden layers after the first add their input */
   int32_t sg_dense[2];   /* CF_HEAD_LATE: SG-CNN dense (ReLU) widths before its
                             output, 0 = absent (a 0 ends the list) */
+  int32_t cnn_dense2;    /* second 3D-CNN dense + ReLU width (needs cnn_dense), 0 = none */
+  int32_t H_nc;          /* 0, or PotentialNet staging (Sec. 3.3.1, Table II gather
+                            widths): the covalent stage (width H) ends in a per-atom
+                            gated gather, embedded to the non-covalent stage's width
+                            H_nc (64 or 128, > H) */
 } cf_model_desc;
 
 /* Create a scoring context on the current device.  Copies the weights (the blob

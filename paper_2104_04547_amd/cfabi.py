@@ -57,7 +57,7 @@ class cf_model_desc(ctypes.Structure):
                 ("H", ctypes.c_int32), ("K_c", ctypes.c_int32), ("K_n", ctypes.c_int32),
                 ("r_cov_u", ctypes.c_int32), ("r_nc_u", ctypes.c_int32), ("fusion_hidden", ctypes.c_int32),
                 ("head", ctypes.c_int32), ("fusion_layers", ctypes.c_int32), ("fusion_residual", ctypes.c_int32),
-                ("sg_dense", ctypes.c_int32 * 2)]
+                ("sg_dense", ctypes.c_int32 * 2), ("cnn_dense2", ctypes.c_int32), ("H_nc", ctypes.c_int32)]
 
 
 class cf_kernel_stat(ctypes.Structure):
@@ -156,6 +156,8 @@ def model_desc(arch) -> cf_model_desc:
         raise ValueError("at most two SG-CNN dense layers")
     for j, v in enumerate(arch.sg_dense):
         d.sg_dense[j] = int(v)
+    d.cnn_dense2 = arch.cnn_dense2
+    d.H_nc = arch.H_nc
     return d
 
 
@@ -168,8 +170,12 @@ def blob_param_order(arch):
             names += [f"bn{i}.gamma", f"bn{i}.beta", f"bn{i}.mean", f"bn{i}.var"]
     if arch.cnn_dense:
         names += ["cnn_dense.w", "cnn_dense.b"]
+    if arch.cnn_dense2:
+        names += ["cnn_dense2.w", "cnn_dense2.b"]
     names += ["sg.embed.w", "sg.embed.b"]
     for stage, K in (("cov", arch.K_c), ("nc", arch.K_n)):
+        if stage == "nc" and arch.H_nc:
+            names += ["sg.mid.gate.w", "sg.mid.gate.b", "sg.mid.val.w", "sg.mid.val.b", "sg.embed2.w", "sg.embed2.b"]
         names += [f"sg.{stage}.msg{t}.w" for t in range(K)]
         names += [f"sg.{stage}.gru.w_ih", f"sg.{stage}.gru.w_hh", f"sg.{stage}.gru.b_ih", f"sg.{stage}.gru.b_hh"]
     names += ["sg.gate.w", "sg.gate.b", "sg.val.w", "sg.val.b"]

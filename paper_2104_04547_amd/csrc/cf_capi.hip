@@ -53,6 +53,10 @@ struct cf_ctx {
   int lc = 0;  // CNN latent width
   int c_last = 0;
   float *dense_w = nullptr, *dense_b = nullptr;
+  float *dense2_w = nullptr, *dense2_b = nullptr;
+  int sgw = 0;              // SG-CNN latent width
+  int64_t sg_floats = 0;    // SG-CNN state floats per atom (scratch)
+  double sg_flop_atom = 0;  // SG-CNN FLOPs per atom (timing only)
   cf::SgWeights sg{};
   cf::HeadProgram head{};  // fusion head compiled to dense layers
   float *head_prm = nullptr;
@@ -161,7 +165,7 @@ int64_t scratch_after(const cf_ctx *c, int G, int64_t n, int64_t atoms) {
   }
   grow(c->centers, n * 3 * 4);
   grow(c->cnn_lat, n * c->lc * 4);
-  grow(c->sg_lat, n * c->desc.H * 4);
+  grow(c->sg_lat, n * c->sgw * 4);
   if (atoms > 0) {
     grow(c->deg, 2 * atoms * 4);
     grow(c->pose_tot, 4 * n * 8);
@@ -169,7 +173,7 @@ int64_t scratch_after(const cf_ctx *c, int G, int64_t n, int64_t atoms) {
     grow(c->nc_row, (atoms + 1) * 4);
     grow(c->cov_col, atoms * 16 * 4);
     grow(c->nc_col, atoms * 96 * 4);
-    grow(c->hbuf, 2 * atoms * c->desc.H * 4);
+    grow(c->hbuf, atoms * c->sg_floats * 4);
   }
   return t;
 }
@@ -263,7 +267,7 @@ int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s) {
   const auto &Ll = c->conv.back();
   hipEvent_t e = tbegin(c, s);
   CF_HIP(cf::launch_pool_dense(t.back(), c->bf16, np, D * D * D, Ll.cout_store, Ll.cout, c->dense_w, c->dense_b,
-                               c->desc.cnn_dense, cnn_lat, s));
+                               c->desc.cnn_dense, c->dense2_w, c->dense2_b, c->desc.cnn_dense2, cnn_lat, s));
   tend(c, s, e, "pool_dense", 0.0, (double)D * D * D * np * Ll.cout * elem_size(c));
   return CF_OK;
 }
@@ -361,14 +365,14 @@ int upload_split(cf_ctx *c, const float *W, int N, int K, const bf16_t **hi, con
   return CF_OK;
 }
 
-static_assert(sizeof(cf_model_desc) == 4 * (3 + 40 + 8 + 5), "cf_model_desc layout");
+static_assert(sizeof(cf_model_desc) == 4 * (3 + 40 + 8 + 7), "cf_model_desc layout");
 
 // Compile the model's fusion head (Coherent, Mid-level or Late Fusion) into a
 // list of dense layers over the per-pose buffer [cnn latent | sg latent | ...]
 // and upload its parameters as one array.
 int build_head(cf_ctx *c, BlobReader &R) {
   const cf_model_desc &d = c->desc;
-  const int lc = c->lc, H = d.H;
+  const int lc = c->lc, H = c->sgw;
   cf::HeadProgram &hp = c->head;
   hp = cf::HeadProgram{};
   std::vector<float> prm;
@@ -438,7 +442,12 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
   if (d.magic != CF_MODEL_MAGIC) return fail(CF_ERR_INVALID_ARG, "bad model magic");
   if (d.n_ch != CF_NCH) return fail(CF_ERR_INVALID_ARG, "model must take 19 feature channels");
   if (d.n_conv < 1 || d.n_conv > 8) return fail(CF_ERR_INVALID_ARG, "n_conv must be 1..8");
-  if (d.H != 16 && d.H != 32 && d.H != 64) return fail(CF_ERR_UNSUPPORTED, "H must be 16, 32 or 64");
+  if (d.H_nc == 0 && d.H != 16 && d.H != 32 && d.H != 64)
+    return fail(CF_ERR_UNSUPPORTED, "H must be 16, 32 or 64 (without PotentialNet staging)");
+  if (d.H_nc != 0 && (d.H < 1 || d.H > 64 || !cf::sgcnn_staged_supported(d.H <= 32 ? 32 : 64, d.H_nc)))
+    return fail(CF_ERR_UNSUPPORTED, "staged SG-CNN widths must be H <= 64 and H_nc in {64, 128} (H_nc > H)");
+  if (d.cnn_dense2 < 0 || d.cnn_dense2 > 256 || (d.cnn_dense2 && !d.cnn_dense))
+    return fail(CF_ERR_INVALID_ARG, "cnn_dense2 needs cnn_dense and must be <= 256");
   if (d.K_c < 0 || d.K_n < 0 || d.K_c > 8 || d.K_n > 8) return fail(CF_ERR_INVALID_ARG, "K_c, K_n must be 0..8");
   if (d.r_cov_u <= 0 || d.r_nc_u <= 0 || d.r_cov_u > 65536 || d.r_nc_u > 65536)
     return fail(CF_ERR_INVALID_ARG, "cutoffs must be 1..65536 u");
@@ -463,7 +472,7 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     const int ci = d.conv[i][0], co = d.conv[i][1], k = d.conv[i][2], st = d.conv[i][3], rs = d.conv[i][4];
     if (ci != cin) return fail(CF_ERR_INVALID_ARG, "conv input channels do not chain");
     if (co < 1 || co > 256) return fail(CF_ERR_INVALID_ARG, "conv output channels must be 1..256");
-    if ((k != 5 && k != 7)) return fail(CF_ERR_UNSUPPORTED, "conv kernel size must be 5 or 7");
+    if (k != 3 && k != 5 && k != 7) return fail(CF_ERR_UNSUPPORTED, "conv kernel size must be 3, 5 or 7");
     if (st != 1 && st != 2) return fail(CF_ERR_INVALID_ARG, "conv stride must be 1 or 2");
     if (rs >= 0) {
       if (rs > i || chans[rs] != co) return fail(CF_ERR_INVALID_ARG, "residual source must match channels");
@@ -532,68 +541,110 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     if ((rc = upload_f(c, &c->dense_w, W, (size_t)d.cnn_dense * c->c_last))) return rc;
     if ((rc = upload_f(c, &c->dense_b, b, d.cnn_dense))) return rc;
     c->lc = d.cnn_dense;
+    if (d.cnn_dense2) {
+      const float *W2 = R.take((size_t)d.cnn_dense2 * d.cnn_dense), *b2 = R.take(d.cnn_dense2);
+      if (!W2 || !b2) return fail(CF_ERR_INVALID_ARG, "blob truncated (cnn dense2)");
+      if ((rc = upload_f(c, &c->dense2_w, W2, (size_t)d.cnn_dense2 * d.cnn_dense))) return rc;
+      if ((rc = upload_f(c, &c->dense2_b, b2, d.cnn_dense2))) return rc;
+      c->lc = d.cnn_dense2;
+    }
   } else {
     c->lc = c->c_last;
   }
-  const int H = d.H;
+  // SG-CNN.  With PotentialNet staging the covalent stage's width is padded with
+  // zero weights to the kernel width (pad features stay exactly 0: their GRU
+  // update is (1 - 1/2) tanh(0) + h / 2 with h = 0) and the non-covalent stage
+  // runs at H_nc.
+  const bool staged = d.H_nc > 0;
+  const int Hm[2] = {d.H, staged ? d.H_nc : d.H};          // stage widths in the blob
+  const int Hp = staged ? (d.H <= 32 ? 32 : 64) : d.H;
+  const int Hs[2] = {Hp, staged ? d.H_nc : Hp};             // stage widths in the kernels
   cf::SgWeights &S = c->sg;
-  S.H = H;
+  S.H = Hp;
+  S.H2 = Hs[1];
+  S.staged = staged;
   S.K_c = d.K_c;
   S.K_n = d.K_n;
-  {
-    const float *W = R.take((size_t)H * CF_NCH), *b = R.take(H);
-    if (!W || !b) return fail(CF_ERR_INVALID_ARG, "blob truncated (embed)");
-    auto t = transpose(W, H, CF_NCH);
+  c->sgw = Hs[1];
+  c->sg_floats = staged ? 2 * (int64_t)Hs[1] + Hp : 2 * (int64_t)Hp;
+  c->sg_flop_atom = 2.0 * (CF_NCH * Hp + d.K_c * 7.0 * Hp * Hp + d.K_n * 7.0 * Hs[1] * Hs[1] +
+                           (staged ? (2.0 * Hp + CF_NCH) * Hp + (double)Hp * Hs[1] : 0.0));
+  // W [rows][cols] -> zero-padded [prows][pcols]; source column q goes to q < split ? q : q + shift
+  auto padm = [](const float *W, int rows, int cols, int prows, int pcols, int split, int shift) {
+    std::vector<float> o((size_t)prows * pcols, 0.0f);
+    for (int r = 0; r < rows; ++r)
+      for (int q = 0; q < cols; ++q) o[(size_t)r * pcols + (q < split ? q : q + shift)] = W[(size_t)r * cols + q];
+    return o;
+  };
+  // stacked gates [3h][cols] -> [3hp][pcols], each gate's rows padded
+  auto padg = [](const float *W, int h, int cols, int hp, int pcols) {
+    std::vector<float> o((size_t)3 * hp * pcols, 0.0f);
+    for (int g = 0; g < 3; ++g)
+      for (int r = 0; r < h; ++r)
+        for (int q = 0; q < cols; ++q) o[((size_t)g * hp + r) * pcols + q] = W[((size_t)g * h + r) * cols + q];
+    return o;
+  };
+  auto put = [&](const std::vector<float> &v, const float **dst) -> int {
     float *p;
-    if ((rc = upload_f(c, &p, t.data(), t.size()))) return rc;
-    S.embed_wT = p;
-    if ((rc = upload_f(c, &p, b, H))) return rc;
-    S.embed_b = p;
+    int e = upload_f(c, &p, v.data(), v.size());
+    *dst = p;
+    return e;
+  };
+  {
+    const float *W = R.take((size_t)Hm[0] * CF_NCH), *b = R.take(Hm[0]);
+    if (!W || !b) return fail(CF_ERR_INVALID_ARG, "blob truncated (embed)");
+    if ((rc = put(transpose(padm(W, Hm[0], CF_NCH, Hp, CF_NCH, CF_NCH, 0).data(), Hp, CF_NCH), &S.embed_wT))) return rc;
+    if ((rc = put(padm(b, 1, Hm[0], 1, Hp, Hm[0], 0), &S.embed_b))) return rc;
   }
   int r = 0;
   for (int stage = 0; stage < 2; ++stage) {
+    const int h = Hm[stage], hp = Hs[stage];
+    if (stage == 1 && staged) {
+      const int H = d.H;
+      const float *gw = R.take((size_t)H * (H + CF_NCH)), *gb = R.take(H);
+      const float *vw = R.take((size_t)H * H), *vb = R.take(H);
+      const float *ew = R.take((size_t)d.H_nc * H), *eb = R.take(d.H_nc);
+      if (!gw || !gb || !vw || !vb || !ew || !eb) return fail(CF_ERR_INVALID_ARG, "blob truncated (covalent gather)");
+      if ((rc = put(transpose(padm(gw, H, H + CF_NCH, Hp, Hp + CF_NCH, H, Hp - H).data(), Hp, Hp + CF_NCH),
+                    &S.mid_gate_wT)))
+        return rc;
+      if ((rc = put(padm(gb, 1, H, 1, Hp, H, 0), &S.mid_gate_b))) return rc;
+      if ((rc = put(transpose(padm(vw, H, H, Hp, Hp, H, 0).data(), Hp, Hp), &S.mid_val_wT))) return rc;
+      if ((rc = put(padm(vb, 1, H, 1, Hp, H, 0), &S.mid_val_b))) return rc;
+      if ((rc = put(transpose(padm(ew, d.H_nc, H, d.H_nc, Hp, H, 0).data(), d.H_nc, Hp), &S.embed2_wT))) return rc;
+      if ((rc = put(std::vector<float>(eb, eb + d.H_nc), &S.embed2_b))) return rc;
+    }
     const int K = stage ? d.K_n : d.K_c;
     for (int q = 0; q < K; ++q, ++r) {
-      const float *W = R.take((size_t)H * H);
+      const float *W = R.take((size_t)h * h);
       if (!W) return fail(CF_ERR_INVALID_ARG, "blob truncated (message)");
-      auto t = transpose(W, H, H);
-      float *p;
-      if ((rc = upload_f(c, &p, t.data(), t.size()))) return rc;
-      S.msgT[r] = p;
-      if (c->bf16 && H >= 32 && (rc = upload_split(c, W, H, H, &S.msg_hi[r], &S.msg_lo[r]))) return rc;
+      const auto Wp = padm(W, h, h, hp, hp, h, 0);
+      if ((rc = put(transpose(Wp.data(), hp, hp), &S.msgT[r]))) return rc;
+      if (c->bf16 && hp >= 32 && (rc = upload_split(c, Wp.data(), hp, hp, &S.msg_hi[r], &S.msg_lo[r]))) return rc;
     }
-    const float *wih = R.take((size_t)3 * H * H), *whh = R.take((size_t)3 * H * H);
-    const float *bih = R.take(3 * H), *bhh = R.take(3 * H);
+    const float *wih = R.take((size_t)3 * h * h), *whh = R.take((size_t)3 * h * h);
+    const float *bih = R.take(3 * h), *bhh = R.take(3 * h);
     if (!wih || !whh || !bih || !bhh) return fail(CF_ERR_INVALID_ARG, "blob truncated (gru)");
-    auto ti = transpose(wih, 3 * H, H), th = transpose(whh, 3 * H, H);
-    float *p;
-    if ((rc = upload_f(c, &p, ti.data(), ti.size()))) return rc;
-    S.w_ihT[stage] = p;
-    if ((rc = upload_f(c, &p, th.data(), th.size()))) return rc;
-    S.w_hhT[stage] = p;
-    if ((rc = upload_f(c, &p, bih, 3 * H))) return rc;
-    S.b_ih[stage] = p;
-    if ((rc = upload_f(c, &p, bhh, 3 * H))) return rc;
-    S.b_hh[stage] = p;
-    if (c->bf16 && H >= 32) {
-      if ((rc = upload_split(c, wih, 3 * H, H, &S.ih_hi[stage], &S.ih_lo[stage]))) return rc;
-      if ((rc = upload_split(c, whh, 3 * H, H, &S.hh_hi[stage], &S.hh_lo[stage]))) return rc;
+    const auto wi = padg(wih, h, h, hp, hp), wh = padg(whh, h, h, hp, hp);
+    if ((rc = put(transpose(wi.data(), 3 * hp, hp), &S.w_ihT[stage]))) return rc;
+    if ((rc = put(transpose(wh.data(), 3 * hp, hp), &S.w_hhT[stage]))) return rc;
+    if ((rc = put(padg(bih, h, 1, hp, 1), &S.b_ih[stage]))) return rc;
+    if ((rc = put(padg(bhh, h, 1, hp, 1), &S.b_hh[stage]))) return rc;
+    if (c->bf16 && hp >= 32) {
+      if ((rc = upload_split(c, wi.data(), 3 * hp, hp, &S.ih_hi[stage], &S.ih_lo[stage]))) return rc;
+      if ((rc = upload_split(c, wh.data(), 3 * hp, hp, &S.hh_hi[stage], &S.hh_lo[stage]))) return rc;
     }
   }
   {
-    const float *gw = R.take((size_t)H * (H + CF_NCH)), *gb = R.take(H);
-    const float *vw = R.take((size_t)H * H), *vb = R.take(H);
+    // readout gate over [h; u]: u = the raw features, or (staged) the covalent gather
+    const int h = Hm[1], hp = Hs[1], u = staged ? d.H : CF_NCH, up = staged ? Hp : CF_NCH;
+    const float *gw = R.take((size_t)h * (h + u)), *gb = R.take(h);
+    const float *vw = R.take((size_t)h * h), *vb = R.take(h);
     if (!gw || !gb || !vw || !vb) return fail(CF_ERR_INVALID_ARG, "blob truncated (readout)");
-    auto tg = transpose(gw, H, H + CF_NCH), tv = transpose(vw, H, H);
-    float *p;
-    if ((rc = upload_f(c, &p, tg.data(), tg.size()))) return rc;
-    S.gate_wT = p;
-    if ((rc = upload_f(c, &p, gb, H))) return rc;
-    S.gate_b = p;
-    if ((rc = upload_f(c, &p, tv.data(), tv.size()))) return rc;
-    S.val_wT = p;
-    if ((rc = upload_f(c, &p, vb, H))) return rc;
-    S.val_b = p;
+    if ((rc = put(transpose(padm(gw, h, h + u, hp, hp + up, h, hp - h).data(), hp, hp + up), &S.gate_wT))) return rc;
+    if ((rc = put(padm(gb, 1, h, 1, hp, h, 0), &S.gate_b))) return rc;
+    if ((rc = put(transpose(padm(vw, h, h, hp, hp, h, 0).data(), hp, hp), &S.val_wT))) return rc;
+    if ((rc = put(padm(vb, 1, h, 1, hp, h, 0), &S.val_b))) return rc;
   }
   if ((rc = build_head(c, R))) return rc;
   if (R.left != 0) return fail(CF_ERR_INVALID_ARG, "blob has trailing data");
@@ -616,14 +667,13 @@ void free_ctx(cf_ctx *c) {
 // per-atom scratch for a pose range holding at most `atoms` atoms
 int ensure_atoms(cf_ctx *c, int64_t atoms, int np) {
   int rc;
-  const int H = c->desc.H;
   if ((rc = ensure(c, c->deg, (size_t)2 * atoms * sizeof(int32_t)))) return rc;
   if ((rc = ensure(c, c->pose_tot, (size_t)4 * np * sizeof(int64_t)))) return rc;
   if ((rc = ensure(c, c->cov_row, (size_t)(atoms + 1) * sizeof(int32_t)))) return rc;
   if ((rc = ensure(c, c->nc_row, (size_t)(atoms + 1) * sizeof(int32_t)))) return rc;
   if ((rc = ensure(c, c->cov_col, (size_t)atoms * 16 * sizeof(int32_t)))) return rc;
   if ((rc = ensure(c, c->nc_col, (size_t)atoms * 96 * sizeof(int32_t)))) return rc;
-  if ((rc = ensure(c, c->hbuf, (size_t)2 * atoms * H * sizeof(float)))) return rc;
+  if ((rc = ensure(c, c->hbuf, (size_t)atoms * c->sg_floats * sizeof(float)))) return rc;
   return CF_OK;
 }
 
@@ -679,7 +729,7 @@ void cf_destroy(cf_ctx *c) {
 int cf_model_info(const cf_ctx *c, int32_t *latent_cnn, int32_t *latent_sg, int64_t *n_params, int32_t *precision) {
   if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
   if (latent_cnn) *latent_cnn = c->lc;
-  if (latent_sg) *latent_sg = c->desc.H;
+  if (latent_sg) *latent_sg = c->sgw;
   if (n_params) *n_params = c->n_params;
   if (precision) *precision = c->bf16 ? CF_PREC_BF16 : CF_PREC_FP32;
   return CF_OK;
@@ -754,12 +804,12 @@ int cf_sgcnn_fwd(cf_ctx *c, const cf_pose_batch *b, const cf_csr *cov, const cf_
   hipStream_t s = (hipStream_t)stream;
   const int chunk = std::min(b->n_poses, 512);
   const int64_t acap = atoms_cap_for(b, chunk);
-  if ((rc = ensure(c, c->hbuf, (size_t)2 * acap * c->desc.H * sizeof(float)))) return rc;
+  if ((rc = ensure(c, c->hbuf, (size_t)acap * c->sg_floats * sizeof(float)))) return rc;
   for (int p0 = 0; p0 < b->n_poses; p0 += chunk) {
     const int np = std::min(chunk, b->n_poses - p0);
     CF_HIP(cf::launch_sgcnn(c->sg, c->bf16, b->atom_off, b->n_atoms, b->feat, b->is_lig, p0, np, cov->row_ptr, cov->col,
                             cov->capacity, nc->row_ptr, nc->col, nc->capacity, 1, (float *)c->hbuf.p, acap,
-                            sg_latent + (size_t)p0 * c->desc.H, c->status, s));
+                            sg_latent + (size_t)p0 * c->sgw, c->status, s));
   }
   return CF_OK;
 }
@@ -768,7 +818,7 @@ int cf_fusion_fwd(cf_ctx *c, const float *cnn_latent, const float *sg_latent, in
                   void *stream) {
   if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
   if (!cnn_latent || !sg_latent || !scores || n_poses < 1) return fail(CF_ERR_INVALID_ARG, "bad arguments");
-  CF_HIP(cf::launch_head(cnn_latent, c->lc, sg_latent, c->desc.H, c->head_prm, c->head, n_poses, scores,
+  CF_HIP(cf::launch_head(cnn_latent, c->lc, sg_latent, c->sgw, c->head_prm, c->head, n_poses, scores,
                          (hipStream_t)stream));
   return CF_OK;
 }
@@ -786,8 +836,8 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
   if ((rc = ensure_atoms(c, acap, chunk))) return rc;
   if ((rc = ensure(c, c->centers, (size_t)chunk * 3 * sizeof(int32_t)))) return rc;
   if ((rc = ensure(c, c->cnn_lat, (size_t)chunk * c->lc * sizeof(float)))) return rc;
-  if ((rc = ensure(c, c->sg_lat, (size_t)chunk * c->desc.H * sizeof(float)))) return rc;
-  const int H = c->desc.H;
+  if ((rc = ensure(c, c->sg_lat, (size_t)chunk * c->sgw * sizeof(float)))) return rc;
+  const int H = c->sgw;
   for (int p0 = 0; p0 < b->n_poses; p0 += chunk) {
     const int np = std::min(chunk, b->n_poses - p0);
     const int32_t *cen;
@@ -814,10 +864,7 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
     CF_HIP(cf::launch_sgcnn(c->sg, c->bf16, b->atom_off, b->n_atoms, b->feat, b->is_lig, p0, np, (int32_t *)c->cov_row.p,
                             (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
                             acap * 96, 0, (float *)c->hbuf.p, acap, (float *)c->sg_lat.p, c->status, s));
-    {
-      const double Hd = H, rounds = c->desc.K_c + c->desc.K_n;
-      tend(c, s, e, "sgcnn", atoms * (2.0 * CF_NCH * Hd + rounds * 2.0 * (Hd * Hd + 6.0 * Hd * Hd)), atoms * 4.0 * CF_NCH);
-    }
+    tend(c, s, e, "sgcnn", atoms * c->sg_flop_atom, atoms * 4.0 * CF_NCH);
     e = tbegin(c, s);
     CF_HIP(cf::launch_head((float *)c->cnn_lat.p, c->lc, (float *)c->sg_lat.p, H, c->head_prm, c->head, np,
                            scores + p0, s));

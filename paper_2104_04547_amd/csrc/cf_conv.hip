@@ -67,9 +67,9 @@ __global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, cons
   constexpr int CC = C::CC;
   __shared__ __attribute__((aligned(16))) char lds[C::LDS];
 
-  const int tile = blockIdx.x;
-  const int pose = blockIdx.y;
-  const int n0 = blockIdx.z * NT;
+  int tile, pose, nblk;
+  xcd_order(tile, pose, nblk);
+  const int n0 = nblk * NT;
   const int tz0 = (tile / (nty * ntx)) * TZ, ty0 = ((tile / ntx) % nty) * TY, tx0 = (tile % ntx) * TX;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int khalf = lane >> 5, lrow = lane & 31;
@@ -305,9 +305,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
                                                     int ntx, int wbytes) {
   using C = Conv8Cfg<KS, S, TZ, TY, TX, NW, NT>;
   __shared__ __attribute__((aligned(16))) char lds[C::LDS];
-  const int tile = blockIdx.x;
-  const int pose = blockIdx.y;
-  const int n0 = blockIdx.z * NT;
+  int tile, pose, nblk;
+  xcd_order(tile, pose, nblk);
+  const int n0 = nblk * NT;
   const int tz0 = (tile / (nty * ntx)) * TZ, ty0 = ((tile / ntx) % nty) * TY, tx0 = (tile % ntx) * TX;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int khalf = lane >> 5, lrow = lane & 31;
@@ -568,6 +568,19 @@ const Variant kVariants[] = {
     CF_VARIANT8(7, 2, 8, 8, 8, 4, 64),  // 20: stride-2 first layer, 512-row tile
     CF_VARIANT8(7, 1, 8, 8, 8, 8, 64),  // 21
     CF_VARIANT8(7, 2, 4, 4, 12, 6, 128), // 22: 12^3 outputs of a 24^3 input in 9 whole tiles
+    // 5^3 and 3^3 kernels (the paper-shaped model: 32 filters of 5^3, 64 of 3^3)
+    CF_VARIANT8(5, 2, 8, 8, 8, 4, 32),   // 23
+    CF_VARIANT8(5, 2, 4, 8, 8, 4, 32),   // 24
+    CF_VARIANT8(5, 1, 4, 8, 8, 2, 32),   // 25
+    CF_VARIANT8(3, 1, 8, 8, 8, 4, 64),   // 26
+    CF_VARIANT8(3, 1, 4, 8, 8, 4, 64),   // 27
+    CF_VARIANT8(3, 2, 8, 8, 8, 4, 64),   // 28
+    CF_VARIANT8(3, 2, 4, 8, 8, 4, 64),   // 29
+    CF_VARIANT(5, 2, 4, 8, 8, 4, 32),    // 30
+    CF_VARIANT(3, 1, 8, 8, 8, 4, 64),    // 31
+    CF_VARIANT(3, 1, 4, 8, 8, 4, 64),    // 32
+    CF_VARIANT(3, 2, 4, 8, 8, 4, 64),    // 33
+    CF_VARIANT(3, 2, 4, 4, 8, 4, 64),    // 34
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -588,7 +601,8 @@ int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
   (void)D_in;
   // measured on MI355X at 48^3 (bf16: tap pairs for stride 1 and the 128-column
   // stride-2 layer; fp32 has no tap-pair kernel)
-  const int pref[] = {12, 17, 20, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 19, 21, 22};
+  const int pref[] = {12, 17, 20, 19, 23, 26, 28, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 21, 22,
+                      24, 25, 27, 29, 30, 31, 32, 33, 34};
   for (int v : pref)
     if (conv_variant_ok(v, L, bf16)) return v;
   return -1;

@@ -21,9 +21,12 @@ constexpr float kSeluAlpha = 1.6732632423543772848170429916717f;
 template <typename T>
 __global__ __launch_bounds__(256) void k_pool_dense(const T *__restrict__ act, int vox, int cstride, int c,
                                                     const float *__restrict__ dw, const float *__restrict__ db,
-                                                    int n_dense, float *__restrict__ latent) {
+                                                    int n_dense, const float *__restrict__ dw2,
+                                                    const float *__restrict__ db2, int n_dense2,
+                                                    float *__restrict__ latent) {
   __shared__ float part[4][256];
   __shared__ float mean[256];
+  __shared__ float hid[256];
   const int pose = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const T *a = act + (int64_t)pose * vox * cstride;
@@ -45,11 +48,23 @@ __global__ __launch_bounds__(256) void k_pool_dense(const T *__restrict__ act, i
   __syncthreads();
   if (n_dense == 0) {
     for (int ch = threadIdx.x; ch < c; ch += 256) latent[(int64_t)pose * c + ch] = mean[ch];
-  } else {
+  } else if (n_dense2 == 0) {
     for (int o = threadIdx.x; o < n_dense; o += 256) {
       float acc = db[o];
       for (int k = 0; k < c; ++k) acc += dw[o * c + k] * mean[k];
       latent[(int64_t)pose * n_dense + o] = acc > 0.f ? acc : 0.f;
+    }
+  } else {
+    for (int o = threadIdx.x; o < n_dense; o += 256) {
+      float acc = db[o];
+      for (int k = 0; k < c; ++k) acc += dw[o * c + k] * mean[k];
+      hid[o] = acc > 0.f ? acc : 0.f;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < n_dense2; o += 256) {
+      float acc = db2[o];
+      for (int k = 0; k < n_dense; ++k) acc += dw2[o * n_dense + k] * hid[k];
+      latent[(int64_t)pose * n_dense2 + o] = acc > 0.f ? acc : 0.f;
     }
   }
 }
@@ -91,16 +106,16 @@ __global__ __launch_bounds__(64) void k_head(const float *__restrict__ cnn, int 
 }  // namespace
 
 hipError_t launch_pool_dense(const void *act, int bf16, int n_poses, int vox, int cstride, int c,
-                             const float *dense_w, const float *dense_b, int n_dense, float *latent,
-                             hipStream_t s) {
+                             const float *dense_w, const float *dense_b, int n_dense, const float *dense2_w,
+                             const float *dense2_b, int n_dense2, float *latent, hipStream_t s) {
   if (n_poses <= 0) return hipSuccess;
-  if (c > 256 || n_dense > 256) return hipErrorInvalidValue;
+  if (c > 256 || n_dense > 256 || n_dense2 > 256 || (n_dense2 && !n_dense)) return hipErrorInvalidValue;
   if (bf16)
     hipLaunchKernelGGL(k_pool_dense<bf16_t>, dim3(n_poses), dim3(256), 0, s, reinterpret_cast<const bf16_t *>(act),
-                       vox, cstride, c, dense_w, dense_b, n_dense, latent);
+                       vox, cstride, c, dense_w, dense_b, n_dense, dense2_w, dense2_b, n_dense2, latent);
   else
     hipLaunchKernelGGL(k_pool_dense<float>, dim3(n_poses), dim3(256), 0, s, reinterpret_cast<const float *>(act),
-                       vox, cstride, c, dense_w, dense_b, n_dense, latent);
+                       vox, cstride, c, dense_w, dense_b, n_dense, dense2_w, dense2_b, n_dense2, latent);
   return hipGetLastError();
 }
 

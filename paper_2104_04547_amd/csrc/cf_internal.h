@@ -44,6 +44,24 @@ __device__ inline bool pose_range(const int32_t *atom_off, int p, int n_atoms, i
   return ok;
 }
 
+// Work order that keeps neighbouring work on one XCD.  The dispatcher hands
+// consecutive workgroups of a grid to the chip's 8 XCDs in turn, and each XCD has
+// its own L2: renumber the linear workgroup id so that every XCD receives a
+// contiguous range of the logical order (z fastest, then x, then y -- for the
+// conv kernels: output-channel block, tile, pose), so that the tiles of a pose,
+// which share halo voxels, run under one L2.
+__device__ inline void xcd_order(int &x, int &y, int &z) {
+  constexpr int kXcd = 8;
+  const int gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const int n = gx * gy * gz;
+  const int L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int q = n / kXcd, r = n % kXcd, xcd = L % kXcd, k = L / kXcd;
+  const int l = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
+  z = l % gz;
+  x = (l / gz) % gx;
+  y = l / (gz * gx);
+}
+
 // ---- per-layer conv launch description (host side) ----
 struct ConvLayer {
   int cin, cout, k, stride, res_src;
@@ -80,24 +98,32 @@ hipError_t launch_conv(int variant, const ConvLayer &L, int bf16, const void *in
                        void *out, int n_poses, int D_in, hipStream_t s);
 
 hipError_t launch_pool_dense(const void *act, int bf16, int n_poses, int vox, int cstride, int c,
-                             const float *dense_w, const float *dense_b, int n_dense, float *latent,
-                             hipStream_t s);
+                             const float *dense_w, const float *dense_b, int n_dense, const float *dense2_w,
+                             const float *dense2_b, int n_dense2, float *latent, hipStream_t s);
 
 // SG-CNN weights on the device, transposed to [k][out] so that consecutive lanes
 // (consecutive outputs) read consecutive words.
+// Widths: H is the covalent stage's (padded with zero weights to a kernel width),
+// H2 the non-covalent stage's (= H without staging).  "Stage s width" below is
+// H for s = 0 and H2 for s = 1; the readout runs at H2.
 struct SgWeights {
   int H, K_c, K_n;
+  int H2;                           // non-covalent stage width
+  int staged;                       // PotentialNet staging: per-atom gather between the stages
   const float *embed_wT, *embed_b;  // [19][H], [H]
-  const float *msgT[16];            // per round [H][H] (covalent rounds first)
-  const float *w_ihT[2], *w_hhT[2]; // per stage [H][3H] (gate columns r, z, n)
-  const float *b_ih[2], *b_hh[2];   // per stage [3H]
-  const float *gate_wT, *gate_b;    // [H+19][H], [H]
-  const float *val_wT, *val_b;      // [H][H], [H]
+  const float *msgT[16];            // per round [Hs][Hs] (covalent rounds first)
+  const float *w_ihT[2], *w_hhT[2]; // per stage [Hs][3Hs] (gate columns r, z, n)
+  const float *b_ih[2], *b_hh[2];   // per stage [3Hs]
+  const float *gate_wT, *gate_b;    // [H2+U][H2], [H2]; U = 19 (raw features) or H (staged: the gather)
+  const float *val_wT, *val_b;      // [H2][H2], [H2]
+  const float *mid_gate_wT, *mid_gate_b;  // staged: [H+19][H], [H]
+  const float *mid_val_wT, *mid_val_b;    // staged: [H][H], [H]
+  const float *embed2_wT, *embed2_b;      // staged: [H][H2], [H2]
   // precision form (H >= 32): split-bfloat16 copies (hi = bf16(w), lo = bf16(w - hi))
   // packed as MFMA B operands, [K/16][N][16] with element [ks][n][e] = W[n][16 ks + e]
-  const bf16_t *msg_hi[16], *msg_lo[16];  // N = H
-  const bf16_t *ih_hi[2], *ih_lo[2];      // N = 3H
-  const bf16_t *hh_hi[2], *hh_lo[2];      // N = 3H
+  const bf16_t *msg_hi[16], *msg_lo[16];  // N = Hs
+  const bf16_t *ih_hi[2], *ih_lo[2];      // N = 3Hs
+  const bf16_t *hh_hi[2], *hh_lo[2];      // N = 3Hs
 };
 // csr_global = 1: rows indexed by global atom id and columns are global ids (the
 // public neighbour-list layout); 0: both are relative to the first atom of pose p0.
@@ -106,6 +132,9 @@ hipError_t launch_sgcnn(const SgWeights &W, int bf16, const int32_t *atom_off, i
                         const int32_t *cov_col, int64_t cov_cap, const int32_t *nc_row,
                         const int32_t *nc_col, int64_t nc_cap, int csr_global, float *hbuf,
                         int64_t hcap_atoms, float *sg_latent, int64_t *status, hipStream_t s);
+
+// covalent / non-covalent widths (after padding) the staged SG-CNN kernel supports
+bool sgcnn_staged_supported(int hc, int hn);
 
 hipError_t launch_segmax(const float *scores, int n_scores, const int32_t *off, int n_seg, float *best,
                          int32_t *best_idx, int64_t *status, hipStream_t s);

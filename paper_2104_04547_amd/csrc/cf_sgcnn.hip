@@ -271,110 +271,103 @@ __device__ inline f32x16v mfma3(const bf16x8 &ah, const bf16x8 &al, const bf16x8
   return c;
 }
 
+// Tile of one stage at width H: each of the four waves owns a 32-atom x 32-feature
+// tile of the block (FB feature blocks x MBK atom blocks); rows padded to LD.
 template <int H>
-struct SgMfmaShared {
+struct SgTile {
   static constexpr int LD = H + 4;      // padded row stride (floats)
   static constexpr int FB = H / 32;     // 32-feature blocks
   static constexpr int MBK = 4 / FB;    // 32-atom blocks per workgroup block
   static constexpr int BLK = 32 * MBK;  // atoms per block
-  // rounds: A | M | Hc; readout (after the rounds): Wg | Wv | red, in the same
-  // space, so that several poses share a CU
-  float buf[3 * BLK * LD];
-  static_assert((H + CF_NCH) * H + H * H + kThreads <= 3 * BLK * LD, "readout staging must fit");
-  __device__ float *A() { return buf; }
-  __device__ float *M() { return buf + BLK * LD; }
-  __device__ float *Hc() { return buf + 2 * BLK * LD; }
-  __device__ float *Wg() { return buf; }
-  __device__ float *Wv() { return buf + (H + CF_NCH) * H; }
-  __device__ float *red() { return buf + (H + CF_NCH) * H + H * H; }
+  static constexpr int FLOATS = 3 * BLK * LD;  // A | M | Hc
+  static_assert(H % 32 == 0 && H <= 128, "matrix-core widths are 32, 64 or 128");
 };
 
-template <int H>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_sgcnn_mfma(
-    SgWeights W, const int32_t *__restrict__ atom_off,
-                                                         int n_atoms, const float *__restrict__ feat,
-                                                         const uint8_t *__restrict__ is_lig, int p0,
-                                                         const int32_t *__restrict__ cov_row,
-                                                         const int32_t *__restrict__ cov_col, int64_t cov_cap,
-                                                         const int32_t *__restrict__ nc_row,
-                                                         const int32_t *__restrict__ nc_col, int64_t nc_cap,
-                                                         int csr_global, float *__restrict__ hbuf, int64_t hcap,
-                                                         float *__restrict__ sg_latent, int64_t *__restrict__ status) {
-  using SS = SgMfmaShared<H>;
-  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
-  SS &S = *reinterpret_cast<SS *>(smem_raw);
-  constexpr int LD = SS::LD, BLK = SS::BLK;
+// acc += A[row][0..K) W^T for this lane's output column `col` of N, W given as
+// split-bfloat16 MFMA B operands ([K/16][N][16], hi and lo) -- three products per
+// term -- or, for the plain form, as float32 W^T [K][N] on the 32x32x2 float32
+// matrix instruction.
+template <int K, bool F32>
+__device__ inline f32x16v mm_row(const float *arow, const bf16_t *bhi, const bf16_t *blo, const float *bT, int N,
+                                 int col, int khalf, f32x16v acc) {
+  if constexpr (F32) {
+#pragma unroll 8
+    for (int k = 0; k < K; k += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[k + khalf], bT[(int64_t)(k + khalf) * N + col], acc, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int ks = 0; ks < K / 16; ++ks) {
+      bf16x8 ah, al;
+      split8(arow + ks * 16 + khalf * 8, ah, al);
+      const int64_t wo = ((int64_t)ks * N + col) * 16 + khalf * 8;
+      acc = mfma3(ah, al, *reinterpret_cast<const bf16x8 *>(bhi + wo), *reinterpret_cast<const bf16x8 *>(blo + wo),
+                  acc);
+    }
+  }
+  return acc;
+}
+
+// K rounds of one stage at width H (rounds r0 .. r0+K-1 of the weight lists, GRU
+// of stage `stage`); states ping-pong between cur and nxt (row stride H).
+template <int H, bool F32>
+__device__ void sg_rounds(const SgWeights &W, int stage, int r0, int K, const int32_t *__restrict__ rowp,
+                          const int32_t *__restrict__ colp, int64_t cap, int csr_global, int a0, int base,
+                          int64_t lb, int n, float *&cur, float *&nxt, float *lds, int64_t *status) {
+  using T = SgTile<H>;
+  constexpr int LD = T::LD, BLK = T::BLK;
+  float *A = lds, *M = lds + BLK * LD, *Hc = lds + 2 * BLK * LD;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int mb = wave / SS::FB, fb = wave % SS::FB;  // this wave's 32-atom x 32-feature tile
+  const int mb = wave / T::FB, fb = wave % T::FB;  // this wave's 32-atom x 32-feature tile
   const int lrow = lane & 31, khalf = lane >> 5;
-  const int pl = blockIdx.x;
-  const int base = atom_off[p0];
-  int a0, a1;
-  const bool ok = pose_range(atom_off, p0 + pl, n_atoms, a0, a1);
-  const int n = a1 - a0;
-  const int64_t lb = (int64_t)a0 - base;
-  if (!ok || n <= 0 || lb < 0 || lb + n > hcap) {
-    if (t == 0 && (!ok || lb < 0 || lb + n > hcap)) dev_fail(status, kDevBadOffsets);
-    if (t < H) sg_latent[(int64_t)pl * H + t] = 0.0f;
-    return;
-  }
-  float *h0 = hbuf, *h1 = hbuf + hcap * H;
-  sg_embed<H>(W, feat, a0, n, lb, h0);
-  __threadfence();
-  __syncthreads();
-
   const int ocol = fb * 32 + lrow;  // output feature of this lane's accumulator column
-  float *cur = h0, *nxt = h1;
-  const int rounds = W.K_c + W.K_n;
-  for (int r = 0; r < rounds; ++r) {
-    const int stage = r < W.K_c ? 0 : 1;
-    const int32_t *rowp = stage ? nc_row : cov_row;
-    const int32_t *colp = stage ? nc_col : cov_col;
-    const int64_t cap = stage ? nc_cap : cov_cap;
-    const bf16_t *mh = W.msg_hi[r], *ml = W.msg_lo[r];
-    const bf16_t *ih = W.ih_hi[stage], *il = W.ih_lo[stage], *hh = W.hh_hi[stage], *hl = W.hh_lo[stage];
-    const float *bih = W.b_ih[stage], *bhh = W.b_hh[stage];
-    const float bir = bih[ocol], biz = bih[H + ocol], bin = bih[2 * H + ocol];
-    const float bhr = bhh[ocol], bhz = bhh[H + ocol], bhn = bhh[2 * H + ocol];
+  const float *bih = W.b_ih[stage], *bhh = W.b_hh[stage];
+  const float bir = bih[ocol], biz = bih[H + ocol], bin = bih[2 * H + ocol];
+  const float bhr = bhh[ocol], bhz = bhh[H + ocol], bhn = bhh[2 * H + ocol];
+  for (int r = r0; r < r0 + K; ++r) {
     for (int blk = 0; blk < n; blk += BLK) {
-      sg_aggregate<H>(cur, rowp, colp, cap, csr_global, a0, base, lb, n, blk, BLK, LD, S.A(), S.Hc(), status);
+      sg_aggregate<H>(cur, rowp, colp, cap, csr_global, a0, base, lb, n, blk, BLK, LD, A, Hc, status);
       __syncthreads();
       // messages: M[atoms, ocol] = sum_k A[atoms, k] W_t[ocol, k]
       {
         f32x16v acc = {};
-#pragma unroll
-        for (int ks = 0; ks < H / 16; ++ks) {
-          bf16x8 ah, al;
-          split8(&S.A()[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], ah, al);
-          const int64_t wo = ((int64_t)ks * H + ocol) * 16 + khalf * 8;
-          const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(mh + wo);
-          const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(ml + wo);
-          acc = mfma3(ah, al, bh, bl, acc);
-        }
+        acc = mm_row<H, F32>(&A[(mb * 32 + lrow) * LD], W.msg_hi[r], W.msg_lo[r], W.msgT[r], H, ocol, khalf, acc);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           const int row = mb * 32 + 8 * (j >> 2) + 4 * khalf + (j & 3);
-          S.M()[row * LD + ocol] = acc[j];
+          M[row * LD + ocol] = acc[j];
         }
       }
       __syncthreads();
       // GRU gates for this wave's tile, all six products from the same operands
       {
         f32x16v gir = {}, giz = {}, gin = {}, ghr = {}, ghz = {}, ghn = {};
-#pragma unroll
-        for (int ks = 0; ks < H / 16; ++ks) {
-          bf16x8 mhi, mlo, hhi, hlo;
-          split8(&S.M()[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], mhi, mlo);
-          split8(&S.Hc()[(mb * 32 + lrow) * LD + ks * 16 + khalf * 8], hhi, hlo);
-          const int64_t w0 = ((int64_t)ks * 3 * H + ocol) * 16 + khalf * 8;
-          const int64_t gs = (int64_t)H * 16;  // next gate's rows
-          gir = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0), *reinterpret_cast<const bf16x8 *>(il + w0), gir);
-          giz = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0 + gs), *reinterpret_cast<const bf16x8 *>(il + w0 + gs), giz);
-          gin = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0 + 2 * gs), *reinterpret_cast<const bf16x8 *>(il + w0 + 2 * gs), gin);
-          ghr = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0), *reinterpret_cast<const bf16x8 *>(hl + w0), ghr);
-          ghz = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0 + gs), *reinterpret_cast<const bf16x8 *>(hl + w0 + gs), ghz);
-          ghn = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0 + 2 * gs), *reinterpret_cast<const bf16x8 *>(hl + w0 + 2 * gs), ghn);
+        const float *mrow = &M[(mb * 32 + lrow) * LD], *hrow = &Hc[(mb * 32 + lrow) * LD];
+        if constexpr (F32) {
+          const float *wi = W.w_ihT[stage], *wh = W.w_hhT[stage];
+          gir = mm_row<H, true>(mrow, nullptr, nullptr, wi, 3 * H, ocol, khalf, gir);
+          giz = mm_row<H, true>(mrow, nullptr, nullptr, wi, 3 * H, H + ocol, khalf, giz);
+          gin = mm_row<H, true>(mrow, nullptr, nullptr, wi, 3 * H, 2 * H + ocol, khalf, gin);
+          ghr = mm_row<H, true>(hrow, nullptr, nullptr, wh, 3 * H, ocol, khalf, ghr);
+          ghz = mm_row<H, true>(hrow, nullptr, nullptr, wh, 3 * H, H + ocol, khalf, ghz);
+          ghn = mm_row<H, true>(hrow, nullptr, nullptr, wh, 3 * H, 2 * H + ocol, khalf, ghn);
+        } else {
+          const bf16_t *ih = W.ih_hi[stage], *il = W.ih_lo[stage], *hh = W.hh_hi[stage], *hl = W.hh_lo[stage];
+          constexpr int kUnroll = H <= 64 ? H / 16 : 2;  // wider: bounded unroll keeps it in registers
+#pragma unroll kUnroll
+          for (int ks = 0; ks < H / 16; ++ks) {
+            bf16x8 mhi, mlo, hhi, hlo;
+            split8(mrow + ks * 16 + khalf * 8, mhi, mlo);
+            split8(hrow + ks * 16 + khalf * 8, hhi, hlo);
+            const int64_t w0 = ((int64_t)ks * 3 * H + ocol) * 16 + khalf * 8;
+            const int64_t gs = (int64_t)H * 16;  // next gate's rows
+            gir = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0), *reinterpret_cast<const bf16x8 *>(il + w0), gir);
+            giz = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0 + gs), *reinterpret_cast<const bf16x8 *>(il + w0 + gs), giz);
+            gin = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0 + 2 * gs), *reinterpret_cast<const bf16x8 *>(il + w0 + 2 * gs), gin);
+            ghr = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0), *reinterpret_cast<const bf16x8 *>(hl + w0), ghr);
+            ghz = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0 + gs), *reinterpret_cast<const bf16x8 *>(hl + w0 + gs), ghz);
+            ghn = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0 + 2 * gs), *reinterpret_cast<const bf16x8 *>(hl + w0 + 2 * gs), ghn);
+          }
         }
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
@@ -384,7 +377,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             const float rr = sigm(gir[j] + bir + ghr[j] + bhr);
             const float zz = sigm(giz[j] + biz + ghz[j] + bhz);
             const float nn = tanhf(gin[j] + bin + rr * (ghn[j] + bhn));
-            nxt[(lb + i) * H + ocol] = (1.0f - zz) * nn + zz * S.Hc()[row * LD + ocol];
+            nxt[(lb + i) * H + ocol] = (1.0f - zz) * nn + zz * Hc[row * LD + ocol];
           }
         }
       }
@@ -396,15 +389,159 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     cur = nxt;
     nxt = tmp;
   }
-  for (int e = t; e < (H + CF_NCH) * H; e += kThreads) S.Wg()[e] = W.gate_wT[e];
-  for (int e = t; e < H * H; e += kThreads) S.Wv()[e] = W.val_wT[e];
+}
+
+template <int H>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_sgcnn_mfma(
+    SgWeights W, const int32_t *__restrict__ atom_off, int n_atoms, const float *__restrict__ feat,
+    const uint8_t *__restrict__ is_lig, int p0, const int32_t *__restrict__ cov_row,
+    const int32_t *__restrict__ cov_col, int64_t cov_cap, const int32_t *__restrict__ nc_row,
+    const int32_t *__restrict__ nc_col, int64_t nc_cap, int csr_global, float *__restrict__ hbuf, int64_t hcap,
+    float *__restrict__ sg_latent, int64_t *__restrict__ status) {
+  // rounds: A | M | Hc; readout (after the rounds): Wg | Wv | red, in the same
+  // space, so that several poses share a CU
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  static_assert((H + CF_NCH) * H + H * H + kThreads <= SgTile<H>::FLOATS, "readout staging must fit");
+  const int t = threadIdx.x;
+  const int pl = blockIdx.x;
+  const int base = atom_off[p0];
+  int a0, a1;
+  const bool ok = pose_range(atom_off, p0 + pl, n_atoms, a0, a1);
+  const int n = a1 - a0;
+  const int64_t lb = (int64_t)a0 - base;
+  if (!ok || n <= 0 || lb < 0 || lb + n > hcap) {
+    if (t == 0 && (!ok || lb < 0 || lb + n > hcap)) dev_fail(status, kDevBadOffsets);
+    if (t < H) sg_latent[(int64_t)pl * H + t] = 0.0f;
+    return;
+  }
+  float *cur = hbuf, *nxt = hbuf + hcap * H;
+  sg_embed<H>(W, feat, a0, n, lb, cur);
+  __threadfence();
   __syncthreads();
-  sg_readout<H>(W, cur, feat, is_lig, a0, n, lb, S.Wg(), S.Wv(), S.red(), sg_latent + (int64_t)pl * H);
+  sg_rounds<H, false>(W, 0, 0, W.K_c, cov_row, cov_col, cov_cap, csr_global, a0, base, lb, n, cur, nxt, lds, status);
+  sg_rounds<H, false>(W, 1, W.K_c, W.K_n, nc_row, nc_col, nc_cap, csr_global, a0, base, lb, n, cur, nxt, lds,
+                      status);
+  float *Wg = lds, *Wv = lds + (H + CF_NCH) * H, *red = Wv + H * H;
+  for (int e = t; e < (H + CF_NCH) * H; e += kThreads) Wg[e] = W.gate_wT[e];
+  for (int e = t; e < H * H; e += kThreads) Wv[e] = W.val_wT[e];
+  __syncthreads();
+  sg_readout<H>(W, cur, feat, is_lig, a0, n, lb, Wg, Wv, red, sg_latent + (int64_t)pl * H);
+}
+
+// ---- PotentialNet staging: covalent stage at width HC, per-atom gather,
+// linear embedding to width HN, non-covalent stage at HN, readout over ligand
+// atoms whose gate reads [h; g].  The per-atom work outside the rounds is small
+// (float32 FMAs with the weights read through the caches). ----
+
+// g_i = sigmoid(W_g1 [h_i; x_i] + b) * (W_v1 h_i + b), width HC
+template <int HC>
+__device__ void sg_mid_gather(const SgWeights &W, const float *__restrict__ cur, const float *__restrict__ feat,
+                              int a0, int n, int64_t lb, float *__restrict__ gb) {
+  for (int e = threadIdx.x; e < n * HC; e += kThreads) {
+    const int i = e / HC, o = e % HC;
+    const float *hi = cur + (lb + i) * HC;
+    const float *xi = feat + (int64_t)(a0 + i) * CF_NCH;
+    float gt = W.mid_gate_b[o], vl = W.mid_val_b[o];
+    for (int k = 0; k < HC; ++k) {
+      const float hk = hi[k];
+      gt += W.mid_gate_wT[k * HC + o] * hk;
+      vl += W.mid_val_wT[k * HC + o] * hk;
+    }
+    for (int c = 0; c < CF_NCH; ++c) gt += W.mid_gate_wT[(HC + c) * HC + o] * xi[c];
+    gb[(lb + i) * HC + o] = sigm(gt) * vl;
+  }
+}
+
+// h_i = W_e2 g_i + b, width HN
+template <int HC, int HN>
+__device__ void sg_embed2(const SgWeights &W, const float *__restrict__ gb, int n, int64_t lb, float *__restrict__ h) {
+  for (int e = threadIdx.x; e < n * HN; e += kThreads) {
+    const int i = e / HN, o = e % HN;
+    const float *gi = gb + (lb + i) * HC;
+    float v = W.embed2_b[o];
+    for (int k = 0; k < HC; ++k) v += W.embed2_wT[k * HN + o] * gi[k];
+    h[(lb + i) * HN + o] = v;
+  }
+}
+
+// s = sum over ligand atoms of sigmoid(W_g [h; g] + b_g) * (W_v h + b_v), width HN
+template <int HC, int HN>
+__device__ void sg_readout_staged(const SgWeights &W, const float *__restrict__ cur, const float *__restrict__ gb,
+                                  const uint8_t *__restrict__ is_lig, int a0, int n, int64_t lb, float *red,
+                                  float *out) {
+  constexpr int G = kThreads / HN;
+  const int o = threadIdx.x % HN, g = threadIdx.x / HN;
+  float acc = 0.0f;
+  for (int i = g; i < n; i += G) {
+    if (!is_lig[a0 + i]) continue;
+    const float *hi = cur + (lb + i) * HN;
+    const float *gi = gb + (lb + i) * HC;
+    float gt = W.gate_b[o], vl = W.val_b[o];
+    for (int k = 0; k < HN; ++k) {
+      const float hk = hi[k];
+      gt += W.gate_wT[k * HN + o] * hk;
+      vl += W.val_wT[k * HN + o] * hk;
+    }
+    for (int k = 0; k < HC; ++k) gt += W.gate_wT[(HN + k) * HN + o] * gi[k];
+    acc += sigm(gt) * vl;
+  }
+  red[g * HN + o] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < HN) {
+    float s = 0.0f;
+    for (int q = 0; q < G; ++q) s += red[q * HN + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+template <int HC, int HN, bool F32>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_sgcnn_staged(
+    SgWeights W, const int32_t *__restrict__ atom_off, int n_atoms, const float *__restrict__ feat,
+    const uint8_t *__restrict__ is_lig, int p0, const int32_t *__restrict__ cov_row,
+    const int32_t *__restrict__ cov_col, int64_t cov_cap, const int32_t *__restrict__ nc_row,
+    const int32_t *__restrict__ nc_col, int64_t nc_cap, int csr_global, float *__restrict__ hbuf, int64_t hcap,
+    float *__restrict__ sg_latent, int64_t *__restrict__ status) {
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  static_assert(kThreads % HN == 0 && HC <= HN, "stage widths");
+  const int t = threadIdx.x;
+  const int pl = blockIdx.x;
+  const int base = atom_off[p0];
+  int a0, a1;
+  const bool ok = pose_range(atom_off, p0 + pl, n_atoms, a0, a1);
+  const int n = a1 - a0;
+  const int64_t lb = (int64_t)a0 - base;
+  if (!ok || n <= 0 || lb < 0 || lb + n > hcap) {
+    if (t == 0 && (!ok || lb < 0 || lb + n > hcap)) dev_fail(status, kDevBadOffsets);
+    if (t < HN) sg_latent[(int64_t)pl * HN + t] = 0.0f;
+    return;
+  }
+  // states: two [hcap][HN] buffers (the covalent stage uses row stride HC), then
+  // the covalent gather [hcap][HC]
+  float *cur = hbuf, *nxt = hbuf + hcap * HN, *gb = hbuf + 2 * hcap * HN;
+  sg_embed<HC>(W, feat, a0, n, lb, cur);
+  __threadfence();
+  __syncthreads();
+  sg_rounds<HC, F32>(W, 0, 0, W.K_c, cov_row, cov_col, cov_cap, csr_global, a0, base, lb, n, cur, nxt, lds, status);
+  sg_mid_gather<HC>(W, cur, feat, a0, n, lb, gb);
+  __threadfence();
+  __syncthreads();
+  sg_embed2<HC, HN>(W, gb, n, lb, nxt);
+  __threadfence();
+  __syncthreads();
+  {
+    float *tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  sg_rounds<HN, F32>(W, 1, W.K_c, W.K_n, nc_row, nc_col, nc_cap, csr_global, a0, base, lb, n, cur, nxt, lds,
+                     status);
+  sg_readout_staged<HC, HN>(W, cur, gb, is_lig, a0, n, lb, lds, sg_latent + (int64_t)pl * HN);
 }
 
 template <typename K>
 void set_lds_attr(K kernel, size_t lds) {
-  hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
 }
 
 template <int H>
@@ -415,7 +552,7 @@ hipError_t launch_h(const SgWeights &W, int mfma, const int32_t *atom_off, int n
   static_assert((H + CF_NCH) * H <= 3 * H * H, "readout weights must fit the staging area");
   if constexpr (H >= 32) {
     if (mfma) {
-      const size_t lds = sizeof(SgMfmaShared<H>);
+      const size_t lds = sizeof(float) * SgTile<H>::FLOATS;
       static bool attr = false;
       if (!attr) {
         set_lds_attr(&k_sgcnn_mfma<H>, lds);
@@ -439,7 +576,42 @@ hipError_t launch_h(const SgWeights &W, int mfma, const int32_t *atom_off, int n
   return hipGetLastError();
 }
 
+template <int HC, int HN>
+hipError_t launch_staged(const SgWeights &W, int bf16, const int32_t *atom_off, int n_atoms, const float *feat,
+                         const uint8_t *is_lig, int p0, int n_poses, const int32_t *cov_row, const int32_t *cov_col,
+                         int64_t cov_cap, const int32_t *nc_row, const int32_t *nc_col, int64_t nc_cap,
+                         int csr_global, float *hbuf, int64_t hcap, float *sg_latent, int64_t *status,
+                         hipStream_t s) {
+  constexpr int fl = SgTile<HC>::FLOATS > SgTile<HN>::FLOATS ? SgTile<HC>::FLOATS : SgTile<HN>::FLOATS;
+  const size_t lds = sizeof(float) * (fl > kThreads ? fl : kThreads);
+  if (bf16) {
+    static bool attr = false;
+    if (!attr) {
+      set_lds_attr(&k_sgcnn_staged<HC, HN, false>, lds);
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_sgcnn_staged<HC, HN, false>), dim3(n_poses), dim3(kThreads), lds, s, W, atom_off,
+                       n_atoms, feat, is_lig, p0, cov_row, cov_col, cov_cap, nc_row, nc_col, nc_cap, csr_global,
+                       hbuf, hcap, sg_latent, status);
+  } else {
+    static bool attr = false;
+    if (!attr) {
+      set_lds_attr(&k_sgcnn_staged<HC, HN, true>, lds);
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_sgcnn_staged<HC, HN, true>), dim3(n_poses), dim3(kThreads), lds, s, W, atom_off,
+                       n_atoms, feat, is_lig, p0, cov_row, cov_col, cov_cap, nc_row, nc_col, nc_cap, csr_global,
+                       hbuf, hcap, sg_latent, status);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+// widths the staged kernel is built for (covalent, non-covalent)
+bool sgcnn_staged_supported(int hc, int hn) {
+  return (hc == 32 && (hn == 64 || hn == 128)) || (hc == 64 && hn == 128);
+}
 
 hipError_t launch_sgcnn(const SgWeights &W, int bf16, const int32_t *atom_off, int n_atoms, const float *feat,
                         const uint8_t *is_lig, int p0, int n_poses, const int32_t *cov_row,
@@ -447,6 +619,17 @@ hipError_t launch_sgcnn(const SgWeights &W, int bf16, const int32_t *atom_off, i
                         const int32_t *nc_col, int64_t nc_cap, int csr_global, float *hbuf,
                         int64_t hcap_atoms, float *sg_latent, int64_t *status, hipStream_t s) {
   if (n_poses <= 0) return hipSuccess;
+  if (W.staged) {
+    // the precision form needs the split-bfloat16 weight copies
+    const int split = bf16 && W.msg_hi[0] != nullptr;
+    if (bf16 && !split) return hipErrorInvalidValue;
+#define CF_ST(HC, HN)                                                                                             if (W.H == HC && W.H2 == HN)                                                                                      return launch_staged<HC, HN>(W, split, atom_off, n_atoms, feat, is_lig, p0, n_poses, cov_row, cov_col,                                       cov_cap, nc_row, nc_col, nc_cap, csr_global, hbuf, hcap_atoms, sg_latent, status, s);
+    CF_ST(32, 64)
+    CF_ST(32, 128)
+    CF_ST(64, 128)
+#undef CF_ST
+    return hipErrorInvalidValue;
+  }
   // the matrix-core path needs the split-bfloat16 weight copies (precision form, H >= 32)
   const int mfma = bf16 && W.msg_hi[0] != nullptr;
 #define CF_SG(HH)                                                                                              \

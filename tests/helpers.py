@@ -22,8 +22,10 @@ def weights(arch_name: str, calibrated: bool = True):
     return arch, w
 
 
-def golden(cfg: str, G: int):
-    path = os.path.join(GOLDEN, f"{cfg}_G{G}_oracle.json")
+def golden(cfg: str, G: int, arch: str = ""):
+    """Stored oracle values of a workload config (another architecture: `arch`)."""
+    tag = f"_{arch}" if arch and arch != synth.CONFIGS[cfg]["arch"] else ""
+    path = os.path.join(GOLDEN, f"{cfg}_G{G}{tag}_oracle.json")
     if not os.path.exists(path):
         return None
     return json.load(open(path))

@@ -39,13 +39,13 @@ def test_library_exports_every_declared_function():
 
 def test_struct_layouts_match_header():
     from paper_2104_04547_amd import cfabi
-    # cf_model_desc: 3 + 8*5 + 8 + 5 four-byte fields
-    assert ctypes.sizeof(cfabi.cf_model_desc) == 4 * (3 + 40 + 8 + 5)
+    # cf_model_desc: 3 + 8*5 + 8 + 7 four-byte fields
+    assert ctypes.sizeof(cfabi.cf_model_desc) == 4 * (3 + 40 + 8 + 7)
     assert ctypes.sizeof(cfabi.cf_pose_batch) == 8 + 5 * 8
     assert ctypes.sizeof(cfabi.cf_csr) == 24
 
 
-@pytest.mark.parametrize("arch_name", ["tiny", "full", "full_mid", "full_late"])
+@pytest.mark.parametrize("arch_name", ["tiny", "full", "full_mid", "full_late", "paper"])
 def test_model_blob_size_and_order(arch_name):
     from paper_2104_04547_amd import cfabi
     arch = synth.ARCHS[arch_name]

@@ -21,7 +21,7 @@ def _say(msg):
 @pytest.fixture(scope="module")
 def cases():
     out = {}
-    for arch_name, G in (("tiny", 24), ("full", 24), ("full", 40)):
+    for arch_name, G in (("tiny", 24), ("full", 24), ("full", 40), ("paper", 24), ("paper", 40)):
         arch, w = weights(arch_name)
         b = synth.make_poses("c1" if G == 24 else "c2", 2)
         cen = np.stack([oracle.pose_center(b.xyz[b.atom_off[p]:b.atom_off[p + 1]][
@@ -32,7 +32,7 @@ def cases():
     return out
 
 
-@pytest.mark.parametrize("arch_name,G", [("tiny", 24), ("full", 24), ("full", 40)])
+@pytest.mark.parametrize("arch_name,G", [("tiny", 24), ("full", 24), ("full", 40), ("paper", 24), ("paper", 40)])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_every_conv_variant_matches_oracle(cases, arch_name, G, prec):
     import torch

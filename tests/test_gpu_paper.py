@@ -1,0 +1,87 @@
+"""The paper-shaped model (5^3 / 3^3 convs without BatchNorm, two dense layers,
+PotentialNet-staged SG-CNN at widths 24 -> 128, Table II cutoffs, four fusion
+layers) through the whole path and stage by stage, against stored FP64 oracle
+values.  The covalent stage runs zero-padded to width 32 on the GPU.
+
+Plain form: |s_gpu - s_oracle| <= 1e-4 * max(1, |s_oracle|); precision form:
+<= 2e-2 pK."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import BF16_PK_TOL, golden, score_tol, weights
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def scorers():
+    from paper_2104_04547_amd import Scorer
+    arch, w = weights("paper")
+    out = {p: Scorer(arch, w, p) for p in ("fp32", "bf16")}
+    yield out
+    for s in out.values():
+        s.close()
+
+
+def _score(s, b, G):
+    from paper_2104_04547_amd import cfabi
+    got = s.score(cfabi.DeviceBatch.from_pose_batch(b), G).cpu().numpy().astype(np.float64)
+    s.check()
+    return got
+
+
+@pytest.mark.parametrize("cfg,G,n", [("c2", 48, 32), ("c2", 40, 8), ("c4", 64, 8)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_paper_model_scores_match_oracle(scorers, cfg, G, n, prec):
+    gd = golden(cfg, G, "paper")
+    n = min(n, len(gd["poses"]))
+    _say(f"cf_score_poses paper model {prec} {cfg} G={G} poses={n}")
+    b = synth.make_poses(cfg, n)
+    want = np.array([p["score"] for p in gd["poses"][:n]])
+    got = _score(scorers[prec], b, G)
+    err = np.abs(got - want)
+    print(f"paper {prec} {cfg} G={G}: max |err| {err.max():.3e} mean {err.mean():.3e}")
+    if prec == "fp32":
+        assert np.all(err <= score_tol(want)), f"worst pose {int(err.argmax())}"
+    else:
+        assert err.max() <= BF16_PK_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_paper_model_stage_latents(scorers, prec):
+    from paper_2104_04547_amd import cfabi
+    _say(f"paper model latents {prec}: cf_voxelize -> cf_cnn3d_fwd, cf_build_graphs -> cf_sgcnn_fwd, c2 G=40")
+    gd = golden("c2", 40, "paper")
+    n = 8
+    b = synth.make_poses("c2", n)
+    s = scorers[prec]
+    db = cfabi.DeviceBatch.from_pose_batch(b)
+    cnn = s.cnn3d(s.voxelize(db, 40), 40).cpu().numpy()
+    sg = s.sgcnn(db, s.build_graphs(db)).cpu().numpy()
+    s.check()
+    want_c = np.array([p["cnn_lat"] for p in gd["poses"][:n]])
+    want_s = np.array([p["sg_lat"] for p in gd["poses"][:n]])
+    assert cnn.shape == want_c.shape and sg.shape == want_s.shape
+    if prec == "fp32":
+        np.testing.assert_allclose(cnn, want_c, rtol=1e-4, atol=1e-5 * np.abs(want_c).max())
+        np.testing.assert_allclose(sg, want_s, rtol=1e-4, atol=1e-5 * np.abs(want_s).max())
+    else:
+        np.testing.assert_allclose(cnn, want_c, rtol=3e-2, atol=3e-2 * np.abs(want_c).max())
+        np.testing.assert_allclose(sg, want_s, rtol=2e-3, atol=1e-3 * np.abs(want_s).max())
+
+
+def test_paper_model_batch_invariance(scorers):
+    _say("paper model: alone vs in a batch, bf16, c2 G=48")
+    b = synth.make_poses("c2", 6)
+    s = scorers["bf16"]
+    full = _score(s, b, 48)
+    for p in (0, 5):
+        assert _score(s, b.pose(p), 48)[0] == full[p]
