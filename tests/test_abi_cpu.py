@@ -53,6 +53,8 @@ def test_model_blob_size_and_order(arch_name):
     blob = cfabi.pack_model(arch, w)
     assert len(blob) == ctypes.sizeof(cfabi.cf_model_desc) + 4 * synth.n_params(arch)
     assert sorted(cfabi.blob_param_order(arch)) == sorted(w.keys())
+    # the generator draws the tensors in the blob's order
+    assert cfabi.blob_param_order(arch) == [n for n, _, _ in synth.model.param_shapes(arch)]
     d = cfabi.cf_model_desc.from_buffer_copy(blob[:ctypes.sizeof(cfabi.cf_model_desc)])
     assert d.magic == cfabi.CF_MODEL_MAGIC and d.n_conv == len(arch.conv) and d.H == arch.H
     first = np.frombuffer(blob, dtype="<f4", count=8, offset=ctypes.sizeof(cfabi.cf_model_desc))

@@ -23,7 +23,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("name", ["tiny", "full", "full_mid", "full_late"])
+@pytest.mark.parametrize("name", ["tiny", "full", "full_mid", "full_late", "paper"])
 def test_fusion_fwd_matches_oracle(name):
     import torch
     from paper_2104_04547_amd import Scorer
@@ -33,7 +33,7 @@ def test_fusion_fwd_matches_oracle(name):
     n = 300
     # latent scales of real poses: non-negative CNN latents (ReLU), signed SG latents
     cnn = np.abs(rng.normal(0.0, 2.0, size=(n, arch.cnn_latent))).astype(np.float32)
-    sg = rng.normal(0.0, 8.0, size=(n, arch.H)).astype(np.float32)
+    sg = rng.normal(0.0, 8.0, size=(n, arch.sg_latent)).astype(np.float32)
     cnn[0] = 0.0
     sg[1] = 0.0
     s = Scorer(arch, w, "fp32")

@@ -70,6 +70,9 @@ def test_paper_model_stage_latents(scorers, prec):
     want_c = np.array([p["cnn_lat"] for p in gd["poses"][:n]])
     want_s = np.array([p["sg_lat"] for p in gd["poses"][:n]])
     assert cnn.shape == want_c.shape and sg.shape == want_s.shape
+    for p in range(n):
+        print(f"pose {p}: cnn rel {np.abs(cnn[p] - want_c[p]).max() / np.abs(want_c[p]).max():.2e} "
+              f"sg rel {np.abs(sg[p] - want_s[p]).max() / np.abs(want_s[p]).max():.2e}")
     if prec == "fp32":
         np.testing.assert_allclose(cnn, want_c, rtol=1e-4, atol=1e-5 * np.abs(want_c).max())
         np.testing.assert_allclose(sg, want_s, rtol=1e-4, atol=1e-5 * np.abs(want_s).max())
