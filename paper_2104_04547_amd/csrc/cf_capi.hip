@@ -68,7 +68,11 @@ struct cf_ctx {
     std::string key;
     hipEvent_t e0, e1;
     double flop, bytes;
+    const int64_t *edges = nullptr;  // graph launches: {cov count, nc count, cov offset, nc offset} of the last pose
   };
+  // pinned host slots the graph launches' edge totals are copied into (timing only)
+  std::vector<int64_t *> pin_blocks;
+  int pin_used = 0;
   struct Stat {
     int launches = 0;
     double ms = 0, flop = 0, bytes = 0;
@@ -121,6 +125,20 @@ hipEvent_t tbegin(cf_ctx *c, hipStream_t s) {
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   (void)hipEventRecord(e, s);
   return e;
+}
+
+// Four pinned int64 slots (timing only): the graph stage's edge totals, read when
+// its events have completed.
+constexpr int kPinBlock = 4096;
+int64_t *pin_slots(cf_ctx *c) {
+  const size_t blk = (size_t)c->pin_used / kPinBlock, off = (size_t)c->pin_used % kPinBlock;
+  if (blk == c->pin_blocks.size()) {
+    void *p = nullptr;
+    if (hipHostMalloc(&p, kPinBlock * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) return nullptr;
+    c->pin_blocks.push_back(static_cast<int64_t *>(p));
+  }
+  c->pin_used += 4;
+  return c->pin_blocks[blk] + off;
 }
 
 void tend(cf_ctx *c, hipStream_t s, hipEvent_t e0, const std::string &key, double flop, double bytes) {
@@ -566,7 +584,7 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
   S.K_c = d.K_c;
   S.K_n = d.K_n;
   c->sgw = Hs[1];
-  c->sg_floats = staged ? 2 * (int64_t)Hs[1] + Hp : 2 * (int64_t)Hp;
+  c->sg_floats = staged ? 3 * (int64_t)Hp + 2 * (int64_t)Hs[1] : 2 * (int64_t)Hp;
   c->sg_flop_atom = 2.0 * (CF_NCH * Hp + d.K_c * 7.0 * Hp * Hp + d.K_n * 7.0 * Hs[1] * Hs[1] +
                            (staged ? (2.0 * Hp + CF_NCH) * Hp + (double)Hp * Hs[1] : 0.0));
   // W [rows][cols] -> zero-padded [prows][pcols]; source column q goes to q < split ? q : q + shift
@@ -654,6 +672,7 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
 
 void free_ctx(cf_ctx *c) {
   for (void *p : c->weight_allocs) (void)hipFree(p);
+  for (int64_t *p : c->pin_blocks) (void)hipHostFree(p);
   DevBuf *bufs[] = {&c->grid, &c->centers, &c->cnn_lat, &c->sg_lat, &c->deg, &c->pose_tot,
                     &c->cov_row, &c->cov_col, &c->nc_row, &c->nc_col, &c->hbuf, &c->sel};
   for (DevBuf *b : bufs)
@@ -859,7 +878,19 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
     CF_HIP(cf::launch_graph(b->atom_off, b->n_atoms, b->xyz, p0, np, c->desc.r_cov_u, c->desc.r_nc_u, (int32_t *)c->cov_row.p,
                             (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
                             acap * 96, (int32_t *)c->deg.p, acap, (int64_t *)c->pose_tot.p, c->status, s));
-    tend(c, s, e, "graph", 0.0, atoms * 12.0);
+    // algorithmic bytes: coordinates read once, two row-pointer arrays and 4 B per
+    // edge written (the edge totals arrive with the events)
+    tend(c, s, e, "graph", 0.0, atoms * (12.0 + 8.0));
+    if (c->timing && !c->pending.empty() && c->pending.back().key == "graph") {
+      int64_t *slot = pin_slots(c);
+      const int64_t *pt = (const int64_t *)c->pose_tot.p;
+      if (slot) {
+        const int64_t idx[4] = {np - 1, 2 * (int64_t)np - 1, 3 * (int64_t)np - 1, 4 * (int64_t)np - 1};
+        for (int q = 0; q < 4; ++q)
+          CF_HIP(hipMemcpyAsync(slot + q, pt + idx[q], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        c->pending.back().edges = slot;
+      }
+    }
     e = tbegin(c, s);
     CF_HIP(cf::launch_sgcnn(c->sg, c->bf16, b->atom_off, b->n_atoms, b->feat, b->is_lig, p0, np, (int32_t *)c->cov_row.p,
                             (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
@@ -920,6 +951,9 @@ int cf_timing_enable(cf_ctx *c, int enable) {
 
 int cf_timing_read(cf_ctx *c, cf_kernel_stat *out, int32_t max_entries, int32_t *n_out) {
   if (!c || (!out && max_entries > 0)) return fail(CF_ERR_INVALID_ARG, "bad arguments");
+  // the edge-total copies follow their launch's end event on the same stream:
+  // wait for the last recorded event before reading them
+  if (!c->pending.empty()) CF_HIP(hipEventSynchronize(c->pending.back().e1));
   for (auto &p : c->pending) {
     CF_HIP(hipEventSynchronize(p.e1));
     float ms = 0.0f;
@@ -929,10 +963,12 @@ int cf_timing_read(cf_ctx *c, cf_kernel_stat *out, int32_t max_entries, int32_t 
     st.ms += ms;
     st.flop += p.flop;
     st.bytes += p.bytes;
+    if (p.edges) st.bytes += 4.0 * (double)(p.edges[0] + p.edges[1] + p.edges[2] + p.edges[3]);
     (void)hipEventDestroy(p.e0);
     (void)hipEventDestroy(p.e1);
   }
   c->pending.clear();
+  c->pin_used = 0;
   int n = 0;
   for (auto &kv : c->stats) {
     if (n < max_entries) {

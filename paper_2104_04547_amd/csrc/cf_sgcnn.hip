@@ -515,9 +515,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     if (t < HN) sg_latent[(int64_t)pl * HN + t] = 0.0f;
     return;
   }
-  // states: two [hcap][HN] buffers (the covalent stage uses row stride HC), then
-  // the covalent gather [hcap][HC]
-  float *cur = hbuf, *nxt = hbuf + hcap * HN, *gb = hbuf + 2 * hcap * HN;
+  // Each stage has its own pair of state buffers indexed at its own row stride:
+  // the workgroups of a launch run different poses at different stages at the
+  // same time, so one buffer indexed at two strides would let a pose's wide rows
+  // overwrite another pose's narrow ones.  Layout (floats): covalent states
+  // 2 x [hcap][HC], covalent gather [hcap][HC], non-covalent states 2 x [hcap][HN].
+  float *cur = hbuf, *nxt = hbuf + hcap * HC, *gb = hbuf + 2 * hcap * HC;
+  float *cur2 = gb + hcap * HC, *nxt2 = cur2 + hcap * HN;
   sg_embed<HC>(W, feat, a0, n, lb, cur);
   __threadfence();
   __syncthreads();
@@ -525,17 +529,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   sg_mid_gather<HC>(W, cur, feat, a0, n, lb, gb);
   __threadfence();
   __syncthreads();
-  sg_embed2<HC, HN>(W, gb, n, lb, nxt);
+  sg_embed2<HC, HN>(W, gb, n, lb, cur2);
   __threadfence();
   __syncthreads();
-  {
-    float *tmp = cur;
-    cur = nxt;
-    nxt = tmp;
-  }
-  sg_rounds<HN, F32>(W, 1, W.K_c, W.K_n, nc_row, nc_col, nc_cap, csr_global, a0, base, lb, n, cur, nxt, lds,
+  sg_rounds<HN, F32>(W, 1, W.K_c, W.K_n, nc_row, nc_col, nc_cap, csr_global, a0, base, lb, n, cur2, nxt2, lds,
                      status);
-  sg_readout_staged<HC, HN>(W, cur, gb, is_lig, a0, n, lb, lds, sg_latent + (int64_t)pl * HN);
+  sg_readout_staged<HC, HN>(W, cur2, gb, is_lig, a0, n, lb, lds, sg_latent + (int64_t)pl * HN);
 }
 
 template <typename K>
