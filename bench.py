@@ -217,30 +217,42 @@ def paper_leg(db, n_poses, steps):
 def serve_leg(arch, w, res, seconds):
     """Open-loop Poisson serving: requests of U{1..256} poses (200-1500 atoms),
     grid 48^3 or 64^3 per request, continuous batching on 4 slots with hipGraph
-    replay.  Both forms at equal load (0.7 x the plain path's capacity for this
-    request mix), and the precision form at 0.7 x its own capacity."""
+    replay.  Each form's capacity on this request mix is measured first (a burst
+    of requests, closed loop); then both forms run at equal load -- 0.7 x the
+    plain form's capacity -- and the precision form also at 0.7 x its own."""
     import numpy as np
     import synth
     from paper_2104_04547_amd.serve import Engine, make_requests, run_open_loop, warm_up
-    f48, f64 = arch.flops_per_pose(48), arch.flops_per_pose(64)
-    mix = 2.0 / (1.0 + f64 / f48)            # capacity at the 48/64 mix relative to 48^3
     mean_req = 128.5
-    cap = {p: res[p]["poses_per_s"] * mix for p in res}
     t0 = time.perf_counter()
     pool = synth.make_poses("c5", 2048)
     log(f"serving pool: {pool.n_poses} poses in {time.perf_counter() - t0:.1f}s")
-    runs = [("bf16", 0.7 * cap["fp32"], "equal_load"), ("fp32", 0.7 * cap["fp32"], "equal_load"),
-            ("bf16", 0.7 * cap["bf16"], "own_capacity")]
+    f48, f64 = arch.flops_per_pose(48), arch.flops_per_pose(64)
+    mix = 2.0 / (1.0 + f64 / f48)            # rough capacity at the 48/64 mix relative to 48^3
     out = {}
     engines = {}
+    cap = {}
     try:
+        for prec in ("bf16", "fp32"):
+            engines[prec] = Engine(arch, w, prec, n_slots=4, slot_poses=512, slot_atoms=512 * 1600,
+                                   hbm_budget_bytes=64 << 30)
+            t0 = time.perf_counter()
+            warm_up(engines[prec], pool)
+            log(f"serving {prec}: graphs captured in {time.perf_counter() - t0:.1f}s")
+            # capacity: a burst sized for ~8 s of work at the rough estimate
+            n_req = int(min(400, max(12, 8.0 * res[prec]["poses_per_s"] * mix / mean_req)))
+            reqs = make_requests(pool, n_req, np.random.default_rng(5))
+            t0 = time.perf_counter()
+            tickets = [(engines[prec].submit(b, G), b.n_poses) for b, G in reqs]
+            for t, n in tickets:
+                engines[prec].result(t, n)
+            dt = time.perf_counter() - t0
+            cap[prec] = sum(n for _, n in tickets) / dt
+            out[f"{prec}_capacity_poses_per_s"] = round(cap[prec], 2)
+            log(f"serving {prec}: capacity {cap[prec]:.1f} poses/s on this mix ({n_req} requests in {dt:.1f}s)")
+        runs = [("bf16", 0.7 * cap["fp32"], "equal_load"), ("fp32", 0.7 * cap["fp32"], "equal_load"),
+                ("bf16", 0.7 * cap["bf16"], "own_capacity")]
         for prec, poses_rate, tag in runs:
-            if prec not in engines:
-                engines[prec] = Engine(arch, w, prec, n_slots=4, slot_poses=512, slot_atoms=512 * 1600,
-                                       hbm_budget_bytes=64 << 30)
-                t0 = time.perf_counter()
-                warm_up(engines[prec], pool)
-                log(f"serving {prec}: graphs captured in {time.perf_counter() - t0:.1f}s")
             rps = poses_rate / mean_req
             n_req = max(20, int(rps * seconds))
             reqs = make_requests(pool, n_req, np.random.default_rng(7))
