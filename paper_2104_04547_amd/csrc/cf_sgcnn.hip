@@ -47,16 +47,22 @@ __device__ inline void sg_embed(const SgWeights &W, const float *__restrict__ fe
 }
 
 // Neighbour sums of atoms [blk, blk+nblk) into A (row stride ld) and their current
-// states into Hc; rows past the pose are zero.
+// states into Hc; rows past the pose are zero.  Each thread owns four consecutive
+// features of a row (one 16-byte load per neighbour row segment), H / 4 threads
+// share a row, and the neighbour loop keeps several rows in flight; every
+// feature's sum runs over the row's neighbours in CSR order.
 template <int H>
 __device__ inline void sg_aggregate(const float *__restrict__ cur, const int32_t *__restrict__ rowp,
                                     const int32_t *__restrict__ colp, int64_t cap, int csr_global, int a0, int base,
                                     int64_t lb, int n, int blk, int nblk, int ld, float *A, float *Hc,
                                     int64_t *status) {
-  for (int e = threadIdx.x; e < nblk * H; e += kThreads) {
-    const int a = e / H, oo = e % H;
+  constexpr int TPR = H / 4;              // threads per row
+  constexpr int RPI = kThreads / TPR;     // rows per pass
+  static_assert(H % 4 == 0 && kThreads % TPR == 0, "row split");
+  const int tr = threadIdx.x / TPR, c4 = (threadIdx.x % TPR) * 4;
+  for (int a = tr; a < nblk; a += RPI) {
     const int i = blk + a;
-    float s = 0.0f, hc = 0.0f;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f), hc = s;
     if (i < n) {
       const int64_t ri = csr_global ? (int64_t)a0 + i : lb + i;
       int64_t e0 = rowp[ri], e1 = rowp[ri + 1];
@@ -66,20 +72,25 @@ __device__ inline void sg_aggregate(const float *__restrict__ cur, const int32_t
         e0 = e1;
       }
       // branch-free body (a column outside the pose reads the atom's own row and
-      // adds nothing) so that several neighbour rows are in flight at once
-#pragma unroll 4
+      // adds nothing) so that the loads of several neighbours overlap
+#pragma unroll 8
       for (int64_t q = e0; q < e1; ++q) {
         int64_t j = colp[q];
         if (csr_global) j -= base;
         const bool bad = j < lb || j >= lb + n;
         if (bad) dev_fail(status, kDevBadGraph);
-        const float v = cur[(bad ? lb + i : j) * H + oo];
-        s += bad ? 0.0f : v;
+        const float4 v = *reinterpret_cast<const float4 *>(cur + (bad ? lb + i : j) * H + c4);
+        if (!bad) {
+          s.x += v.x;
+          s.y += v.y;
+          s.z += v.z;
+          s.w += v.w;
+        }
       }
-      hc = cur[(lb + i) * H + oo];
+      hc = *reinterpret_cast<const float4 *>(cur + (lb + i) * H + c4);
     }
-    A[a * ld + oo] = s;
-    Hc[a * ld + oo] = hc;
+    *reinterpret_cast<float4 *>(A + a * ld + c4) = s;
+    *reinterpret_cast<float4 *>(Hc + a * ld + c4) = hc;
   }
 }
 
