@@ -282,7 +282,11 @@ struct Conv8Cfg {
   static_assert(KS >= 3 && KS % 2 == 1, "odd kernel of at least 3 taps per axis");
   static constexpr int PAD = (KS - 1) / 2;
   static constexpr int HZ = TZ * S + KS - S, HY = TY * S + KS - S, HX = TX * S + KS - S;
-  static constexpr int ROW = HX * 16 + 16;  // bytes, padded
+  // Row pitch.  A 16-lane group of a 16-byte LDS read covers two 8-voxel output
+  // rows; a pitch of 128 mod 256 bytes puts those rows on disjoint banks.  Used
+  // when the halo still fits twice per CU, else the tight pitch.
+  static constexpr int ROW_CF = ((HX * 16 + 127) / 256) * 256 + 128;
+  static constexpr int ROW = (HZ * HY * ROW_CF <= 81920) ? ROW_CF : HX * 16 + 16;  // bytes
   static constexpr int SLAB = HY * ROW;
   static constexpr int HALO = HZ * SLAB;
   static constexpr int MT = TZ * TY * TX;
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   };
   // weight prefetch distance in pairs, even (the row fragments ping-pong inside
   // the unrolled pair loop); the packed weights carry 4 zero pairs past the end
-  constexpr int kPF = C::NB <= 2 ? 4 : 2;
+  constexpr int kPF = (C::NB <= 2 && KS > 3) ? 4 : 2;
   const int pair_bytes = nchunks * cout_pad32 * 16 * 2;
   const __amdgpu_buffer_rsrc_t wrs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(wpk), (short)0, wbytes, 0x00020000);
