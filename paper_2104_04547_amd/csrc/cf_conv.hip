@@ -585,6 +585,10 @@ const Variant kVariants[] = {
     CF_VARIANT(3, 1, 4, 8, 8, 4, 64),    // 32
     CF_VARIANT(3, 2, 4, 8, 8, 4, 64),    // 33
     CF_VARIANT(3, 2, 4, 4, 8, 4, 64),    // 34
+    // stride-2 tiles whose halo allows one workgroup per CU: eight waves hide more latency
+    CF_VARIANT8(7, 2, 8, 8, 8, 8, 64),   // 35
+    CF_VARIANT8(7, 2, 4, 8, 8, 8, 128),  // 36
+    CF_VARIANT8(5, 2, 8, 8, 8, 8, 32)    // 37
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -606,7 +610,7 @@ int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
   // measured on MI355X at 48^3 (bf16: tap pairs for stride 1 and the 128-column
   // stride-2 layer; fp32 has no tap-pair kernel)
   const int pref[] = {12, 17, 20, 19, 23, 26, 28, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 21, 22,
-                      24, 25, 27, 29, 30, 31, 32, 33, 34};
+                      24, 25, 27, 29, 30, 31, 32, 33, 34, 35, 36, 37};
   for (int v : pref)
     if (conv_variant_ok(v, L, bf16)) return v;
   return -1;
