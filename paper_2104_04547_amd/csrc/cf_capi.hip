@@ -62,6 +62,9 @@ struct cf_ctx {
   float *head_prm = nullptr;
   int64_t *status = nullptr;
   std::vector<void *> weight_allocs;
+  // second stream for the graph / SG-CNN branch of cf_score_poses, joined by events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_sg = nullptr, ev_head = nullptr;
 
   // per-kernel timing (diagnostics, off by default)
   struct Pending {
@@ -680,6 +683,10 @@ void free_ctx(cf_ctx *c) {
   for (auto &b : c->act)
     if (b.p) (void)hipFree(b.p);
   if (c->status) (void)hipFree(c->status);
+  hipEvent_t evs[] = {c->ev_fork, c->ev_sg, c->ev_head};
+  for (hipEvent_t e : evs)
+    if (e) (void)hipEventDestroy(e);
+  if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
 }
 
@@ -731,6 +738,12 @@ int cf_create(const void *blob, size_t nbytes, int precision, int64_t hbm_budget
         hipMemset(c->status, 0, 4 * sizeof(int64_t)) != hipSuccess)
       rc = fail(CF_ERR_OOM, "status word allocation failed");
   }
+  if (rc == CF_OK &&
+      (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&c->ev_sg, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&c->ev_head, hipEventDisableTiming) != hipSuccess))
+    rc = fail(CF_ERR_HIP, "stream or event creation failed");
   if (rc != CF_OK) {
     free_ctx(c);
     return rc;
@@ -857,10 +870,40 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
   if ((rc = ensure(c, c->cnn_lat, (size_t)chunk * c->lc * sizeof(float)))) return rc;
   if ((rc = ensure(c, c->sg_lat, (size_t)chunk * c->sgw * sizeof(float)))) return rc;
   const int H = c->sgw;
+  // The graph / SG-CNN branch of each chunk runs on the context's side stream,
+  // overlapping the chunk's voxelisation and conv stack; the head joins them.  The
+  // side stream starts after the caller's prior work on `stream` (ev_fork) and each
+  // chunk's branch after the previous chunk's head has read sg_lat (ev_head).
+  hipStream_t s2 = c->side;
+  CF_HIP(hipEventRecord(c->ev_fork, s));
   for (int p0 = 0; p0 < b->n_poses; p0 += chunk) {
     const int np = std::min(chunk, b->n_poses - p0);
     const int32_t *cen;
     const double atoms = (double)b->n_atoms * np / b->n_poses;  // for the byte counts only
+    CF_HIP(hipStreamWaitEvent(s2, p0 == 0 ? c->ev_fork : c->ev_head, 0));
+    hipEvent_t eg = tbegin(c, s2);
+    CF_HIP(cf::launch_graph(b->atom_off, b->n_atoms, b->xyz, p0, np, c->desc.r_cov_u, c->desc.r_nc_u, (int32_t *)c->cov_row.p,
+                            (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
+                            acap * 96, (int32_t *)c->deg.p, acap, (int64_t *)c->pose_tot.p, c->status, s2));
+    // algorithmic bytes: coordinates read once, two row-pointer arrays and 4 B per
+    // edge written (the edge totals arrive with the events)
+    tend(c, s2, eg, "graph", 0.0, atoms * (12.0 + 8.0));
+    if (c->timing && !c->pending.empty() && c->pending.back().key == "graph") {
+      int64_t *slot = pin_slots(c);
+      const int64_t *pt = (const int64_t *)c->pose_tot.p;
+      if (slot) {
+        const int64_t idx[4] = {np - 1, 2 * (int64_t)np - 1, 3 * (int64_t)np - 1, 4 * (int64_t)np - 1};
+        for (int q = 0; q < 4; ++q)
+          CF_HIP(hipMemcpyAsync(slot + q, pt + idx[q], sizeof(int64_t), hipMemcpyDeviceToHost, s2));
+        c->pending.back().edges = slot;
+      }
+    }
+    eg = tbegin(c, s2);
+    CF_HIP(cf::launch_sgcnn(c->sg, c->bf16, b->atom_off, b->n_atoms, b->feat, b->is_lig, p0, np, (int32_t *)c->cov_row.p,
+                            (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
+                            acap * 96, 0, (float *)c->hbuf.p, acap, (float *)c->sg_lat.p, c->status, s2));
+    tend(c, s2, eg, "sgcnn", atoms * c->sg_flop_atom, atoms * 4.0 * CF_NCH);
+    CF_HIP(hipEventRecord(c->ev_sg, s2));
     if (b->center) {
       cen = b->center + 3 * (size_t)p0;
     } else {
@@ -874,32 +917,12 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
                             grid_cpad(c), c->status, s));
     tend(c, s, e, "splat", 0.0, atoms * (12.0 + 4.0 * CF_NCH) + (double)np * G * G * G * CF_NCH * elem_size(c));
     if ((rc = run_cnn(c, G, np, (float *)c->cnn_lat.p, s))) return rc;
-    e = tbegin(c, s);
-    CF_HIP(cf::launch_graph(b->atom_off, b->n_atoms, b->xyz, p0, np, c->desc.r_cov_u, c->desc.r_nc_u, (int32_t *)c->cov_row.p,
-                            (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
-                            acap * 96, (int32_t *)c->deg.p, acap, (int64_t *)c->pose_tot.p, c->status, s));
-    // algorithmic bytes: coordinates read once, two row-pointer arrays and 4 B per
-    // edge written (the edge totals arrive with the events)
-    tend(c, s, e, "graph", 0.0, atoms * (12.0 + 8.0));
-    if (c->timing && !c->pending.empty() && c->pending.back().key == "graph") {
-      int64_t *slot = pin_slots(c);
-      const int64_t *pt = (const int64_t *)c->pose_tot.p;
-      if (slot) {
-        const int64_t idx[4] = {np - 1, 2 * (int64_t)np - 1, 3 * (int64_t)np - 1, 4 * (int64_t)np - 1};
-        for (int q = 0; q < 4; ++q)
-          CF_HIP(hipMemcpyAsync(slot + q, pt + idx[q], sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        c->pending.back().edges = slot;
-      }
-    }
-    e = tbegin(c, s);
-    CF_HIP(cf::launch_sgcnn(c->sg, c->bf16, b->atom_off, b->n_atoms, b->feat, b->is_lig, p0, np, (int32_t *)c->cov_row.p,
-                            (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
-                            acap * 96, 0, (float *)c->hbuf.p, acap, (float *)c->sg_lat.p, c->status, s));
-    tend(c, s, e, "sgcnn", atoms * c->sg_flop_atom, atoms * 4.0 * CF_NCH);
+    CF_HIP(hipStreamWaitEvent(s, c->ev_sg, 0));
     e = tbegin(c, s);
     CF_HIP(cf::launch_head((float *)c->cnn_lat.p, c->lc, (float *)c->sg_lat.p, H, c->head_prm, c->head, np,
                            scores + p0, s));
     tend(c, s, e, "fusion", 0.0, 0.0);
+    CF_HIP(hipEventRecord(c->ev_head, s));
   }
   return CF_OK;
 }
