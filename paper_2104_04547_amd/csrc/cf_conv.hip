@@ -277,52 +277,84 @@ __global__ __launch_bounds__(NW * 64) void k_conv(const T *__restrict__ in, cons
 // voxel, so an 8x8x8 output tile (128 rows per wave, 8 MFMAs per step) fits twice
 // per CU, halving the weight traffic per FLOP of the 64-row tiles; and a 19-channel
 // input costs 3 chunks instead of the 2 x 16 = 32 padded channels.
-template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+//
+// Two further knobs serve the 64 -> 128 stride-2 layer, whose 12^3 output tiles
+// poorly and whose weights do not stay in L2: WN waves split the columns (each
+// wave 64 x 64, half the weight loads per MFMA of a 32 x 128 wave), and PP poses
+// share one workgroup (the same tile of consecutive poses, one halo each), so one
+// pass over the weights serves PP times the rows.
+template <int KS, int S, int TZ, int TY, int TX, int NW, int NT, int WN, int PP>
 struct Conv8Cfg {
   static_assert(KS >= 3 && KS % 2 == 1, "odd kernel of at least 3 taps per axis");
   static constexpr int PAD = (KS - 1) / 2;
   static constexpr int HZ = TZ * S + KS - S, HY = TY * S + KS - S, HX = TX * S + KS - S;
   // Row pitch.  A 16-lane group of a 16-byte LDS read covers two 8-voxel output
-  // rows; a pitch of 128 mod 256 bytes puts those rows on disjoint banks.  Used
-  // when the halo still fits twice per CU, else the tight pitch.
-  static constexpr int ROW_CF = ((HX * 16 + 127) / 256) * 256 + 128;
-  static constexpr int ROW = (HZ * HY * ROW_CF <= 81920) ? ROW_CF : HX * 16 + 16;  // bytes
+  // rows; a pitch of 128 mod 256 bytes puts those rows on disjoint banks.  Taken
+  // unless only a tighter pitch keeps two workgroups per CU (or fits at all):
+  // then the tight pitch + 16 bytes, or without the 16 bytes as a last resort.
+  static constexpr int ROW_CF = ((HX * 16 + 127) / 256) * 256 + 128, ROW_T = HX * 16 + 16;
+  static constexpr int PLANES = PP * HZ * HY;
+  static constexpr int ROW = (PLANES * ROW_CF <= 81920)   ? ROW_CF
+                             : (PLANES * ROW_T <= 81920)  ? ROW_T
+                             : (PLANES * ROW_CF <= 163840) ? ROW_CF
+                             : (PLANES * ROW_T <= 163840)  ? ROW_T
+                                                           : HX * 16;  // bytes
   static constexpr int SLAB = HY * ROW;
-  static constexpr int HALO = HZ * SLAB;
-  static constexpr int MT = TZ * TY * TX;
-  static constexpr int WM = MT / NW;
-  static constexpr int MB = WM / 32, NB = NT / 32;
+  // PP poses per workgroup (the same tile of consecutive poses): the halo of
+  // pose pp sits at pp * HALO1, its rows are tile rows pp * MT1 .. + MT1.  Each
+  // weight fragment then serves PP times the rows.
+  static constexpr int HALO1 = HZ * SLAB, HALO = PP * HALO1;
+  static constexpr int MT1 = TZ * TY * TX, MT = PP * MT1;
+  // the NW waves form NWM row groups x WN column groups: wave w takes rows
+  // (w / WN) * WM .. + WM and columns (w % WN) * NT / WN .. + NT / WN
+  static constexpr int NWM = NW / WN;
+  static constexpr int WM = MT / NWM;
+  static constexpr int MB = WM / 32, NB = NT / WN / 32;
   static constexpr int TAPS = KS * KS * KS, PAIRS = (TAPS + 1) / 2;
-  // epilogue: output rows go through LDS in groups of MBG 32-row blocks per wave
-  static constexpr int MBG = (NW * 32 * NT * 2 * MB <= HALO) ? MB : ((NW * 32 * NT * 2 * 2 <= HALO && MB % 2 == 0) ? 2 : 1);
-  static constexpr int EPI = NW * 32 * MBG * NT * 2;
+  // epilogue: output rows go through LDS in groups of MBG 32-row blocks per row group
+  static constexpr int MBG = (NWM * 32 * NT * 2 * MB <= HALO) ? MB : ((NWM * 32 * NT * 2 * 2 <= HALO && MB % 2 == 0) ? 2 : 1);
+  static constexpr int EPI = NWM * 32 * MBG * NT * 2;
   static constexpr int LDS = HALO > EPI ? HALO : EPI;
+  // Waves per SIMD the tile allows: a halo above half the LDS leaves one
+  // workgroup per CU, so a four-wave workgroup owns its SIMDs' whole register file
+  // (512 per lane); six-wave workgroups run two per CU (three waves per SIMD).
+  static constexpr int WPE = (NW == 6 || NW == 12) ? 3 : ((LDS > 81920 && NW <= 4) ? 1 : 2);
+  // Halo voxels each thread loads per chunk, and how many of those loads are in
+  // flight at once (one batch per L2 round trip): all of them where the
+  // registers allow, else batches of 6 beside 128 accumulator registers.
+  static constexpr int NV1 = HZ * HY * HX, HITER = (PP * NV1 + NW * 64 - 1) / (NW * 64);
+  static constexpr int HB_MAX = WPE == 1 ? 40 : (MB * NB <= 4 ? 16 : 6);
+  static constexpr int HB = HITER < HB_MAX ? HITER : HB_MAX;
+  static_assert(NW % WN == 0 && NT % (32 * WN) == 0, "waves split the columns in 32-column blocks");
   static_assert(WM % 32 == 0, "rows per wave must be a multiple of 32");
   static_assert(LDS <= 163840, "halo exceeds LDS");
 };
 
-template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_conv8(const bf16_t *__restrict__ in, const bf16_t *__restrict__ wpk,
+template <int KS, int S, int TZ, int TY, int TX, int NW, int NT, int WN, int PP>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv8Cfg<KS, S, TZ, TY, TX, NW, NT, WN, PP>::WPE))) void k_conv8(const bf16_t *__restrict__ in, const bf16_t *__restrict__ wpk,
                                                     const float *__restrict__ bias, const bf16_t *__restrict__ res,
-                                                    bf16_t *__restrict__ out, int D, int Do, int cin_pad,
+                                                    bf16_t *__restrict__ out, int n_poses, int D, int Do, int cin_pad,
                                                     int nchunks, int cout_pad32, int cout, int cout_store, int nty,
                                                     int ntx, int wbytes) {
-  using C = Conv8Cfg<KS, S, TZ, TY, TX, NW, NT>;
+  using C = Conv8Cfg<KS, S, TZ, TY, TX, NW, NT, WN, PP>;
   __shared__ __attribute__((aligned(16))) char lds[C::LDS];
-  int tile, pose, nblk;
-  xcd_order(tile, pose, nblk);
+  int tile, pblk, nblk;
+  xcd_order(tile, pblk, nblk);
+  const int pose0 = pblk * PP;
   const int n0 = nblk * NT;
   const int tz0 = (tile / (nty * ntx)) * TZ, ty0 = ((tile / ntx) % nty) * TY, tx0 = (tile % ntx) * TX;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wave_m = wave / WN, ncol0 = (wave % WN) * (NT / WN);
   const int khalf = lane >> 5, lrow = lane & 31;
   constexpr int NTH = NW * 64;
 
   int rowoff[C::MB];
 #pragma unroll
   for (int mb = 0; mb < C::MB; ++mb) {
-    const int m = wave * C::WM + mb * 32 + lrow;
-    const int z = m / (TY * TX), y = (m / TX) % TY, x = m % TX;
-    rowoff[mb] = z * C::SLAB + y * C::ROW + x * 16;
+    const int m = wave_m * C::WM + mb * 32 + lrow;
+    const int pp = m / C::MT1, ml = m % C::MT1;
+    const int z = ml / (TY * TX), y = (ml / TX) % TY, x = ml % TX;
+    rowoff[mb] = pp * C::HALO1 + z * C::SLAB + y * C::ROW + x * 16;
   }
   typedef float accv __attribute__((ext_vector_type(16)));
   accv acc[C::MB][C::NB];
@@ -334,12 +366,12 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
       for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
 
   const int oz = tz0 * S - C::PAD, oy = ty0 * S - C::PAD, ox = tx0 * S - C::PAD;
-  const int64_t pose_in = (int64_t)pose * D * D * D;
+  const int64_t pose_in = (int64_t)pose0 * D * D * D;
   constexpr int HZ2 = S == 1 ? 0 : (C::HZ + 1) / 2;
   constexpr int HY2 = S == 1 ? 0 : (C::HY + 1) / 2;
   constexpr int HX2 = S == 1 ? 0 : (C::HX + 1) / 2;
-  constexpr int NV = C::HZ * C::HY * C::HX;
-  constexpr int HITER = (NV + NTH - 1) / NTH;
+  constexpr int NV = PP * C::NV1;
+  constexpr int HITER = C::HITER, HB = C::HB;
   auto tapoff = [&](int dz, int dy, int dx) {
     return (S == 1 ? dz : (dz & 1) * HZ2 + (dz >> 1)) * C::SLAB +
            (S == 1 ? dy : (dy & 1) * HY2 + (dy >> 1)) * C::ROW + (S == 1 ? dx : (dx & 1) * HX2 + (dx >> 1)) * 16;
@@ -369,7 +401,6 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(wpk), (short)0, wbytes, 0x00020000);
   for (int chunk = 0; chunk < nchunks; ++chunk) {
     if (chunk) __syncthreads();
-    constexpr int HB = HITER < 6 ? HITER : 6;  // halo iterations in flight per batch
 #pragma unroll
     for (int it0 = 0; it0 < HITER; it0 += HB) {
       uint4 hv[HB];
@@ -378,19 +409,22 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
         const int v = it * NTH + (int)threadIdx.x;
         hv[it - it0] = make_uint4(0, 0, 0, 0);
         if (v < NV) {
-          const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
+          const int pp = PP == 1 ? 0 : v / C::NV1, vl = PP == 1 ? v : v % C::NV1;
+          const int hx = vl % C::HX, hy = (vl / C::HX) % C::HY, hz = vl / (C::HX * C::HY);
           const int gz = oz + hz, gy = oy + hy, gx = ox + hx;
-          if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gx < (unsigned)D)
+          if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gx < (unsigned)D &&
+              (PP == 1 || pose0 + pp < n_poses))
             hv[it - it0] = *reinterpret_cast<const uint4 *>(
-                in + ((pose_in + ((int64_t)gz * D + gy) * D + gx) * cin_pad + chunk * 8));
+                in + ((pose_in + (((int64_t)pp * D + gz) * D + gy) * D + gx) * cin_pad + chunk * 8));
         }
       }
 #pragma unroll
       for (int it = it0; it < it0 + HB && it < HITER; ++it) {
         const int v = it * NTH + (int)threadIdx.x;
         if (v < NV) {
-          const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
-          const int off = stored_index(hz, C::HZ, S) * C::SLAB + stored_index(hy, C::HY, S) * C::ROW +
+          const int pp = PP == 1 ? 0 : v / C::NV1, vl = PP == 1 ? v : v % C::NV1;
+          const int hx = vl % C::HX, hy = (vl / C::HX) % C::HY, hz = vl / (C::HX * C::HY);
+          const int off = pp * C::HALO1 + stored_index(hz, C::HZ, S) * C::SLAB + stored_index(hy, C::HY, S) * C::ROW +
                           stored_index(hx, C::HX, S) * 16;
           *reinterpret_cast<uint4 *>(lds + off) = hv[it - it0];
         }
@@ -399,7 +433,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     __syncthreads();
     int vb[C::NB];
 #pragma unroll
-    for (int nb = 0; nb < C::NB; ++nb) vb[nb] = ((chunk * cout_pad32 + n0 + nb * 32 + lrow) * 16 + khalf * 8) * 2;
+    for (int nb = 0; nb < C::NB; ++nb) vb[nb] = ((chunk * cout_pad32 + n0 + ncol0 + nb * 32 + lrow) * 16 + khalf * 8) * 2;
     // software pipeline: the weight fragments of pair p + kPF and the LDS row
     // fragments of pair p + 1 are in flight while the MFMAs of pair p issue.  The
     // pair loop is unrolled by kPF so that both rings are indexed at compile time
@@ -454,21 +488,22 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   }
 
   // ---- epilogue through LDS, MBG row blocks per wave at a time ----
-  const int64_t pose_out = (int64_t)pose * Do * Do * Do;
+  const int64_t pose_out = (int64_t)pose0 * Do * Do * Do;
   auto row_base = [&](int m, bool &valid) -> int64_t {
-    const int z = tz0 + m / (TY * TX), y = ty0 + (m / TX) % TY, x = tx0 + m % TX;
-    valid = z < Do && y < Do && x < Do;
-    return (pose_out + ((int64_t)z * Do + y) * Do + x) * cout_store;
+    const int pp = m / C::MT1, ml = m % C::MT1;
+    const int z = tz0 + ml / (TY * TX), y = ty0 + (ml / TX) % TY, x = tx0 + ml % TX;
+    valid = z < Do && y < Do && x < Do && (PP == 1 || pose0 + pp < n_poses);
+    return (pose_out + (((int64_t)pp * Do + z) * Do + y) * Do + x) * cout_store;
   };
-  bf16_t *ot = reinterpret_cast<bf16_t *>(lds);  // [NW][MBG*32][NT]
+  bf16_t *ot = reinterpret_cast<bf16_t *>(lds);  // [NWM][MBG*32][NT]
   constexpr int SEG = NT / 8;
-  constexpr int GR = C::MBG * 32;  // rows per wave per group
-  // local row lr of group g -> tile row (wave lr / GR)*WM + (g + (lr % GR) / 32) * 32 + lr % 32
+  constexpr int GR = C::MBG * 32;  // rows per row group per epilogue group
+  // local row lr of group g -> tile row (lr / GR) * WM + (g + (lr % GR) / 32) * 32 + lr % 32
 #pragma unroll
   for (int g = 0; g < C::MB; g += C::MBG) {
     __syncthreads();
     if (res) {
-      for (int e = threadIdx.x; e < NW * GR * SEG; e += NTH) {
+      for (int e = threadIdx.x; e < C::NWM * GR * SEG; e += NTH) {
         const int lr = e / SEG, q = e % SEG;
         const int m = (lr / GR) * C::WM + g * 32 + lr % GR;
         bool valid;
@@ -482,17 +517,17 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     for (int mb = g; mb < g + C::MBG; ++mb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int lr = wave * GR + (mb - g) * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
+        const int lr = wave_m * GR + (mb - g) * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) {
-          const int col = nb * 32 + lrow;
+          const int col = ncol0 + nb * 32 + lrow;
           float v = acc[mb][nb][r] + bias[n0 + col];
           if (res) v += (float)ot[lr * NT + col];
           ot[lr * NT + col] = (bf16_t)(v > 0.0f ? v : 0.0f);
         }
       }
     __syncthreads();
-    for (int e = threadIdx.x; e < NW * GR * SEG; e += NTH) {
+    for (int e = threadIdx.x; e < C::NWM * GR * SEG; e += NTH) {
       const int lr = e / SEG, q = e % SEG;
       const int m = (lr / GR) * C::WM + g * 32 + lr % GR;
       bool valid;
@@ -511,15 +546,15 @@ struct Variant {
   hipError_t (*launch_f32)(const ConvLayer &, const void *, const void *, void *, int, int, hipStream_t);
 };
 
-template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+template <int KS, int S, int TZ, int TY, int TX, int NW, int NT, int WN, int PP>
 hipError_t launch_p(const ConvLayer &L, const void *in, const void *res, void *out, int n_poses, int D,
                     hipStream_t s) {
   const int Do = (D + 2 * ((KS - 1) / 2) - KS) / S + 1;
   const int ntz = (Do + TZ - 1) / TZ, nty = (Do + TY - 1) / TY, ntx = (Do + TX - 1) / TX;
-  const dim3 grid(ntz * nty * ntx, n_poses, L.cout_pad32 / NT);
-  hipLaunchKernelGGL((k_conv8<KS, S, TZ, TY, TX, NW, NT>), grid, dim3(NW * 64), 0, s,
+  const dim3 grid(ntz * nty * ntx, (n_poses + PP - 1) / PP, L.cout_pad32 / NT);
+  hipLaunchKernelGGL((k_conv8<KS, S, TZ, TY, TX, NW, NT, WN, PP>), grid, dim3(NW * 64), 0, s,
                      reinterpret_cast<const bf16_t *>(in), reinterpret_cast<const bf16_t *>(L.wpk8), L.bias,
-                     reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), D, Do, L.cin_pad,
+                     reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), n_poses, D, Do, L.cin_pad,
                      (L.cin + 7) / 8, L.cout_pad32, L.cout, L.cout_store, nty, ntx, (int)L.wbytes8);
   return hipGetLastError();
 }
@@ -545,7 +580,19 @@ hipError_t launch_t(const ConvLayer &L, const void *in, const void *res, void *o
 #define CF_VARIANT8(KS, S, TZ, TY, TX, NW, NT)                                                   \
   Variant {                                                                                      \
     "p8k" #KS "s" #S "_t" #TZ "x" #TY "x" #TX "_w" #NW "_n" #NT, KS, S, TZ, TY, TX, NW, NT, 1,   \
-        &launch_p<KS, S, TZ, TY, TX, NW, NT>, nullptr                                            \
+        &launch_p<KS, S, TZ, TY, TX, NW, NT, 1, 1>, nullptr                                      \
+  }
+// WN waves across the columns (each wave: NT / WN columns of its row group)
+#define CF_VARIANT8N(KS, S, TZ, TY, TX, NW, NT, WN)                                                      \
+  Variant {                                                                                              \
+    "p8k" #KS "s" #S "_t" #TZ "x" #TY "x" #TX "_w" #NW "c" #WN "_n" #NT, KS, S, TZ, TY, TX, NW, NT, 1,   \
+        &launch_p<KS, S, TZ, TY, TX, NW, NT, WN, 1>, nullptr                                             \
+  }
+// ... and PP poses per workgroup
+#define CF_VARIANT8P(KS, S, TZ, TY, TX, NW, NT, WN, PP)                                                           \
+  Variant {                                                                                                       \
+    "p8k" #KS "s" #S "_t" #TZ "x" #TY "x" #TX "_w" #NW "c" #WN "_n" #NT "_p" #PP, KS, S, TZ, TY, TX, NW, NT, 1,   \
+        &launch_p<KS, S, TZ, TY, TX, NW, NT, WN, PP>, nullptr                                                     \
   }
 
 const Variant kVariants[] = {
@@ -588,7 +635,15 @@ const Variant kVariants[] = {
     // stride-2 tiles whose halo allows one workgroup per CU: eight waves hide more latency
     CF_VARIANT8(7, 2, 8, 8, 8, 8, 64),   // 35
     CF_VARIANT8(7, 2, 4, 8, 8, 8, 128),  // 36
-    CF_VARIANT8(5, 2, 8, 8, 8, 8, 32)    // 37
+    CF_VARIANT8(5, 2, 8, 8, 8, 8, 32),   // 37
+    // 128-column stride-2 layers with the columns split over two waves (64 rows x
+    // 64 columns per wave: half the weight-fragment loads per MFMA of 17/22)
+    CF_VARIANT8N(7, 2, 4, 4, 12, 6, 128, 2),  // 38: 12^3 outputs in 9 whole tiles
+    CF_VARIANT8N(7, 2, 4, 4, 8, 4, 128, 2),   // 39
+    // two poses per workgroup: 384 rows share each weight fragment (the 5.6 MB of
+    // weights of the 64 -> 128 layer exceed an XCD's L2, so weight traffic per row
+    // sets its speed); 12^3 outputs in 9 whole tiles
+    CF_VARIANT8P(7, 2, 4, 4, 12, 8, 128, 2, 2)    // 40
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -608,9 +663,9 @@ bool conv_variant_ok(int v, const ConvLayer &L, int bf16) {
 int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
   (void)D_in;
   // measured on MI355X at 48^3 (bf16: tap pairs for stride 1 and the 128-column
-  // stride-2 layer; fp32 has no tap-pair kernel)
-  const int pref[] = {12, 17, 20, 19, 23, 26, 28, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 21, 22,
-                      24, 25, 27, 29, 30, 31, 32, 33, 34, 35, 36, 37};
+  // stride-2 layer, two poses per workgroup there; fp32 has no tap-pair kernel)
+  const int pref[] = {12, 40, 17, 20, 19, 23, 26, 28, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 21,
+                      22, 24, 25, 27, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39};
   for (int v : pref)
     if (conv_variant_ok(v, L, bf16)) return v;
   return -1;

@@ -42,12 +42,17 @@ def demangle(names: List[str]) -> Dict[str, str]:
     return out
 
 
-_CONV8 = re.compile(r"k_conv8<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+)>")
+_CONV8 = re.compile(r"k_conv8<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+)(?:, (\d+))?>")
 _CONV = re.compile(r"k_conv<([^,]+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+)>")
 _PLAIN = re.compile(r"(?:cf::\(anonymous namespace\)::)?(k_\w+)")
 
 
 _MANGLED_CONV = re.compile(r"k_conv(8?)I(DF16b|f)?((?:Li\d+E)+)E")
+
+
+def _split(wn: int) -> str:
+    """Column split of the tap-pair conv as in the library's variant names."""
+    return f"c{wn}" if wn > 1 else ""
 
 
 def short_name(name: str) -> str:
@@ -57,14 +62,15 @@ def short_name(name: str) -> str:
     if m:   # names c++filt leaves mangled (bfloat16 template arguments)
         p8, t, ints = m.groups()
         v = [int(x) for x in re.findall(r"Li(\d+)E", ints)]
-        if len(v) == 7:
-            ks, s, tz, ty, tx, nw, nt = v
+        if len(v) in (7, 8):
+            ks, s, tz, ty, tx, nw, nt = v[:7]
+            wn = v[7] if len(v) == 8 else 1
             pre = "conv.p8" if p8 else ("conv.f32." if t == "f" else "conv.")
-            return f"{pre}k{ks}s{s}_t{tz}x{ty}x{tx}_w{nw}_n{nt}"
+            return f"{pre}k{ks}s{s}_t{tz}x{ty}x{tx}_w{nw}{_split(wn)}_n{nt}"
     m = _CONV8.search(name)
     if m:
-        ks, s, tz, ty, tx, nw, nt = m.groups()
-        return f"conv.p8k{ks}s{s}_t{tz}x{ty}x{tx}_w{nw}_n{nt}"
+        ks, s, tz, ty, tx, nw, nt, wn = m.groups()
+        return f"conv.p8k{ks}s{s}_t{tz}x{ty}x{tx}_w{nw}{_split(int(wn or 1))}_n{nt}"
     m = _CONV.search(name)
     if m:
         t, ks, s, tz, ty, tx, nw, nt = m.groups()

@@ -23,7 +23,7 @@ def cases():
     out = {}
     for arch_name, G in (("tiny", 24), ("full", 24), ("full", 40), ("paper", 24), ("paper", 40)):
         arch, w = weights(arch_name)
-        b = synth.make_poses("c1" if G == 24 else "c2", 2)
+        b = synth.make_poses("c1" if G == 24 else "c2", 3)  # odd: a lone pose in two-pose tiles
         cen = np.stack([oracle.pose_center(b.xyz[b.atom_off[p]:b.atom_off[p + 1]][
             b.is_lig[b.atom_off[p]:b.atom_off[p + 1]].astype(bool)]) for p in range(b.n_poses)])
         grids = oracle.splat_batch(b, cen, G)
