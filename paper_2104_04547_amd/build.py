@@ -18,9 +18,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["cf_splat.hip", "cf_graph.hip", "cf_conv.hip", "cf_head.hip", "cf_sgcnn.hip", "cf_capi.hip",
+SOURCES = ["cf_splat.hip", "cf_graph.hip", "cf_conv.hip", "cf_fftconv.hip", "cf_head.hip", "cf_sgcnn.hip", "cf_capi.hip",
            "cf_engine.hip", "cf_select.hip"]
-HEADERS = ["cf_internal.h"]
+HEADERS = ["cf_internal.h", "cf_fft32.h"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

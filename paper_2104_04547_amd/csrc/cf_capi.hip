@@ -87,6 +87,7 @@ struct cf_ctx {
   // scratch
   DevBuf grid, centers, cnn_lat, sg_lat, deg, pose_tot, cov_row, cov_col, nc_row, nc_col, hbuf, sel;
   std::vector<DevBuf> act;  // t_1 .. t_L
+  DevBuf convwork;          // scratch of the frequency-domain conv (spectra)
   std::map<int, std::vector<int>> variants;  // per G
 };
 
@@ -178,12 +179,16 @@ int64_t scratch_after(const cf_ctx *c, int G, int64_t n, int64_t atoms) {
   };
   grow(c->grid, n * G * G * G * grid_cpad(c) * (int64_t)elem_size(c));
   int D = G;
+  int64_t work = 0;
   for (size_t i = 0; i < c->conv.size(); ++i) {
+    // the frequency-domain path's spectra, wherever it may be selected
+    if (c->bf16 && cf::fft_conv_ok(c->conv[i], D)) work = std::max(work, cf::fft_conv_work_bytes(c->conv[i], D, n));
     D = conv_out_dim(D, c->conv[i].k, c->conv[i].stride);
     const int64_t need = n * D * D * D * c->conv[i].cout_store * (int64_t)elem_size(c);
     if (i < c->act.size()) grow(c->act[i], need);
     else t += need;
   }
+  grow(c->convwork, work);
   grow(c->centers, n * 3 * 4);
   grow(c->cnn_lat, n * c->lc * 4);
   grow(c->sg_lat, n * c->sgw * 4);
@@ -267,6 +272,15 @@ int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s) {
   std::vector<int> var;
   int rc = variants_for(c, G, var);
   if (rc) return rc;
+  {
+    int64_t work = 0;
+    int D = G;
+    for (size_t i = 0; i < c->conv.size(); ++i) {
+      work = std::max(work, cf::conv_work_bytes(var[i], c->conv[i], D, np));
+      D = conv_out_dim(D, c->conv[i].k, c->conv[i].stride);
+    }
+    if (work > 0 && (rc = ensure(c, c->convwork, (size_t)work))) return rc;
+  }
   std::vector<const void *> t;
   t.push_back(c->grid.p);
   int D = G;
@@ -275,7 +289,7 @@ int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s) {
     const void *res = L.res_src >= 0 ? t[L.res_src] : nullptr;
     const int Do = conv_out_dim(D, L.k, L.stride);
     hipEvent_t e = tbegin(c, s);
-    CF_HIP(cf::launch_conv(var[i], L, c->bf16, t[i], res, c->act[i].p, np, D, s));
+    CF_HIP(cf::launch_conv(var[i], L, c->bf16, t[i], res, c->act[i].p, np, D, c->convwork.p, s));
     if (e) {
       const double vox = (double)Do * Do * Do * np;
       const double flop = 2.0 * L.cin * L.cout * L.k * L.k * L.k * vox;
@@ -546,6 +560,19 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
       L.wbytes8 = (int64_t)(pk8.size() * sizeof(bf16_t));
       rc = alloc_weight(c, &L.wpk8, pk8.size() * sizeof(bf16_t), pk8.data());
     }
+    if (!rc && c->bf16 && cf::fft_conv_layer_ok(L)) {
+      // frequency-domain path: in-plane spectra of the folded weights, built on the device
+      L.gspec_bytes = cf::fft_conv_gspec_bytes(L);
+      rc = alloc_weight(c, &L.gspec, (size_t)L.gspec_bytes, nullptr);
+      float *wd = nullptr;
+      if (!rc && hipMalloc(&wd, Wf.size() * sizeof(float)) != hipSuccess) rc = fail(CF_ERR_OOM, "weight staging failed");
+      if (!rc) {
+        if (hipMemcpy(wd, Wf.data(), Wf.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+            cf::fft_conv_prepare(L, wd, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+          rc = fail(CF_ERR_HIP, "weight spectra failed");
+        (void)hipFree(wd);
+      }
+    }
     if (rc) return rc;
     if ((rc = upload_f(c, &L.bias, bf.data(), bf.size()))) return rc;
     c->conv.push_back(L);
@@ -682,6 +709,7 @@ void free_ctx(cf_ctx *c) {
     if (b->p) (void)hipFree(b->p);
   for (auto &b : c->act)
     if (b.p) (void)hipFree(b.p);
+  if (c->convwork.p) (void)hipFree(c->convwork.p);
   if (c->status) (void)hipFree(c->status);
   hipEvent_t evs[] = {c->ev_fork, c->ev_sg, c->ev_head};
   for (hipEvent_t e : evs)
@@ -1024,9 +1052,13 @@ int cf_set_conv_variants(cf_ctx *c, int G, const int32_t *variants, int32_t n_la
   if (rc) return rc;
   if (n_layers != (int32_t)c->conv.size()) return fail(CF_ERR_INVALID_ARG, "one variant per conv layer is needed");
   std::vector<int> v(variants, variants + n_layers);
-  for (int i = 0; i < n_layers; ++i)
-    if (!cf::conv_variant_ok(v[i], c->conv[i], c->bf16))
+  int D = G;
+  for (int i = 0; i < n_layers; ++i) {
+    if (!cf::conv_variant_ok(v[i], c->conv[i], c->bf16, D))
       return fail(CF_ERR_UNSUPPORTED, "variant does not fit layer " + std::to_string(i));
+    D = conv_out_dim(D, c->conv[i].k, c->conv[i].stride);
+    if (D < 1) return fail(CF_ERR_UNSUPPORTED, "grid too small for the conv stack");
+  }
   c->variants[G] = v;
   return CF_OK;
 }
@@ -1054,17 +1086,29 @@ int cf_autotune(cf_ctx *c, int G, int32_t n_poses, void *stream) {
   CF_HIP(hipEventCreate(&e1));
   std::vector<const void *> t{c->grid.p};
   for (auto &b : c->act) t.push_back(b.p);
+  {
+    int64_t work = 0;
+    int D = G;
+    for (size_t i = 0; i < c->conv.size(); ++i) {
+      for (int v = 0; v < cf::conv_num_variants(); ++v)
+        if (cf::conv_variant_ok(v, c->conv[i], c->bf16, D))
+          work = std::max(work, cf::conv_work_bytes(v, c->conv[i], D, np));
+      D = conv_out_dim(D, c->conv[i].k, c->conv[i].stride);
+    }
+    if (work > 0 && (rc = ensure(c, c->convwork, (size_t)work))) return rc;
+  }
   int D = G;
   for (size_t i = 0; i < c->conv.size(); ++i) {
     const auto &L = c->conv[i];
     float best_ms = 1e30f;
     int best_v = -1;
     for (int v = 0; v < cf::conv_num_variants(); ++v) {
-      if (!cf::conv_variant_ok(v, L, c->bf16)) continue;
+      if (!cf::conv_variant_ok(v, L, c->bf16, D)) continue;
       const void *res = L.res_src >= 0 ? t[L.res_src] : nullptr;
-      CF_HIP(cf::launch_conv(v, L, c->bf16, t[i], res, c->act[i].p, np, D, s));  // warm-up
+      void *wk = c->convwork.p;
+      CF_HIP(cf::launch_conv(v, L, c->bf16, t[i], res, c->act[i].p, np, D, wk, s));  // warm-up
       CF_HIP(hipEventRecord(e0, s));
-      for (int rep = 0; rep < 3; ++rep) CF_HIP(cf::launch_conv(v, L, c->bf16, t[i], res, c->act[i].p, np, D, s));
+      for (int rep = 0; rep < 3; ++rep) CF_HIP(cf::launch_conv(v, L, c->bf16, t[i], res, c->act[i].p, np, D, wk, s));
       CF_HIP(hipEventRecord(e1, s));
       CF_HIP(hipEventSynchronize(e1));
       float ms = 0;

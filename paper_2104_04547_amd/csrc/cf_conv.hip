@@ -649,10 +649,16 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 }  // namespace
 
-int conv_num_variants() { return kNumVariants; }
-const char *conv_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : "?"; }
+// one more variant id past the direct kernels: the frequency-domain path
+constexpr int kFftVariant = kNumVariants;
 
-bool conv_variant_ok(int v, const ConvLayer &L, int bf16) {
+int conv_num_variants() { return kNumVariants + 1; }
+const char *conv_variant_name(int v) {
+  return (v >= 0 && v < kNumVariants) ? kVariants[v].name : (v == kFftVariant ? "fft32" : "?");
+}
+
+bool conv_variant_ok(int v, const ConvLayer &L, int bf16, int D_in) {
+  if (v == kFftVariant) return bf16 && fft_conv_ok(L, D_in);
   if (v < 0 || v >= kNumVariants) return false;
   const Variant &V = kVariants[v];
   if (V.pairs) return bf16 && L.wpk8 && V.ks == L.k && V.s == L.stride && L.cout_pad32 % V.nt == 0 && L.cin_pad % 8 == 0;
@@ -661,19 +667,23 @@ bool conv_variant_ok(int v, const ConvLayer &L, int bf16) {
 }
 
 int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
-  (void)D_in;
   // measured on MI355X at 48^3 (bf16: tap pairs for stride 1 and the 128-column
   // stride-2 layer, two poses per workgroup there; fp32 has no tap-pair kernel)
   const int pref[] = {12, 40, 17, 20, 19, 23, 26, 28, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 21,
                       22, 24, 25, 27, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39};
   for (int v : pref)
-    if (conv_variant_ok(v, L, bf16)) return v;
+    if (conv_variant_ok(v, L, bf16, D_in)) return v;
   return -1;
 }
 
+int64_t conv_work_bytes(int v, const ConvLayer &L, int D_in, int n_poses) {
+  return v == kFftVariant ? fft_conv_work_bytes(L, D_in, n_poses) : 0;
+}
+
 hipError_t launch_conv(int variant, const ConvLayer &L, int bf16, const void *in, const void *res,
-                       void *out, int n_poses, int D_in, hipStream_t s) {
-  if (!conv_variant_ok(variant, L, bf16)) return hipErrorInvalidValue;
+                       void *out, int n_poses, int D_in, void *work, hipStream_t s) {
+  if (!conv_variant_ok(variant, L, bf16, D_in)) return hipErrorInvalidValue;
+  if (variant == kFftVariant) return launch_fft_conv(L, in, res, out, n_poses, D_in, work, s);
   const Variant &V = kVariants[variant];
   return bf16 ? V.launch_bf16(L, in, res, out, n_poses, D_in, s) : V.launch_f32(L, in, res, out, n_poses, D_in, s);
 }

@@ -1,0 +1,410 @@
+// Stride-1 conv3d in the frequency domain of the two in-plane axes.
+//
+// The 3D-CNN (Sec. 3.3.1, Table III) applies cross-correlations with k^3 kernels
+// and zero "same" padding.  For a stride-1 layer on a D^3 grid with D + k - 1 <= 32
+// the (y, x) part of the correlation is exact as a product of 32 x 32 DFTs (the
+// zero padding of the DFT covers the conv padding, so no wrap-around reaches an
+// output), which leaves a k-tap correlation along z per (ky, kx) frequency:
+//
+//   Y[ky,kx](z, co) = sum_{dz, ci} X[ky,kx](z + dz - p, ci) G[ky,kx](dz, ci, co)
+//   G[ky,kx](dz, ci, co) = sum_{dy,dx} W(co, ci, dz, dy, dx) e^{+2 pi i ((dy-p) ky + (dx-p) kx) / 32}
+//
+// with X the forward DFT of the input plane z and y = inverse DFT of Y.  Real
+// inputs give Hermitian spectra, so kx runs over 0..16 only (544 columns).  The
+// z-correlation is a complex GEMM per column (rows = (pose, z), K = (dz, ci),
+// N = (re, im) x co) and runs on the bf16 MFMAs; the FFTs are HBM-bound streams.
+// Per layer and pose the work drops from 2 k^3 cin cout D^3 FLOP to
+// 8 k cin cout D 544 + O(D^2 log) -- 12x fewer at k = 7, D = 24.
+//
+// Three kernels per layer:
+//   k_fft_fwd2d  one (pose, z, 8-channel chunk) plane: 2-D real FFT -> spectrum rows
+//   k_fft_zconv  one (column, block of poses): the z-correlation on MFMAs
+//   k_fft_inv2d  one (pose, z, 8-channel chunk) plane: inverse FFT, bias, residual,
+//                ReLU, bf16 store in the activations' channels-last layout
+//
+// Spectrum layout (bf16): [col][pose][z][chunk][re | im][8 channels] -- 64 bytes
+// per 8 channels, so a (column, pose block) of the z-correlation is one
+// contiguous run of rows, and one MFMA K step (16 deep) is 8 channels x (re, im).
+#include "cf_internal.h"
+#include "cf_fft32.h"
+
+namespace cf {
+
+namespace {
+
+constexpr int kN = 32, kNX = kN / 2 + 1, kCols = kN * kNX;  // 544 (ky, kx) columns
+constexpr int kDMax = 30;                                      // D + k - 1 <= 32, k >= 3
+constexpr int kRowsZ = 192;                                    // (pose, z) rows per z-correlation block
+constexpr int kPanelRows = 288;                                // LDS rows of one block incl. z halo
+
+// ---------------------------------------------------------------- forward
+
+// blockIdx = (chunk, z, pose).  in: [P][D][D][D][cin_pad] bf16.
+__global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in, bf16_t *__restrict__ xs, int np,
+                                                   int D, int cin_pad, int nch) {
+  const int chunk = blockIdx.x, z = blockIdx.y, p = blockIdx.z;
+  __shared__ __attribute__((aligned(16))) bf16_t plane[kDMax * kDMax * 8];   // [y][x][8]
+  __shared__ __attribute__((aligned(16))) float2 T[kNX * kDMax * 8];         // [kx][y][8]; later the output
+  const int tid = threadIdx.x;
+  const bf16_t *src = in + (((int64_t)p * D + z) * D * D) * cin_pad + chunk * 8;
+  for (int v = tid; v < D * D; v += 256)
+    *reinterpret_cast<uint4 *>(plane + v * 8) = *reinterpret_cast<const uint4 *>(src + (int64_t)v * cin_pad);
+  __syncthreads();
+  // rows along x, two channels per complex transform
+  if (tid < D * 4) {
+    const int y = tid >> 2, c0 = (tid & 3) * 2;
+    float re[32], im[32];
+#pragma unroll
+    for (int x = 0; x < 32; ++x) {
+      re[x] = x < D ? (float)plane[(y * D + x) * 8 + c0] : 0.0f;
+      im[x] = x < D ? (float)plane[(y * D + x) * 8 + c0 + 1] : 0.0f;
+    }
+    fft32<false>(re, im);
+#pragma unroll
+    for (int k = 0; k < kNX; ++k) {
+      const int m = (32 - k) & 31;
+      T[(k * kDMax + y) * 8 + c0] = make_float2(0.5f * (re[k] + re[m]), 0.5f * (im[k] - im[m]));
+      T[(k * kDMax + y) * 8 + c0 + 1] = make_float2(0.5f * (im[k] + im[m]), -0.5f * (re[k] - re[m]));
+    }
+  }
+  __syncthreads();
+  // columns along y, one channel per transform
+  float re[32], im[32];
+  const bool colw = tid < kNX * 8;
+  const int kx = tid >> 3, c = tid & 7;
+  if (colw) {
+#pragma unroll
+    for (int y = 0; y < 32; ++y) {
+      const float2 v = y < D ? T[(kx * kDMax + y) * 8 + c] : make_float2(0.0f, 0.0f);
+      re[y] = v.x;
+      im[y] = v.y;
+    }
+    fft32<false>(re, im);
+  }
+  __syncthreads();
+  bf16_t *O = reinterpret_cast<bf16_t *>(T);  // [col][re | im][8]
+  if (colw) {
+#pragma unroll
+    for (int ky = 0; ky < 32; ++ky) {
+      O[(ky * kNX + kx) * 16 + c] = (bf16_t)re[ky];
+      O[(ky * kNX + kx) * 16 + 8 + c] = (bf16_t)im[ky];
+    }
+  }
+  __syncthreads();
+  const int64_t rowb = (int64_t)nch * 16;  // bf16 elements per (col, pose, z) row
+  for (int e = tid; e < kCols * 2; e += 256) {
+    const int col = e >> 1, h = e & 1;
+    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * 8) =
+        *reinterpret_cast<const uint4 *>(O + col * 16 + h * 8);
+  }
+}
+
+// ---------------------------------------------------------------- inverse
+
+// blockIdx = (output chunk, z, pose).  out, res: [P][D][D][D][cout_store] bf16.
+__global__ __launch_bounds__(256) void k_fft_inv2d(const bf16_t *__restrict__ ys, const float *__restrict__ bias,
+                                                   const bf16_t *__restrict__ res, bf16_t *__restrict__ out, int np,
+                                                   int D, int nco, int cout_store) {
+  const int chunk = blockIdx.x, z = blockIdx.y, p = blockIdx.z;
+  __shared__ __attribute__((aligned(16))) bf16_t Y[kCols * 16];          // [col][re | im][8]
+  __shared__ __attribute__((aligned(16))) float2 T[kNX * kDMax * 8];     // [kx][y][8]; later [y][x][8] floats
+  const int tid = threadIdx.x;
+  const int64_t rowb = (int64_t)nco * 16;
+  for (int e = tid; e < kCols * 2; e += 256) {
+    const int col = e >> 1, h = e & 1;
+    *reinterpret_cast<uint4 *>(Y + col * 16 + h * 8) =
+        *reinterpret_cast<const uint4 *>(ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * 8);
+  }
+  __syncthreads();
+  // columns along ky
+  if (tid < kNX * 8) {
+    const int kx = tid >> 3, c = tid & 7;
+    float re[32], im[32];
+#pragma unroll
+    for (int ky = 0; ky < 32; ++ky) {
+      re[ky] = (float)Y[(ky * kNX + kx) * 16 + c];
+      im[ky] = (float)Y[(ky * kNX + kx) * 16 + 8 + c];
+    }
+    fft32<true>(re, im);
+#pragma unroll
+    for (int y = 0; y < kDMax; ++y)
+      if (y < D) T[(kx * kDMax + y) * 8 + c] = make_float2(re[y], im[y]);
+  }
+  __syncthreads();
+  // rows along x: the Hermitian halves of two channels in one complex transform
+  float re[32], im[32];
+  const bool roww = tid < D * 4;
+  const int y = tid >> 2, c0 = (tid & 3) * 2;
+  if (roww) {
+#pragma unroll
+    for (int k = 0; k < kNX; ++k) {
+      float2 a = T[(k * kDMax + y) * 8 + c0], b = T[(k * kDMax + y) * 8 + c0 + 1];
+      if (k == 0 || k == kNX - 1) {  // DC and Nyquist of a real signal are real
+        a.y = 0.0f;
+        b.y = 0.0f;
+      }
+      re[k] = a.x - b.y;
+      im[k] = a.y + b.x;
+      if (k > 0 && k < kNX - 1) {
+        re[32 - k] = a.x + b.y;
+        im[32 - k] = b.x - a.y;
+      }
+    }
+    fft32<true>(re, im);
+  }
+  __syncthreads();
+  float *O = reinterpret_cast<float *>(T);  // [y][x][8] conv result + bias
+  if (roww) {
+    constexpr float kScale = 1.0f / (kN * kN);
+    const float b0 = bias[chunk * 8 + c0], b1 = bias[chunk * 8 + c0 + 1];
+#pragma unroll
+    for (int x = 0; x < kDMax; ++x)
+      if (x < D) {
+        O[(y * D + x) * 8 + c0] = re[x] * kScale + b0;
+        O[(y * D + x) * 8 + c0 + 1] = im[x] * kScale + b1;
+      }
+  }
+  __syncthreads();
+  const int64_t base = (((int64_t)p * D + z) * D * D) * cout_store + chunk * 8;
+  for (int v = tid; v < D * D; v += 256) {
+    float f[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) f[q] = O[v * 8 + q];
+    if (res) {
+      const uint4 r = *reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store);
+      const bf16_t *rb = reinterpret_cast<const bf16_t *>(&r);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) f[q] += (float)rb[q];
+    }
+    uint4 o;
+    bf16_t *ob = reinterpret_cast<bf16_t *>(&o);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ob[q] = (bf16_t)(f[q] > 0.0f ? f[q] : 0.0f);
+    *reinterpret_cast<uint4 *>(out + base + (int64_t)v * cout_store) = o;
+  }
+}
+
+// ---------------------------------------------------------------- z-correlation
+
+// One (column, block of ppb poses): rows r = (pose pl, z), pl = r / D; the panel in
+// LDS holds, per pose, its D spectrum rows between KS - 1 zero rows (the z
+// padding), each row nch x 32 bytes + 16 (bank offset between consecutive rows).
+// Real output column n < NT: (re, im) part n / (NT / 2) of channel n % (NT / 2).
+// Waves: NT = 128 -> 2 row groups x 2 column groups, else 2 row groups; each wave
+// 96 rows (3 blocks of 32).
+template <int KS, int NT>
+__global__ __launch_bounds__(NT == 128 ? 256 : 128) __attribute__((amdgpu_waves_per_eu(2))) void k_fft_zconv(
+    const bf16_t *__restrict__ xs, const bf16_t *__restrict__ gp, bf16_t *__restrict__ ys, int np, int D, int nch,
+    int ppb, int gbytes) {
+  constexpr int P = (KS - 1) / 2;
+  constexpr int WN = NT == 128 ? 2 : 1, NW = 2 * WN, NB = NT / WN / 32, MB = 3;
+  constexpr int NBT = NT / 32;
+  __shared__ __attribute__((aligned(16))) char lds[kPanelRows * 272];
+  int pblk, col, zero;
+  xcd_order(pblk, col, zero);
+  (void)zero;
+  const int p0 = pblk * ppb;
+  const int nvalid = min(ppb, np - p0);
+  const int rowb = nch * 32, pitch = rowb + 16;  // bytes
+  const int zrows = D + KS - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wave_m = wave / WN, wave_n = wave % WN;
+  const int khalf = lane >> 5, lrow = lane & 31;
+
+  // panel: rows (pl, zz), zz = z + P
+  {
+    const int q16 = rowb / 16;  // uint4 per row
+    const int total = ppb * zrows * q16;
+    const bf16_t *src = xs + ((int64_t)col * np + p0) * D * (rowb / 2);
+    for (int e = tid; e < total; e += NW * 64) {
+      const int q = e % q16, rr = e / q16, pl = rr / zrows, zz = rr % zrows, zr = zz - P;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (pl < nvalid && zr >= 0 && zr < D)
+        v = *reinterpret_cast<const uint4 *>(src + ((int64_t)pl * D + zr) * (rowb / 2) + q * 8);
+      *reinterpret_cast<uint4 *>(lds + rr * pitch + q * 16) = v;
+    }
+  }
+  int rowoff[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    const int r = wave_m * 96 + mb * 32 + lrow;
+    const int pl = r / D, zl = r % D;
+    rowoff[mb] = (pl < ppb ? (pl * zrows + zl) * pitch : 0) + khalf * 16;
+  }
+  typedef float accv __attribute__((ext_vector_type(16)));
+  accv acc[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
+  __syncthreads();
+
+  // K steps s = chunk * KS + dz; weight fragments [col][chunk][dz][NBT][64 lanes][8],
+  // prefetched kPF steps ahead (past the last step the last one is loaded again)
+  const int steps = nch * KS;
+  const int step_bytes = NBT * 1024;
+  const __amdgpu_buffer_rsrc_t wrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(gp), (short)0, gbytes, 0x00020000);
+  const int wbase = col * steps * step_bytes + (wave_n * NB * 64 + lane) * 16;
+  constexpr int kPF = 4;
+  uint4 bq[kPF][NB];
+#pragma unroll
+  for (int q = 0; q < kPF; ++q)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      bq[q][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                wrs, wbase + nb * 1024, min(q, steps - 1) * step_bytes, 0));
+  for (int s0 = 0; s0 < steps; s0 += kPF) {
+#pragma unroll
+    for (int ph = 0; ph < kPF; ++ph) {
+      const int s = s0 + ph;
+      if (s < steps) {
+        const int chunk = s / KS, dz = s - chunk * KS;
+        uint4 a[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+          a[mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + dz * pitch + chunk * 32);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[mb]),
+                                                                   __builtin_bit_cast(bf16x8, bq[ph][nb]),
+                                                                   acc[mb][nb], 0, 0, 0);
+        const int sn = s + kPF;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                     wrs, wbase + nb * 1024, min(sn, steps - 1) * step_bytes, 0));
+      }
+    }
+  }
+
+  // epilogue through LDS: rows of NT bf16 in the spectrum layout, then contiguous stores
+  __syncthreads();
+  constexpr int HALF = NT / 2;
+  const int orow = HALF * 4;  // bytes per output row (HALF channels x re, im x 2 B)
+  const int opitch = orow + 16;
+  bf16_t *ot = reinterpret_cast<bf16_t *>(lds);
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = wave_m * 96 + mb * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int n = (wave_n * NB + nb) * 32 + lrow;
+        const int part = n / HALF, co = n % HALF;
+        ot[(row * opitch + (co >> 3) * 32 + part * 16) / 2 + (co & 7)] = (bf16_t)acc[mb][nb][r];
+      }
+    }
+  __syncthreads();
+  const int q16 = orow / 16;
+  bf16_t *dst = ys + ((int64_t)col * np + p0) * D * (orow / 2);
+  for (int e = tid; e < nvalid * D * q16; e += NW * 64) {
+    const int q = e % q16, row = e / q16;
+    *reinterpret_cast<uint4 *>(dst + (int64_t)row * (orow / 2) + q * 8) =
+        *reinterpret_cast<const uint4 *>(lds + row * opitch + q * 16);
+  }
+}
+
+// ---------------------------------------------------------------- weights
+
+// One thread per (col, chunk, dz, 32-column block, lane): the 8 bf16 of one MFMA
+// B fragment.  w: folded fp32 weights [cout][cin][k][k][k].
+__global__ void k_fft_gspec(const float *__restrict__ w, bf16_t *__restrict__ gp, int cin, int cout, int nch, int KS,
+                            int nbt) {
+  const int64_t total = (int64_t)kCols * nch * KS * nbt * 64;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int lane = (int)(t % 64), nbk = (int)((t / 64) % nbt);
+  const int dz = (int)((t / (64 * nbt)) % KS), chunk = (int)((t / (64 * nbt * KS)) % nch);
+  const int col = (int)(t / ((int64_t)64 * nbt * KS * nch));
+  const int ky = col / kNX, kx = col % kNX, P = (KS - 1) / 2;
+  const int n = nbk * 32 + (lane & 31), half = nbt * 16;
+  const int part = n / half, co = n % half;
+  bf16_t v[8];
+  for (int j = 0; j < 8; ++j) {
+    const int k = 8 * (lane >> 5) + j, ci = chunk * 8 + (k & 7), xim = k >> 3;
+    float gr = 0.0f, gi = 0.0f;
+    if (ci < cin && co < cout) {
+      const float *wk = w + (((int64_t)co * cin + ci) * KS + dz) * KS * KS;
+      for (int dy = 0; dy < KS; ++dy)
+        for (int dx = 0; dx < KS; ++dx) {
+          const int ph = (((dy - P) * ky + (dx - P) * kx) % 32 + 32) % 32;
+          const float c = ph < 16 ? kFftCos32[ph] : -kFftCos32[ph - 16];
+          const float s = ph < 16 ? kFftSin32[ph] : -kFftSin32[ph - 16];
+          gr += wk[dy * KS + dx] * c;
+          gi += wk[dy * KS + dx] * s;
+        }
+    }
+    // Y = X G:  Yr = Xr Gr - Xi Gi,  Yi = Xr Gi + Xi Gr
+    const float b = part == 0 ? (xim == 0 ? gr : -gi) : (xim == 0 ? gi : gr);
+    v[j] = (bf16_t)b;
+  }
+  uint4 o;
+  __builtin_memcpy(&o, v, 16);
+  *reinterpret_cast<uint4 *>(gp + t * 8) = o;
+}
+
+int nch_of(const ConvLayer &L) { return (L.cin + 7) / 8; }
+int nbt_of(const ConvLayer &L) { return L.cout * 2 / 32; }
+
+}  // namespace
+
+bool fft_conv_layer_ok(const ConvLayer &L) {
+  return L.stride == 1 && (L.k == 3 || L.k == 5 || L.k == 7) && L.cin <= 64 && L.cin_pad % 8 == 0 &&
+         (L.cout == 16 || L.cout == 32 || L.cout == 64) && L.cout_store % 8 == 0;
+}
+
+bool fft_conv_ok(const ConvLayer &L, int D) {
+  if (!L.gspec || !fft_conv_layer_ok(L) || D < 1 || D + L.k - 1 > kN || D > kDMax) return false;
+  const int ppb = kRowsZ / D;
+  return ppb >= 1 && ppb * (D + L.k - 1) <= kPanelRows;
+}
+
+int64_t fft_conv_gspec_bytes(const ConvLayer &L) { return (int64_t)kCols * nch_of(L) * L.k * nbt_of(L) * 1024; }
+
+int64_t fft_conv_work_bytes(const ConvLayer &L, int D, int np) {
+  return (int64_t)kCols * np * D * (nch_of(L) + L.cout / 8) * 32;
+}
+
+hipError_t fft_conv_prepare(ConvLayer &L, const float *w_folded_dev, hipStream_t s) {
+  const int64_t total = (int64_t)kCols * nch_of(L) * L.k * nbt_of(L) * 64;
+  hipLaunchKernelGGL(k_fft_gspec, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w_folded_dev,
+                     reinterpret_cast<bf16_t *>(L.gspec), L.cin, L.cout, nch_of(L), L.k, nbt_of(L));
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, void *out, int np, int D, void *work,
+                           hipStream_t s) {
+  if (!fft_conv_ok(L, D) || !work) return hipErrorInvalidValue;
+  const int nch = nch_of(L), nco = L.cout / 8;
+  bf16_t *xs = reinterpret_cast<bf16_t *>(work);
+  bf16_t *ys = xs + (int64_t)kCols * np * D * nch * 16;
+  hipLaunchKernelGGL(k_fft_fwd2d, dim3(nch, D, np), dim3(256), 0, s, reinterpret_cast<const bf16_t *>(in), xs, np, D,
+                     L.cin_pad, nch);
+  const int ppb = kRowsZ / D;
+  const dim3 zg((np + ppb - 1) / ppb, kCols, 1);
+  const bf16_t *gp = reinterpret_cast<const bf16_t *>(L.gspec);
+  const int gb = (int)L.gspec_bytes;
+#define CF_ZCONV(KS, NT) \
+  hipLaunchKernelGGL((k_fft_zconv<KS, NT>), zg, dim3(NT == 128 ? 256 : 128), 0, s, xs, gp, ys, np, D, nch, ppb, gb)
+  const int nt = L.cout * 2;
+  if (L.k == 7) {
+    if (nt == 128) CF_ZCONV(7, 128); else if (nt == 64) CF_ZCONV(7, 64); else CF_ZCONV(7, 32);
+  } else if (L.k == 5) {
+    if (nt == 128) CF_ZCONV(5, 128); else if (nt == 64) CF_ZCONV(5, 64); else CF_ZCONV(5, 32);
+  } else {
+    if (nt == 128) CF_ZCONV(3, 128); else if (nt == 64) CF_ZCONV(3, 64); else CF_ZCONV(3, 32);
+  }
+#undef CF_ZCONV
+  hipLaunchKernelGGL(k_fft_inv2d, dim3(nco, D, np), dim3(256), 0, s, ys, L.bias,
+                     reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), np, D, nco,
+                     L.cout_store);
+  return hipGetLastError();
+}
+
+}  // namespace cf

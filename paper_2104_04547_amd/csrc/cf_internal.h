@@ -73,6 +73,8 @@ struct ConvLayer {
   void *wpk8;      // bf16 only: weights packed for the tap-pair kernel
   int64_t wbytes8;
   float *bias;     // folded bias [cout_pad32]
+  void *gspec;     // bf16 stride-1 layers: in-plane spectra of the weights (frequency-domain path)
+  int64_t gspec_bytes;
 };
 
 // Kernel launchers (defined in the .hip files).
@@ -92,10 +94,21 @@ hipError_t launch_graph(const int32_t *atom_off, int n_atoms, const int32_t *xyz
 
 int conv_num_variants();
 const char *conv_variant_name(int v);
-bool conv_variant_ok(int v, const ConvLayer &L, int bf16);
+bool conv_variant_ok(int v, const ConvLayer &L, int bf16, int D_in);
 int conv_default_variant(const ConvLayer &L, int D_in, int bf16);
+// device scratch a variant needs for n_poses (0 for the direct kernels)
+int64_t conv_work_bytes(int v, const ConvLayer &L, int D_in, int n_poses);
 hipError_t launch_conv(int variant, const ConvLayer &L, int bf16, const void *in, const void *res,
-                       void *out, int n_poses, int D_in, hipStream_t s);
+                       void *out, int n_poses, int D_in, void *work, hipStream_t s);
+
+// frequency-domain stride-1 conv (cf_fftconv.hip)
+bool fft_conv_layer_ok(const ConvLayer &L);     // layer shape supported (spectra prepared at create)
+bool fft_conv_ok(const ConvLayer &L, int D);    // ... and at input size D
+int64_t fft_conv_gspec_bytes(const ConvLayer &L);
+int64_t fft_conv_work_bytes(const ConvLayer &L, int D, int n_poses);
+hipError_t fft_conv_prepare(ConvLayer &L, const float *w_folded_dev, hipStream_t s);
+hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, void *out, int n_poses, int D,
+                           void *work, hipStream_t s);
 
 hipError_t launch_pool_dense(const void *act, int bf16, int n_poses, int vox, int cstride, int c,
                              const float *dense_w, const float *dense_b, int n_dense, const float *dense2_w,
