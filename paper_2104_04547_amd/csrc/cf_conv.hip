@@ -667,8 +667,10 @@ bool conv_variant_ok(int v, const ConvLayer &L, int bf16, int D_in) {
 }
 
 int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
-  // measured on MI355X at 48^3 (bf16: tap pairs for stride 1 and the 128-column
-  // stride-2 layer, two poses per workgroup there; fp32 has no tap-pair kernel)
+  // measured on MI355X at 48^3: bf16 7^3 stride-1 layers in the frequency domain
+  // (2x the tap-pair kernel), else tap pairs for stride 1 and the 128-column
+  // stride-2 layer, two poses per workgroup there; fp32 has no tap-pair kernel
+  if (bf16 && L.k == 7 && conv_variant_ok(kFftVariant, L, bf16, D_in)) return kFftVariant;
   const int pref[] = {12, 40, 17, 20, 19, 23, 26, 28, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 21,
                       22, 24, 25, 27, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39};
   for (int v : pref)

@@ -39,32 +39,54 @@ constexpr int kPanelRows = 288;                                // LDS rows of on
 
 // ---------------------------------------------------------------- forward
 
-// blockIdx = (chunk, z, pose).  in: [P][D][D][D][cin_pad] bf16.
+// LDS layouts are padded so that the lanes of one access hit distinct banks:
+// the input plane is held transposed, [x][y (pitch D + 1)][8 channels], so the
+// lanes (y, channel pair) of one x read one contiguous run; the half spectrum of
+// the rows is [kx][y (pitch D + 1)][8] complex.
+// One workgroup per (z, pose, chunk), grid (D, np, nch) in XCD order: the chunks
+// of one plane run under one L2, where their 32-byte pieces of each spectrum row
+// (and of each input voxel) meet.  in: [P][D][D][D][cin_pad] bf16.
 __global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in, bf16_t *__restrict__ xs, int np,
                                                    int D, int cin_pad, int nch) {
-  const int chunk = blockIdx.x, z = blockIdx.y, p = blockIdx.z;
-  __shared__ __attribute__((aligned(16))) bf16_t plane[kDMax * kDMax * 8];   // [y][x][8]
-  __shared__ __attribute__((aligned(16))) float2 T[kNX * kDMax * 8];         // [kx][y][8]; later the output
-  const int tid = threadIdx.x;
+  int chunk, z, p;
+  xcd_order(z, p, chunk);
+  // one dynamic LDS block (fft_lds_bytes): the plane, then (after its rows are in
+  // registers) the row spectra, then the output staging
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  bf16_t *plane = reinterpret_cast<bf16_t *>(dyn_lds);  // [x][y][8]
+  float2 *T = reinterpret_cast<float2 *>(dyn_lds);      // [kx][y][8]
+  const int tid = threadIdx.x, DP = D + 1;
   const bf16_t *src = in + (((int64_t)p * D + z) * D * D) * cin_pad + chunk * 8;
-  for (int v = tid; v < D * D; v += 256)
-    *reinterpret_cast<uint4 *>(plane + v * 8) = *reinterpret_cast<const uint4 *>(src + (int64_t)v * cin_pad);
+  for (int v = tid; v < D * D; v += 256) {
+    const int y = v / D, x = v - y * D;
+    *reinterpret_cast<uint4 *>(plane + (x * DP + y) * 8) = *reinterpret_cast<const uint4 *>(src + (int64_t)v * cin_pad);
+  }
   __syncthreads();
   // rows along x, two channels per complex transform
-  if (tid < D * 4) {
+  {
+    const bool roww = tid < D * 4;
     const int y = tid >> 2, c0 = (tid & 3) * 2;
     float re[32], im[32];
 #pragma unroll
     for (int x = 0; x < 32; ++x) {
-      re[x] = x < D ? (float)plane[(y * D + x) * 8 + c0] : 0.0f;
-      im[x] = x < D ? (float)plane[(y * D + x) * 8 + c0 + 1] : 0.0f;
+      if (roww && x < D) {
+        const uint32_t two = *reinterpret_cast<const uint32_t *>(plane + (x * DP + y) * 8 + c0);
+        re[x] = __uint_as_float(two << 16);
+        im[x] = __uint_as_float(two & 0xffff0000u);
+      } else {
+        re[x] = 0.0f;
+        im[x] = 0.0f;
+      }
     }
-    fft32<false>(re, im);
+    __syncthreads();  // the plane is in registers; its LDS becomes the row spectra
+    if (roww) {
+      fft32<false>(re, im);
 #pragma unroll
-    for (int k = 0; k < kNX; ++k) {
-      const int m = (32 - k) & 31;
-      T[(k * kDMax + y) * 8 + c0] = make_float2(0.5f * (re[k] + re[m]), 0.5f * (im[k] - im[m]));
-      T[(k * kDMax + y) * 8 + c0 + 1] = make_float2(0.5f * (im[k] + im[m]), -0.5f * (re[k] - re[m]));
+      for (int k = 0; k < kNX; ++k) {
+        const int m = (32 - k) & 31;
+        *reinterpret_cast<float4 *>(T + (k * DP + y) * 8 + c0) = make_float4(
+            0.5f * (re[k] + re[m]), 0.5f * (im[k] - im[m]), 0.5f * (im[k] + im[m]), -0.5f * (re[k] - re[m]));
+      }
     }
   }
   __syncthreads();
@@ -75,19 +97,26 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in
   if (colw) {
 #pragma unroll
     for (int y = 0; y < 32; ++y) {
-      const float2 v = y < D ? T[(kx * kDMax + y) * 8 + c] : make_float2(0.0f, 0.0f);
+      const float2 v = y < D ? T[(kx * DP + y) * 8 + c] : make_float2(0.0f, 0.0f);
       re[y] = v.x;
       im[y] = v.y;
     }
     fft32<false>(re, im);
   }
   __syncthreads();
-  bf16_t *O = reinterpret_cast<bf16_t *>(T);  // [col][re | im][8]
+  // [col][re | im][8]: lane pairs (c, c ^ 1) swap halves so that each lane
+  // stores two channels at once (even lanes the re pair, odd lanes the im pair)
+  uint32_t *O = reinterpret_cast<uint32_t *>(T);
   if (colw) {
+    const bool odd = c & 1;
 #pragma unroll
     for (int ky = 0; ky < 32; ++ky) {
-      O[(ky * kNX + kx) * 16 + c] = (bf16_t)re[ky];
-      O[(ky * kNX + kx) * 16 + 8 + c] = (bf16_t)im[ky];
+      const float mine = odd ? re[ky] : im[ky];       // what the partner needs
+      const float other = __shfl_xor(mine, 1);
+      const float lo = odd ? other : re[ky], hi = odd ? im[ky] : other;  // channels c & ~1, c | 1
+      const uint32_t packed = (uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)lo) |
+                              ((uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)hi) << 16);
+      O[(ky * kNX + kx) * 8 + (odd ? 4 : 0) + (c >> 1)] = packed;
     }
   }
   __syncthreads();
@@ -95,20 +124,25 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in
   for (int e = tid; e < kCols * 2; e += 256) {
     const int col = e >> 1, h = e & 1;
     *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * 8) =
-        *reinterpret_cast<const uint4 *>(O + col * 16 + h * 8);
+        *reinterpret_cast<const uint4 *>(O + col * 8 + h * 4);
   }
 }
 
 // ---------------------------------------------------------------- inverse
 
-// blockIdx = (output chunk, z, pose).  out, res: [P][D][D][D][cout_store] bf16.
-__global__ __launch_bounds__(256) void k_fft_inv2d(const bf16_t *__restrict__ ys, const float *__restrict__ bias,
+// One workgroup per (z, pose, output chunk), grid (D, np, nco) in XCD order.
+// out, res: [P][D][D][D][cout_store] bf16.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_inv2d(const bf16_t *__restrict__ ys, const float *__restrict__ bias,
                                                    const bf16_t *__restrict__ res, bf16_t *__restrict__ out, int np,
                                                    int D, int nco, int cout_store) {
-  const int chunk = blockIdx.x, z = blockIdx.y, p = blockIdx.z;
-  __shared__ __attribute__((aligned(16))) bf16_t Y[kCols * 16];          // [col][re | im][8]
-  __shared__ __attribute__((aligned(16))) float2 T[kNX * kDMax * 8];     // [kx][y][8]; later [y][x][8] floats
-  const int tid = threadIdx.x;
+  int chunk, z, p;
+  xcd_order(z, p, chunk);
+  // one dynamic LDS block (fft_lds_bytes): the spectrum, then (after its columns
+  // are in registers) the column transforms, then the output plane
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  bf16_t *Y = reinterpret_cast<bf16_t *>(dyn_lds);  // [col][re | im][8]
+  float2 *T = reinterpret_cast<float2 *>(dyn_lds);  // [kx][y][8]; later [x][y][8] floats
+  const int tid = threadIdx.x, DP = D + 1;
   const int64_t rowb = (int64_t)nco * 16;
   for (int e = tid; e < kCols * 2; e += 256) {
     const int col = e >> 1, h = e & 1;
@@ -116,19 +150,31 @@ __global__ __launch_bounds__(256) void k_fft_inv2d(const bf16_t *__restrict__ ys
         *reinterpret_cast<const uint4 *>(ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * 8);
   }
   __syncthreads();
-  // columns along ky
-  if (tid < kNX * 8) {
+  // columns along ky; lane pairs (c, c ^ 1) load two channels at once (even lanes
+  // the re pair, odd lanes the im pair) and swap halves
+  {
+    const bool colw = tid < kNX * 8;
     const int kx = tid >> 3, c = tid & 7;
+    const bool odd = c & 1;
+    const uint32_t *Yw = reinterpret_cast<const uint32_t *>(Y);
     float re[32], im[32];
+    if (colw) {
 #pragma unroll
-    for (int ky = 0; ky < 32; ++ky) {
-      re[ky] = (float)Y[(ky * kNX + kx) * 16 + c];
-      im[ky] = (float)Y[(ky * kNX + kx) * 16 + 8 + c];
+      for (int ky = 0; ky < 32; ++ky) {
+        const uint32_t two = Yw[(ky * kNX + kx) * 8 + (odd ? 4 : 0) + (c >> 1)];
+        const float lo = __uint_as_float(two << 16), hi = __uint_as_float(two & 0xffff0000u);
+        const float other = __shfl_xor(odd ? lo : hi, 1);  // even lanes send the odd channel's re, ...
+        re[ky] = odd ? other : lo;
+        im[ky] = odd ? hi : other;
+      }
     }
-    fft32<true>(re, im);
+    __syncthreads();  // the spectrum is in registers; its LDS becomes the transforms
+    if (colw) {
+      fft32<true>(re, im);
 #pragma unroll
-    for (int y = 0; y < kDMax; ++y)
-      if (y < D) T[(kx * kDMax + y) * 8 + c] = make_float2(re[y], im[y]);
+      for (int y = 0; y < kDMax; ++y)
+        if (y < D) T[(kx * DP + y) * 8 + c] = make_float2(re[y], im[y]);
+    }
   }
   __syncthreads();
   // rows along x: the Hermitian halves of two channels in one complex transform
@@ -138,7 +184,8 @@ __global__ __launch_bounds__(256) void k_fft_inv2d(const bf16_t *__restrict__ ys
   if (roww) {
 #pragma unroll
     for (int k = 0; k < kNX; ++k) {
-      float2 a = T[(k * kDMax + y) * 8 + c0], b = T[(k * kDMax + y) * 8 + c0 + 1];
+      const float4 ab = *reinterpret_cast<const float4 *>(T + (k * DP + y) * 8 + c0);
+      float2 a = make_float2(ab.x, ab.y), b = make_float2(ab.z, ab.w);
       if (k == 0 || k == kNX - 1) {  // DC and Nyquist of a real signal are real
         a.y = 0.0f;
         b.y = 0.0f;
@@ -153,23 +200,23 @@ __global__ __launch_bounds__(256) void k_fft_inv2d(const bf16_t *__restrict__ ys
     fft32<true>(re, im);
   }
   __syncthreads();
-  float *O = reinterpret_cast<float *>(T);  // [y][x][8] conv result + bias
+  float *O = reinterpret_cast<float *>(T);  // [x][y (pitch D + 1)][8] conv result + bias
   if (roww) {
     constexpr float kScale = 1.0f / (kN * kN);
     const float b0 = bias[chunk * 8 + c0], b1 = bias[chunk * 8 + c0 + 1];
 #pragma unroll
     for (int x = 0; x < kDMax; ++x)
-      if (x < D) {
-        O[(y * D + x) * 8 + c0] = re[x] * kScale + b0;
-        O[(y * D + x) * 8 + c0 + 1] = im[x] * kScale + b1;
-      }
+      if (x < D)
+        *reinterpret_cast<float2 *>(O + (x * DP + y) * 8 + c0) = make_float2(re[x] * kScale + b0, im[x] * kScale + b1);
   }
   __syncthreads();
   const int64_t base = (((int64_t)p * D + z) * D * D) * cout_store + chunk * 8;
   for (int v = tid; v < D * D; v += 256) {
+    const int yy = v / D, xx = v - yy * D;
     float f[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) f[q] = O[v * 8 + q];
+    const float4 f0 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8);
+    const float4 f1 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8 + 4);
+    f[0] = f0.x; f[1] = f0.y; f[2] = f0.z; f[3] = f0.w; f[4] = f1.x; f[5] = f1.y; f[6] = f1.z; f[7] = f1.w;
     if (res) {
       const uint4 r = *reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store);
       const bf16_t *rb = reinterpret_cast<const bf16_t *>(&r);
@@ -211,25 +258,41 @@ __global__ __launch_bounds__(NT == 128 ? 256 : 128) __attribute__((amdgpu_waves_
   const int wave_m = wave / WN, wave_n = wave % WN;
   const int khalf = lane >> 5, lrow = lane & 31;
 
-  // panel: rows (pl, zz), zz = z + P
+  // panel: LDS rows rr = (pl, zz), zz = z + P; the loads of a batch are all in
+  // flight before any is stored
   {
+    constexpr int NTH = NW * 64, kIt = (kPanelRows * 16 + NTH - 1) / NTH, kBatch = 18;
     const int q16 = rowb / 16;  // uint4 per row
     const int total = ppb * zrows * q16;
     const bf16_t *src = xs + ((int64_t)col * np + p0) * D * (rowb / 2);
-    for (int e = tid; e < total; e += NW * 64) {
-      const int q = e % q16, rr = e / q16, pl = rr / zrows, zz = rr % zrows, zr = zz - P;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (pl < nvalid && zr >= 0 && zr < D)
-        v = *reinterpret_cast<const uint4 *>(src + ((int64_t)pl * D + zr) * (rowb / 2) + q * 8);
-      *reinterpret_cast<uint4 *>(lds + rr * pitch + q * 16) = v;
+#pragma unroll
+    for (int i0 = 0; i0 < kIt; i0 += kBatch) {
+      uint4 pv[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int e = (i0 + i) * NTH + tid;
+        pv[i] = make_uint4(0, 0, 0, 0);
+        if (i0 + i < kIt && e < total) {
+          const int q = e % q16, rr = e / q16, pl = rr / zrows, zr = rr % zrows - P;
+          if (pl < nvalid && zr >= 0 && zr < D)
+            pv[i] = *reinterpret_cast<const uint4 *>(src + ((int64_t)pl * D + zr) * (rowb / 2) + q * 8);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int e = (i0 + i) * NTH + tid;
+        if (i0 + i < kIt && e < total) *reinterpret_cast<uint4 *>(lds + (e / q16) * pitch + (e % q16) * 16) = pv[i];
+      }
     }
   }
+  // tile rows r = (z, pl), pose fastest: the 16 rows of a lane group then fall on
+  // 16 different bank quads of the 272-byte-pitch panel at D = 24
   int rowoff[MB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
     const int r = wave_m * 96 + mb * 32 + lrow;
-    const int pl = r / D, zl = r % D;
-    rowoff[mb] = (pl < ppb ? (pl * zrows + zl) * pitch : 0) + khalf * 16;
+    const int pl = r % ppb, zl = r / ppb;
+    rowoff[mb] = (zl < D ? (pl * zrows + zl) * pitch : 0) + khalf * 16;
   }
   typedef float accv __attribute__((ext_vector_type(16)));
   accv acc[MB][NB];
@@ -248,6 +311,16 @@ __global__ __launch_bounds__(NT == 128 ? 256 : 128) __attribute__((amdgpu_waves_
   const __amdgpu_buffer_rsrc_t wrs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(gp), (short)0, gbytes, 0x00020000);
   const int wbase = col * steps * step_bytes + (wave_n * NB * 64 + lane) * 16;
+  if (col + 1 < (int)gridDim.y) {
+    // warm L2 with a slice of the next column's weights: the workgroups of one
+    // column run together on one XCD, the next column's follow them there
+    const int colb = steps * step_bytes, slice = (colb + gridDim.x - 1) / gridDim.x;
+    const int off = (col + 1) * colb + pblk * slice + tid * 128;
+    if (tid * 128 < slice && off + 4 <= gbytes) {
+      const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(wrs, off, 0, 0);
+      if (v == 0x7fc00001u && np < 0) ys[0] = (bf16_t)0.0f;  // keeps the load; never true
+    }
+  }
   constexpr int kPF = 4;
   uint4 bq[kPF][NB];
 #pragma unroll
@@ -256,21 +329,31 @@ __global__ __launch_bounds__(NT == 128 ? 256 : 128) __attribute__((amdgpu_waves_
     for (int nb = 0; nb < NB; ++nb)
       bq[q][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
                                                 wrs, wbase + nb * 1024, min(q, steps - 1) * step_bytes, 0));
+  // the row fragments of step s + 1 are read while the MFMAs of step s issue
+  uint4 a[2][MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) a[0][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb]);
+  int nchunk = 0, ndz = 1;  // step s + 1
   for (int s0 = 0; s0 < steps; s0 += kPF) {
 #pragma unroll
     for (int ph = 0; ph < kPF; ++ph) {
       const int s = s0 + ph;
       if (s < steps) {
-        const int chunk = s / KS, dz = s - chunk * KS;
-        uint4 a[MB];
+        if (ndz == KS) {
+          ndz = 0;
+          ++nchunk;
+        }
+        const int noff = s + 1 < steps ? ndz * pitch + nchunk * 32 : 0;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
-          a[mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + dz * pitch + chunk * 32);
+          a[(ph + 1) & 1][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + noff);
+        ++ndz;
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[mb]),
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[ph & 1][mb]),
                                                                    __builtin_bit_cast(bf16x8, bq[ph][nb]),
                                                                    acc[mb][nb], 0, 0, 0);
         const int sn = s + kPF;
@@ -285,8 +368,8 @@ __global__ __launch_bounds__(NT == 128 ? 256 : 128) __attribute__((amdgpu_waves_
   // epilogue through LDS: rows of NT bf16 in the spectrum layout, then contiguous stores
   __syncthreads();
   constexpr int HALF = NT / 2;
-  const int orow = HALF * 4;  // bytes per output row (HALF channels x re, im x 2 B)
-  const int opitch = orow + 16;
+  constexpr int orow = HALF * 4;  // bytes per output row (HALF channels x re, im x 2 B)
+  constexpr int opitch = orow + 16;
   bf16_t *ot = reinterpret_cast<bf16_t *>(lds);
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
@@ -301,12 +384,13 @@ __global__ __launch_bounds__(NT == 128 ? 256 : 128) __attribute__((amdgpu_waves_
       }
     }
   __syncthreads();
-  const int q16 = orow / 16;
+  constexpr int q16 = orow / 16;
   bf16_t *dst = ys + ((int64_t)col * np + p0) * D * (orow / 2);
-  for (int e = tid; e < nvalid * D * q16; e += NW * 64) {
-    const int q = e % q16, row = e / q16;
-    *reinterpret_cast<uint4 *>(dst + (int64_t)row * (orow / 2) + q * 8) =
-        *reinterpret_cast<const uint4 *>(lds + row * opitch + q * 16);
+  for (int e = tid; e < ppb * D * q16; e += NW * 64) {
+    const int q = e % q16, row = e / q16, pl = row % ppb, zl = row / ppb;
+    if (pl < nvalid)
+      *reinterpret_cast<uint4 *>(dst + ((int64_t)pl * D + zl) * (orow / 2) + q * 8) =
+          *reinterpret_cast<const uint4 *>(lds + row * opitch + q * 16);
   }
 }
 
@@ -350,6 +434,14 @@ __global__ void k_fft_gspec(const float *__restrict__ w, bf16_t *__restrict__ gp
 }
 
 int nch_of(const ConvLayer &L) { return (L.cin + 7) / 8; }
+
+// dynamic LDS of the plane transforms: the larger of the row spectra [17][D + 1][8]
+// complex and the bf16 spectrum of a plane (the input plane and output staging fit
+// in either)
+size_t fft_lds_bytes(int D) {
+  const size_t t = (size_t)kNX * (D + 1) * 8 * sizeof(float2), y = (size_t)kCols * 16 * sizeof(bf16_t);
+  return t > y ? t : y;
+}
 int nbt_of(const ConvLayer &L) { return L.cout * 2 / 32; }
 
 }  // namespace
@@ -384,7 +476,7 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
   const int nch = nch_of(L), nco = L.cout / 8;
   bf16_t *xs = reinterpret_cast<bf16_t *>(work);
   bf16_t *ys = xs + (int64_t)kCols * np * D * nch * 16;
-  hipLaunchKernelGGL(k_fft_fwd2d, dim3(nch, D, np), dim3(256), 0, s, reinterpret_cast<const bf16_t *>(in), xs, np, D,
+  hipLaunchKernelGGL(k_fft_fwd2d, dim3(D, np, nch), dim3(256), fft_lds_bytes(D), s, reinterpret_cast<const bf16_t *>(in), xs, np, D,
                      L.cin_pad, nch);
   const int ppb = kRowsZ / D;
   const dim3 zg((np + ppb - 1) / ppb, kCols, 1);
@@ -401,7 +493,7 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
     if (nt == 128) CF_ZCONV(3, 128); else if (nt == 64) CF_ZCONV(3, 64); else CF_ZCONV(3, 32);
   }
 #undef CF_ZCONV
-  hipLaunchKernelGGL(k_fft_inv2d, dim3(nco, D, np), dim3(256), 0, s, ys, L.bias,
+  hipLaunchKernelGGL(k_fft_inv2d, dim3(D, np, nco), dim3(256), fft_lds_bytes(D), s, ys, L.bias,
                      reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), np, D, nco,
                      L.cout_store);
   return hipGetLastError();

@@ -42,7 +42,7 @@ def demangle(names: List[str]) -> Dict[str, str]:
     return out
 
 
-_CONV8 = re.compile(r"k_conv8<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+)(?:, (\d+))?>")
+_CONV8 = re.compile(r"k_conv8<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+)(?:, (\d+))?(?:, (\d+))?>")
 _CONV = re.compile(r"k_conv<([^,]+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+)>")
 _PLAIN = re.compile(r"(?:cf::\(anonymous namespace\)::)?(k_\w+)")
 
@@ -55,6 +55,11 @@ def _split(wn: int) -> str:
     return f"c{wn}" if wn > 1 else ""
 
 
+def _poses(pp: int) -> str:
+    """Poses per workgroup of the tap-pair conv as in the library's variant names."""
+    return f"_p{pp}" if pp > 1 else ""
+
+
 def short_name(name: str) -> str:
     """Conv kernels as 'conv.<variant>' (the library's timing keys; 'conv.f32.' for
     the float32 instances), other library kernels by function name."""
@@ -62,15 +67,16 @@ def short_name(name: str) -> str:
     if m:   # names c++filt leaves mangled (bfloat16 template arguments)
         p8, t, ints = m.groups()
         v = [int(x) for x in re.findall(r"Li(\d+)E", ints)]
-        if len(v) in (7, 8):
+        if len(v) in (7, 8, 9):
             ks, s, tz, ty, tx, nw, nt = v[:7]
-            wn = v[7] if len(v) == 8 else 1
+            wn = v[7] if len(v) >= 8 else 1
+            pp = v[8] if len(v) == 9 else 1
             pre = "conv.p8" if p8 else ("conv.f32." if t == "f" else "conv.")
-            return f"{pre}k{ks}s{s}_t{tz}x{ty}x{tx}_w{nw}{_split(wn)}_n{nt}"
+            return f"{pre}k{ks}s{s}_t{tz}x{ty}x{tx}_w{nw}{_split(wn)}_n{nt}{_poses(pp)}"
     m = _CONV8.search(name)
     if m:
-        ks, s, tz, ty, tx, nw, nt, wn = m.groups()
-        return f"conv.p8k{ks}s{s}_t{tz}x{ty}x{tx}_w{nw}{_split(int(wn or 1))}_n{nt}"
+        ks, s, tz, ty, tx, nw, nt, wn, pp = m.groups()
+        return f"conv.p8k{ks}s{s}_t{tz}x{ty}x{tx}_w{nw}{_split(int(wn or 1))}_n{nt}{_poses(int(pp or 1))}"
     m = _CONV.search(name)
     if m:
         t, ks, s, tz, ty, tx, nw, nt = m.groups()
