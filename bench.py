@@ -98,18 +98,20 @@ def cnn_latent_error(scorer, batch, gd, G, n):
     return float(np.abs(lat - want).max() / np.abs(want).max())
 
 
-def conv_traffic(kernel):
-    """HBM bytes per launch of the dominant conv kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by a plain copy's
-    reading), or None when there is none for this kernel or the conv source has
-    changed since the counters were taken."""
+def kernel_traffic(kernel):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (profiles/traffic.json: FETCH_SIZE + WRITE_SIZE per dispatch, scaled by a plain
+    copy's reading), or None when there is none for this kernel or its source file
+    has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "conv_traffic.json")
+    path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    t = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2104_04547_amd", "csrc", "cf_conv.hip")
-    if t.get("kernel") != kernel or t.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    t = json.load(open(path)).get(kernel)
+    if not t:
+        return None
+    src = os.path.join(ROOT, "paper_2104_04547_amd", "csrc", t["source"])
+    if not os.path.exists(src) or t.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
     return round(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"], 0)
 
@@ -349,15 +351,22 @@ def main():
             log(f"{prec}: error vs oracle {res[prec]['error']}, cnn latent rel {res[prec]['cnn_latent_max_rel_error']:.2e}")
         s.close()
 
-    # dominant kernel of the precision form: the conv kernel (one template instance,
-    # possibly several layers) with the most device time, as a profiler groups it
+    # dominant kernel of the precision form: the kernel (one template instance,
+    # possibly several layers) with the most device time, as a profiler groups it;
+    # its bound follows from its algorithmic FLOP per byte against the ridge point
     st = by_kernel(res["bf16"]["stats"])
     total_ms = sum(v["total_ms"] for v in st.values())
-    dom = max((k for k in st if k.startswith("conv")), key=lambda k: st[k]["total_ms"])
+    dom = max(st, key=lambda k: st[k]["total_ms"])
     d = st[dom]
     avg_ms = d["total_ms"] / d["launches"]
     flop_per_launch = d["flop"] / d["launches"]
-    achieved = flop_per_launch / (avg_ms * 1e-3) / 1e12
+    bytes_per_launch = d["bytes"] / d["launches"]
+    mfma_bound = flop_per_launch > 0 and (bytes_per_launch == 0 or flop_per_launch / bytes_per_launch >
+                                          PEAK_BF16_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9))
+    if mfma_bound:
+        achieved, peak, unit = flop_per_launch / (avg_ms * 1e-3) / 1e12, PEAK_BF16_TFLOPS, "TFLOP/s"
+    else:
+        achieved, peak, unit = bytes_per_launch / (avg_ms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"
     conv_ms = sum(v["total_ms"] for k, v in st.items() if k.startswith("conv"))
     conv_flop = sum(v["flop"] for k, v in st.items() if k.startswith("conv"))
     breakdown = {k: dict(launches=v["launches"], ms_per_step=v["total_ms"] / a.steps,
@@ -406,9 +415,10 @@ def main():
             "conv_variants_bf16": variants.get("bf16"), "conv_variants_fp32": variants.get("fp32"),
         },
         "roofline": {
-            "bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": conv_traffic(dom),
+            "bound": "mfma" if mfma_bound else "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": peak,
+            "unit": unit, "frac": round(achieved / peak, 4), "traffic": kernel_traffic(dom),
             "avg_launch_ms": round(avg_ms, 4), "flop_per_launch": flop_per_launch,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
             "conv_stack_tflops": round(conv_flop / (conv_ms * 1e-3) / 1e12, 2),
             "conv_share_of_step": round(conv_ms / total_ms, 4),
         },

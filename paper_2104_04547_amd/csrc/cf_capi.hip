@@ -288,6 +288,20 @@ int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s) {
     const auto &L = c->conv[i];
     const void *res = L.res_src >= 0 ? t[L.res_src] : nullptr;
     const int Do = conv_out_dim(D, L.k, L.stride);
+    if (c->timing && cf::conv_variant_is_fft(var[i])) {
+      // the frequency-domain path's three kernels, timed one by one
+      static const char *kStage[3] = {"fwd2d", "zconv", "inv2d"};
+      for (int st = 0; st < 3; ++st) {
+        hipEvent_t e = tbegin(c, s);
+        CF_HIP(cf::launch_fft_conv(L, t[i], res, c->act[i].p, np, D, c->convwork.p, s, st));
+        double flop = 0.0, bytes = 0.0;
+        cf::fft_conv_stage_cost(st, L, D, np, &flop, &bytes);
+        tend(c, s, e, "conv" + std::to_string(i) + ".fft32." + kStage[st], flop, bytes);
+      }
+      D = Do;
+      t.push_back(c->act[i].p);
+      continue;
+    }
     hipEvent_t e = tbegin(c, s);
     CF_HIP(cf::launch_conv(var[i], L, c->bf16, t[i], res, c->act[i].p, np, D, c->convwork.p, s));
     if (e) {

@@ -678,6 +678,8 @@ int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
   return -1;
 }
 
+bool conv_variant_is_fft(int v) { return v == kFftVariant; }
+
 int64_t conv_work_bytes(int v, const ConvLayer &L, int D_in, int n_poses) {
   return v == kFftVariant ? fft_conv_work_bytes(L, D_in, n_poses) : 0;
 }

@@ -470,32 +470,51 @@ hipError_t fft_conv_prepare(ConvLayer &L, const float *w_folded_dev, hipStream_t
   return hipGetLastError();
 }
 
+void fft_conv_stage_cost(int stage, const ConvLayer &L, int D, int np, double *flop, double *bytes) {
+  const double spec_in = (double)kCols * np * D * nch_of(L) * 32, spec_out = (double)kCols * np * D * (L.cout / 8) * 32;
+  const double vox = (double)np * D * D * D;
+  if (stage == 0) {  // 2-D real FFTs of D x D planes zero-padded to 32 x 32: ~2.5 N^2 log2 N^2 FLOP each
+    *flop = 2.5 * kN * kN * 10.0 * np * D * L.cin;
+    *bytes = vox * L.cin_pad * 2.0 + spec_in;
+  } else if (stage == 1) {  // complex multiply-adds over (dz, ci) per column and output row
+    *flop = 8.0 * L.cin * L.cout * L.k * D * kCols * np;
+    *bytes = spec_in + spec_out + (double)L.gspec_bytes;
+  } else {
+    *flop = 2.5 * kN * kN * 10.0 * np * D * L.cout;
+    *bytes = spec_out + vox * L.cout_store * 2.0 * (L.res_src >= 0 ? 2 : 1);
+  }
+}
+
 hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, void *out, int np, int D, void *work,
-                           hipStream_t s) {
+                           hipStream_t s, int stage) {
   if (!fft_conv_ok(L, D) || !work) return hipErrorInvalidValue;
   const int nch = nch_of(L), nco = L.cout / 8;
   bf16_t *xs = reinterpret_cast<bf16_t *>(work);
   bf16_t *ys = xs + (int64_t)kCols * np * D * nch * 16;
-  hipLaunchKernelGGL(k_fft_fwd2d, dim3(D, np, nch), dim3(256), fft_lds_bytes(D), s, reinterpret_cast<const bf16_t *>(in), xs, np, D,
-                     L.cin_pad, nch);
-  const int ppb = kRowsZ / D;
-  const dim3 zg((np + ppb - 1) / ppb, kCols, 1);
-  const bf16_t *gp = reinterpret_cast<const bf16_t *>(L.gspec);
-  const int gb = (int)L.gspec_bytes;
+  if (stage < 0 || stage == 0)
+    hipLaunchKernelGGL(k_fft_fwd2d, dim3(D, np, nch), dim3(256), fft_lds_bytes(D), s,
+                       reinterpret_cast<const bf16_t *>(in), xs, np, D, L.cin_pad, nch);
+  if (stage < 0 || stage == 1) {
+    const int ppb = kRowsZ / D;
+    const dim3 zg((np + ppb - 1) / ppb, kCols, 1);
+    const bf16_t *gp = reinterpret_cast<const bf16_t *>(L.gspec);
+    const int gb = (int)L.gspec_bytes;
 #define CF_ZCONV(KS, NT) \
   hipLaunchKernelGGL((k_fft_zconv<KS, NT>), zg, dim3(NT == 128 ? 256 : 128), 0, s, xs, gp, ys, np, D, nch, ppb, gb)
-  const int nt = L.cout * 2;
-  if (L.k == 7) {
-    if (nt == 128) CF_ZCONV(7, 128); else if (nt == 64) CF_ZCONV(7, 64); else CF_ZCONV(7, 32);
-  } else if (L.k == 5) {
-    if (nt == 128) CF_ZCONV(5, 128); else if (nt == 64) CF_ZCONV(5, 64); else CF_ZCONV(5, 32);
-  } else {
-    if (nt == 128) CF_ZCONV(3, 128); else if (nt == 64) CF_ZCONV(3, 64); else CF_ZCONV(3, 32);
-  }
+    const int nt = L.cout * 2;
+    if (L.k == 7) {
+      if (nt == 128) CF_ZCONV(7, 128); else if (nt == 64) CF_ZCONV(7, 64); else CF_ZCONV(7, 32);
+    } else if (L.k == 5) {
+      if (nt == 128) CF_ZCONV(5, 128); else if (nt == 64) CF_ZCONV(5, 64); else CF_ZCONV(5, 32);
+    } else {
+      if (nt == 128) CF_ZCONV(3, 128); else if (nt == 64) CF_ZCONV(3, 64); else CF_ZCONV(3, 32);
+    }
 #undef CF_ZCONV
-  hipLaunchKernelGGL(k_fft_inv2d, dim3(D, np, nco), dim3(256), fft_lds_bytes(D), s, ys, L.bias,
-                     reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), np, D, nco,
-                     L.cout_store);
+  }
+  if (stage < 0 || stage == 2)
+    hipLaunchKernelGGL(k_fft_inv2d, dim3(D, np, nco), dim3(256), fft_lds_bytes(D), s, ys, L.bias,
+                       reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), np, D, nco,
+                       L.cout_store);
   return hipGetLastError();
 }
 

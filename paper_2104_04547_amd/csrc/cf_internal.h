@@ -107,8 +107,12 @@ bool fft_conv_ok(const ConvLayer &L, int D);    // ... and at input size D
 int64_t fft_conv_gspec_bytes(const ConvLayer &L);
 int64_t fft_conv_work_bytes(const ConvLayer &L, int D, int n_poses);
 hipError_t fft_conv_prepare(ConvLayer &L, const float *w_folded_dev, hipStream_t s);
+// stage -1: the whole layer; 0, 1, 2: forward plane FFTs, z-correlation, inverse
 hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, void *out, int n_poses, int D,
-                           void *work, hipStream_t s);
+                           void *work, hipStream_t s, int stage = -1);
+// algorithmic FLOP and HBM bytes of one stage for n_poses
+void fft_conv_stage_cost(int stage, const ConvLayer &L, int D, int n_poses, double *flop, double *bytes);
+bool conv_variant_is_fft(int v);
 
 hipError_t launch_pool_dense(const void *act, int bf16, int n_poses, int vox, int cstride, int c,
                              const float *dense_w, const float *dense_b, int n_dense, const float *dense2_w,

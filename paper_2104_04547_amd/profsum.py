@@ -6,12 +6,14 @@
   traffic  HBM bytes per dispatch of one kernel from two --pmc runs (FETCH_SIZE,
            WRITE_SIZE), each scaled by what the same counter reads for a plain
            elementwise copy of known size (two more --pmc runs of
-           `bench.py --copy-probe MIB`); optionally writes the JSON the benchmark
-           reads to fill its roofline `traffic` field.
+           `bench.py --copy-probe MIB`); optionally merges an entry into the JSON
+           the benchmark reads to fill its roofline `traffic` field, keyed by the
+           benchmark's kernel name and tied to the SHA-256 of the kernel's source.
 
   python -m paper_2104_04547_amd.profsum stats RESULTS.db --command "CMD" [--top N]
-  python -m paper_2104_04547_amd.profsum traffic --kernel NAME --fetch F.db --write W.db \\
-      --copy-fetch CF.db --copy-write CW.db --copy-mib MIB [--json OUT] --command "CMD" ...
+  python -m paper_2104_04547_amd.profsum traffic --kernel NAME --key BENCH_NAME --source FILE.hip \\
+      --fetch F.db --write W.db --copy-fetch CF.db --copy-write CW.db --copy-mib MIB [--json OUT] \\
+      --command "CMD" ...
 """
 from __future__ import annotations
 
@@ -155,6 +157,8 @@ def main(argv=None):
     s.add_argument("--command", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True)
+    t.add_argument("--key", default="", help="the benchmark's name of the kernel (default: --kernel)")
+    t.add_argument("--source", default="cf_conv.hip", help="source file of the kernel under csrc/")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
     t.add_argument("--copy-fetch", required=True)
@@ -185,10 +189,10 @@ def main(argv=None):
         raise SystemExit(f"kernel {a.kernel} not found in the counter runs")
     fb = sum(fetch) / len(fetch) * 1024.0 / f_fac
     wb = sum(write) / len(write) * 1024.0 / w_fac
-    src = os.path.join(HERE, "csrc", "cf_conv.hip")
+    src = os.path.join(HERE, "csrc", a.source)
     res = dict(kernel=a.kernel, dispatches=[len(fetch), len(write)], fetch_bytes_per_launch=fb,
                write_bytes_per_launch=wb, copy_factor_fetch=f_fac, copy_factor_write=w_fac,
-               copy_bytes=nbytes, commands=a.command,
+               copy_bytes=nbytes, commands=a.command, source=a.source,
                source_sha256=hashlib.sha256(open(src, "rb").read()).hexdigest())
     if a.algorithmic_bytes:
         res["algorithmic_bytes_per_launch"] = a.algorithmic_bytes
@@ -199,7 +203,9 @@ def main(argv=None):
     print(f"{a.kernel}: {len(fetch)} dispatches; fetched {fb / 1e6:.2f} MB, written {wb / 1e6:.2f} MB per launch "
           f"(raw {sum(fetch) / len(fetch) / 1024:.1f} / {sum(write) / len(write) / 1024:.1f} MiB)")
     if a.json:
-        json.dump(res, open(a.json, "w"), indent=1)
+        allt = json.load(open(a.json)) if os.path.exists(a.json) else {}
+        allt[a.key or a.kernel] = res
+        json.dump(allt, open(a.json, "w"), indent=1)
 
 
 if __name__ == "__main__":
