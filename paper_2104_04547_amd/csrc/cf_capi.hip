@@ -64,7 +64,7 @@ struct cf_ctx {
   std::vector<void *> weight_allocs;
   // second stream for the graph / SG-CNN branch of cf_score_poses, joined by events
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_sg = nullptr, ev_head = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_sg = nullptr;
 
   // per-kernel timing (diagnostics, off by default)
   struct Pending {
@@ -267,8 +267,9 @@ int ensure_act(cf_ctx *c, int G, int np) {
   return CF_OK;
 }
 
-// conv stack + pooling on grids already in the internal padded layout in c->grid
-int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s) {
+// conv stack + pooling on grids already in the internal padded layout in c->grid;
+// after_first (optional) is recorded on s once the first layer is enqueued
+int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s, hipEvent_t after_first = nullptr) {
   std::vector<int> var;
   int rc = variants_for(c, G, var);
   if (rc) return rc;
@@ -300,6 +301,7 @@ int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s) {
       }
       D = Do;
       t.push_back(c->act[i].p);
+      if (i == 0 && after_first) CF_HIP(hipEventRecord(after_first, s));
       continue;
     }
     hipEvent_t e = tbegin(c, s);
@@ -312,6 +314,7 @@ int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s) {
     }
     D = Do;
     t.push_back(c->act[i].p);
+    if (i == 0 && after_first) CF_HIP(hipEventRecord(after_first, s));
   }
   const auto &Ll = c->conv.back();
   hipEvent_t e = tbegin(c, s);
@@ -725,7 +728,7 @@ void free_ctx(cf_ctx *c) {
     if (b.p) (void)hipFree(b.p);
   if (c->convwork.p) (void)hipFree(c->convwork.p);
   if (c->status) (void)hipFree(c->status);
-  hipEvent_t evs[] = {c->ev_fork, c->ev_sg, c->ev_head};
+  hipEvent_t evs[] = {c->ev_fork, c->ev_sg};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
   if (c->side) (void)hipStreamDestroy(c->side);
@@ -783,8 +786,7 @@ int cf_create(const void *blob, size_t nbytes, int precision, int64_t hbm_budget
   if (rc == CF_OK &&
       (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-       hipEventCreateWithFlags(&c->ev_sg, hipEventDisableTiming) != hipSuccess ||
-       hipEventCreateWithFlags(&c->ev_head, hipEventDisableTiming) != hipSuccess))
+       hipEventCreateWithFlags(&c->ev_sg, hipEventDisableTiming) != hipSuccess))
     rc = fail(CF_ERR_HIP, "stream or event creation failed");
   if (rc != CF_OK) {
     free_ctx(c);
@@ -913,16 +915,30 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
   if ((rc = ensure(c, c->sg_lat, (size_t)chunk * c->sgw * sizeof(float)))) return rc;
   const int H = c->sgw;
   // The graph / SG-CNN branch of each chunk runs on the context's side stream,
-  // overlapping the chunk's voxelisation and conv stack; the head joins them.  The
-  // side stream starts after the caller's prior work on `stream` (ev_fork) and each
-  // chunk's branch after the previous chunk's head has read sg_lat (ev_head).
+  // forked once the chunk's first conv layer is enqueued (ev_fork, recorded on
+  // `stream` after it) so that it overlaps the remaining layers rather than the
+  // first, whose halo fills a CU's LDS; the head joins the branch (ev_sg).  The
+  // fork also orders the branch after the caller's prior work and after the
+  // previous chunk's head, which read the SG latents it overwrites.
   hipStream_t s2 = c->side;
-  CF_HIP(hipEventRecord(c->ev_fork, s));
   for (int p0 = 0; p0 < b->n_poses; p0 += chunk) {
     const int np = std::min(chunk, b->n_poses - p0);
     const int32_t *cen;
     const double atoms = (double)b->n_atoms * np / b->n_poses;  // for the byte counts only
-    CF_HIP(hipStreamWaitEvent(s2, p0 == 0 ? c->ev_fork : c->ev_head, 0));
+    if (b->center) {
+      cen = b->center + 3 * (size_t)p0;
+    } else {
+      hipEvent_t e = tbegin(c, s);
+      CF_HIP(cf::launch_centers(b->atom_off, b->n_atoms, b->xyz, b->is_lig, p0, np, (int32_t *)c->centers.p, c->status, s));
+      tend(c, s, e, "centers", 0.0, atoms * 13.0);
+      cen = (const int32_t *)c->centers.p;
+    }
+    hipEvent_t e = tbegin(c, s);
+    CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, p0, np, G, c->grid.p, c->bf16 ? 3 : 2,
+                            grid_cpad(c), c->status, s));
+    tend(c, s, e, "splat", 0.0, atoms * (12.0 + 4.0 * CF_NCH) + (double)np * G * G * G * CF_NCH * elem_size(c));
+    if ((rc = run_cnn(c, G, np, (float *)c->cnn_lat.p, s, c->ev_fork))) return rc;
+    CF_HIP(hipStreamWaitEvent(s2, c->ev_fork, 0));
     hipEvent_t eg = tbegin(c, s2);
     CF_HIP(cf::launch_graph(b->atom_off, b->n_atoms, b->xyz, p0, np, c->desc.r_cov_u, c->desc.r_nc_u, (int32_t *)c->cov_row.p,
                             (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
@@ -946,25 +962,11 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
                             acap * 96, 0, (float *)c->hbuf.p, acap, (float *)c->sg_lat.p, c->status, s2));
     tend(c, s2, eg, "sgcnn", atoms * c->sg_flop_atom, atoms * 4.0 * CF_NCH);
     CF_HIP(hipEventRecord(c->ev_sg, s2));
-    if (b->center) {
-      cen = b->center + 3 * (size_t)p0;
-    } else {
-      hipEvent_t e = tbegin(c, s);
-      CF_HIP(cf::launch_centers(b->atom_off, b->n_atoms, b->xyz, b->is_lig, p0, np, (int32_t *)c->centers.p, c->status, s));
-      tend(c, s, e, "centers", 0.0, atoms * 13.0);
-      cen = (const int32_t *)c->centers.p;
-    }
-    hipEvent_t e = tbegin(c, s);
-    CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, p0, np, G, c->grid.p, c->bf16 ? 3 : 2,
-                            grid_cpad(c), c->status, s));
-    tend(c, s, e, "splat", 0.0, atoms * (12.0 + 4.0 * CF_NCH) + (double)np * G * G * G * CF_NCH * elem_size(c));
-    if ((rc = run_cnn(c, G, np, (float *)c->cnn_lat.p, s))) return rc;
     CF_HIP(hipStreamWaitEvent(s, c->ev_sg, 0));
     e = tbegin(c, s);
     CF_HIP(cf::launch_head((float *)c->cnn_lat.p, c->lc, (float *)c->sg_lat.p, H, c->head_prm, c->head, np,
                            scores + p0, s));
     tend(c, s, e, "fusion", 0.0, 0.0);
-    CF_HIP(hipEventRecord(c->ev_head, s));
   }
   return CF_OK;
 }
