@@ -300,6 +300,13 @@ struct Conv8Cfg {
                              : (PLANES * ROW_T <= 163840)  ? ROW_T
                                                            : HX * 16;  // bytes
   static constexpr int SLAB = HY * ROW;
+  // Rows of a 16-lane group: two runs of 8 voxels (TX = 8) YD rows apart, with YD
+  // the smallest of 1, 2, 4 that puts them 128 mod 256 bytes apart (disjoint banks)
+  // when the pitch itself cannot be (the tight pitch of one-workgroup halos).
+  static constexpr int YD = (TX != 8 || ROW % 256 == 128)            ? 1
+                            : ((2 * ROW) % 256 == 128 && TY % 4 == 0) ? 2
+                            : ((4 * ROW) % 256 == 128 && TY % 8 == 0) ? 4
+                                                                      : 1;
   // PP poses per workgroup (the same tile of consecutive poses): the halo of
   // pose pp sits at pp * HALO1, its rows are tile rows pp * MT1 .. + MT1.  Each
   // weight fragment then serves PP times the rows.
@@ -330,6 +337,21 @@ struct Conv8Cfg {
   static_assert(LDS <= 163840, "halo exceeds LDS");
 };
 
+// Output voxel (z, y, x) of tile row ml (one pose's tile): x fastest in runs of TX;
+// with YD > 1 the y order pairs y with y + YD in consecutive runs.
+template <int TY, int TX, int YD>
+__device__ inline void tile_coord(int ml, int &z, int &y, int &x) {
+  z = ml / (TY * TX);
+  const int r = ml % (TY * TX), g = r / TX;
+  x = r % TX;
+  if (YD == 4)
+    y = (g & ~7) + (g >> 1 & 3) + 4 * (g & 1);
+  else if (YD == 2)
+    y = (g & ~3) + (g >> 1 & 1) + 2 * (g & 1);
+  else
+    y = g;
+}
+
 template <int KS, int S, int TZ, int TY, int TX, int NW, int NT, int WN, int PP>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv8Cfg<KS, S, TZ, TY, TX, NW, NT, WN, PP>::WPE))) void k_conv8(const bf16_t *__restrict__ in, const bf16_t *__restrict__ wpk,
                                                     const float *__restrict__ bias, const bf16_t *__restrict__ res,
@@ -353,7 +375,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv8Cf
   for (int mb = 0; mb < C::MB; ++mb) {
     const int m = wave_m * C::WM + mb * 32 + lrow;
     const int pp = m / C::MT1, ml = m % C::MT1;
-    const int z = ml / (TY * TX), y = (ml / TX) % TY, x = ml % TX;
+    int z, y, x;
+    tile_coord<TY, TX, C::YD>(ml, z, y, x);
     rowoff[mb] = pp * C::HALO1 + z * C::SLAB + y * C::ROW + x * 16;
   }
   typedef float accv __attribute__((ext_vector_type(16)));
@@ -491,7 +514,11 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv8Cf
   const int64_t pose_out = (int64_t)pose0 * Do * Do * Do;
   auto row_base = [&](int m, bool &valid) -> int64_t {
     const int pp = m / C::MT1, ml = m % C::MT1;
-    const int z = tz0 + ml / (TY * TX), y = ty0 + (ml / TX) % TY, x = tx0 + ml % TX;
+    int z, y, x;
+    tile_coord<TY, TX, C::YD>(ml, z, y, x);
+    z += tz0;
+    y += ty0;
+    x += tx0;
     valid = z < Do && y < Do && x < Do && (PP == 1 || pose0 + pp < n_poses);
     return (pose_out + (((int64_t)pp * Do + z) * Do + y) * Do + x) * cout_store;
   };
