@@ -385,6 +385,23 @@ std::vector<bf16_t> pack_conv8(const std::vector<float> &W, int cout, int cin, i
   return out;
 }
 
+// tap-quad packing: [quad][4-channel chunk][c_out (pad 32)][16], element e of a
+// row = tap 4 quad + e / 4, channel 4 chunk + e % 4; four zero quads past the end
+// for the weight prefetch
+std::vector<bf16_t> pack_conv4(const std::vector<float> &W, int cout, int cin, int k, int cout_pad32) {
+  const int taps = k * k * k, quads = (taps + 3) / 4, nch = (cin + 3) / 4;
+  std::vector<bf16_t> out((size_t)(quads + 4) * nch * cout_pad32 * 16, (bf16_t)0.0f);
+  for (int q = 0; q < quads; ++q)
+    for (int ch = 0; ch < nch; ++ch)
+      for (int n = 0; n < cout; ++n)
+        for (int e = 0; e < 16; ++e) {
+          const int tap = 4 * q + e / 4, c = ch * 4 + e % 4;
+          if (tap >= taps || c >= cin) continue;
+          out[(((size_t)q * nch + ch) * cout_pad32 + n) * 16 + e] = (bf16_t)W[((size_t)n * cin + c) * taps + tap];
+        }
+  return out;
+}
+
 std::vector<float> transpose(const float *w, int rows, int cols) {  // [rows][cols] -> [cols][rows]
   std::vector<float> t((size_t)rows * cols);
   for (int r = 0; r < rows; ++r)
@@ -576,6 +593,11 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
       auto pk8 = pack_conv8(Wf, co, ci, k, L.cout_pad32);
       L.wbytes8 = (int64_t)(pk8.size() * sizeof(bf16_t));
       rc = alloc_weight(c, &L.wpk8, pk8.size() * sizeof(bf16_t), pk8.data());
+    }
+    if (!rc && c->bf16 && ci % 8 != 0) {
+      auto pk4 = pack_conv4(Wf, co, ci, k, L.cout_pad32);
+      L.wbytes4 = (int64_t)(pk4.size() * sizeof(bf16_t));
+      rc = alloc_weight(c, &L.wpk4, pk4.size() * sizeof(bf16_t), pk4.data());
     }
     if (!rc && c->bf16 && cf::fft_conv_layer_ok(L)) {
       // frequency-domain path: in-plane spectra of the folded weights, built on the device

@@ -565,10 +565,228 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv8Cf
   }
 }
 
+// ---- bf16 with 4-channel chunks and tap quads -----------------------------------
+//
+// For inputs whose channel count leaves much of an 8-channel chunk empty (the
+// 19-channel grid: 24 padded channels, 21 % zeros) the K walk takes 4 channels x 4
+// taps per 16-deep MFMA step: lanes of the first K half read taps 4q and 4q + 1,
+// the second half 4q + 2 and 4q + 3, 8 bytes (4 channels) each.  19 channels cost
+// 20, and the halo needs 8 bytes per voxel, so the 21^3 halo of an 8^3 stride-2
+// tile fits twice per CU.  Tap offsets come from a table in LDS.
+template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+struct Conv4Cfg {
+  static_assert(KS >= 3 && KS % 2 == 1, "odd kernel of at least 3 taps per axis");
+  static constexpr int PAD = (KS - 1) / 2;
+  static constexpr int HZ = TZ * S + KS - S, HY = TY * S + KS - S, HX = TX * S + KS - S;
+  static constexpr int ROW = HX * 8 + 8, SLAB = HY * ROW, HALO = HZ * SLAB;  // bytes
+  static constexpr int TAPS = KS * KS * KS, QUADS = (TAPS + 3) / 4, TAB = QUADS * 4 * 4;
+  static constexpr int MT = TZ * TY * TX, WM = MT / NW, MB = WM / 32, NB = NT / 32;
+  static constexpr int MBG = (NW * 32 * NT * 2 * MB <= HALO) ? MB : ((NW * 32 * NT * 2 * 2 <= HALO && MB % 2 == 0) ? 2 : 1);
+  static constexpr int EPI = NW * 32 * MBG * NT * 2;
+  static constexpr int LDS = TAB + (HALO > EPI ? HALO : EPI);
+  static constexpr int WPE = LDS > 81920 ? 1 : 2;
+  static constexpr int HITER = (HZ * HY * HX + NW * 64 - 1) / (NW * 64);
+  static constexpr int HB = HITER < 8 ? HITER : 8;
+  static_assert(WM % 32 == 0, "rows per wave must be a multiple of 32");
+  static_assert(LDS <= 163840, "halo exceeds LDS");
+};
+
+template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv4Cfg<KS, S, TZ, TY, TX, NW, NT>::WPE))) void k_conv4(
+    const bf16_t *__restrict__ in, const bf16_t *__restrict__ wpk, const float *__restrict__ bias,
+    const bf16_t *__restrict__ res, bf16_t *__restrict__ out, int D, int Do, int cin_pad, int nchunks, int cout_pad32,
+    int cout_store, int nty, int ntx, int wbytes) {
+  using C = Conv4Cfg<KS, S, TZ, TY, TX, NW, NT>;
+  __shared__ __attribute__((aligned(16))) char lds[C::LDS];
+  int *tab = reinterpret_cast<int *>(lds);  // [QUADS * 4] tap offsets into the halo
+  char *halo = lds + C::TAB;
+  int tile, pose, nblk;
+  xcd_order(tile, pose, nblk);
+  const int n0 = nblk * NT;
+  const int tz0 = (tile / (nty * ntx)) * TZ, ty0 = ((tile / ntx) % nty) * TY, tx0 = (tile % ntx) * TX;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int khalf = lane >> 5, lrow = lane & 31;
+  constexpr int NTH = NW * 64;
+  constexpr int HZ2 = (C::HZ + 1) / 2, HY2 = (C::HY + 1) / 2, HX2 = (C::HX + 1) / 2;
+  for (int t = threadIdx.x; t < C::QUADS * 4; t += NTH) {
+    int off = 0;  // taps past the last read offset 0 (their weights are zero)
+    if (t < C::TAPS) {
+      const int dz = t / (KS * KS), dy = (t / KS) % KS, dx = t % KS;
+      off = (S == 1 ? dz : (dz & 1) * HZ2 + (dz >> 1)) * C::SLAB + (S == 1 ? dy : (dy & 1) * HY2 + (dy >> 1)) * C::ROW +
+            (S == 1 ? dx : (dx & 1) * HX2 + (dx >> 1)) * 8;
+    }
+    tab[t] = off;
+  }
+  int rowoff[C::MB];
+#pragma unroll
+  for (int mb = 0; mb < C::MB; ++mb) {
+    const int m = wave * C::WM + mb * 32 + lrow;
+    const int z = m / (TY * TX), y = (m / TX) % TY, x = m % TX;
+    rowoff[mb] = z * C::SLAB + y * C::ROW + x * 8;
+  }
+  typedef float accv __attribute__((ext_vector_type(16)));
+  accv acc[C::MB][C::NB];
+#pragma unroll
+  for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
+  const int oz = tz0 * S - C::PAD, oy = ty0 * S - C::PAD, ox = tx0 * S - C::PAD;
+  const int64_t pose_in = (int64_t)pose * D * D * D;
+  constexpr int NV = C::HZ * C::HY * C::HX;
+  constexpr int kPF = 4;
+  const int quad_bytes = nchunks * cout_pad32 * 16 * 2;
+  const __amdgpu_buffer_rsrc_t wrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(wpk), (short)0, wbytes, 0x00020000);
+  for (int chunk = 0; chunk < nchunks; ++chunk) {
+    __syncthreads();  // the table is written / the previous chunk's halo is read
+    // batches of HB loads in flight; the batch loop is not unrolled, so the halo
+    // addressing is recomputed per chunk rather than hoisted and held in registers
+#pragma unroll 1
+    for (int it0 = 0; it0 < C::HITER; it0 += C::HB) {
+      uint2 hv[C::HB];
+#pragma unroll
+      for (int it = it0; it < it0 + C::HB && it < C::HITER; ++it) {
+        const int v = it * NTH + (int)threadIdx.x;
+        hv[it - it0] = make_uint2(0, 0);
+        if (v < NV) {
+          const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
+          const int gz = oz + hz, gy = oy + hy, gx = ox + hx;
+          if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gx < (unsigned)D)
+            hv[it - it0] = *reinterpret_cast<const uint2 *>(
+                in + ((pose_in + ((int64_t)gz * D + gy) * D + gx) * cin_pad + chunk * 4));
+        }
+      }
+#pragma unroll
+      for (int it = it0; it < it0 + C::HB && it < C::HITER; ++it) {
+        const int v = it * NTH + (int)threadIdx.x;
+        if (v < NV) {
+          const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
+          const int off = stored_index(hz, C::HZ, S) * C::SLAB + stored_index(hy, C::HY, S) * C::ROW +
+                          stored_index(hx, C::HX, S) * 8;
+          *reinterpret_cast<uint2 *>(halo + off) = hv[it - it0];
+        }
+      }
+    }
+    __syncthreads();
+    int vb[C::NB];
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb) vb[nb] = ((chunk * cout_pad32 + n0 + nb * 32 + lrow) * 16 + khalf * 8) * 2;
+    uint4 bq[kPF][C::NB];
+#pragma unroll
+    for (int q = 0; q < kPF; ++q)
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb)
+        bq[q][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], q * quad_bytes, 0));
+    int soff = kPF * quad_bytes;
+    // row fragments one quad ahead: two 8-byte reads per row block (taps t, t + 1)
+    uint4 ar[2][C::MB];
+    {
+      const int t0 = tab[2 * khalf], t1 = tab[2 * khalf + 1];
+#pragma unroll
+      for (int mb = 0; mb < C::MB; ++mb) {
+        const uint2 lo = *reinterpret_cast<const uint2 *>(halo + rowoff[mb] + t0);
+        const uint2 hi = *reinterpret_cast<const uint2 *>(halo + rowoff[mb] + t1);
+        ar[0][mb] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+      }
+    }
+    for (int q0 = 0; q0 < C::QUADS; q0 += kPF) {
+#pragma unroll
+      for (int ph = 0; ph < kPF; ++ph) {
+        const int q = q0 + ph;
+        if (q < C::QUADS) {
+          const int qn = q + 1 < C::QUADS ? q + 1 : q;
+          const int t0 = tab[4 * qn + 2 * khalf], t1 = tab[4 * qn + 2 * khalf + 1];
+#pragma unroll
+          for (int mb = 0; mb < C::MB; ++mb) {
+            const uint2 lo = *reinterpret_cast<const uint2 *>(halo + rowoff[mb] + t0);
+            const uint2 hi = *reinterpret_cast<const uint2 *>(halo + rowoff[mb] + t1);
+            ar[(ph + 1) & 1][mb] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ar[ph & 1][mb]),
+                                                                     __builtin_bit_cast(bf16x8, bq[ph][nb]),
+                                                                     acc[mb][nb], 0, 0, 0);
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb)
+            bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], soff, 0));
+          soff += quad_bytes;
+        }
+      }
+    }
+  }
+
+  // ---- epilogue through LDS (as k_conv8) ----
+  const int64_t pose_out = (int64_t)pose * Do * Do * Do;
+  auto row_base = [&](int m, bool &valid) -> int64_t {
+    const int z = tz0 + m / (TY * TX), y = ty0 + (m / TX) % TY, x = tx0 + m % TX;
+    valid = z < Do && y < Do && x < Do;
+    return (pose_out + ((int64_t)z * Do + y) * Do + x) * cout_store;
+  };
+  bf16_t *ot = reinterpret_cast<bf16_t *>(halo);  // [NW][MBG*32][NT]
+  constexpr int SEG = NT / 8;
+  constexpr int GR = C::MBG * 32;
+#pragma unroll
+  for (int g = 0; g < C::MB; g += C::MBG) {
+    __syncthreads();
+    if (res) {
+      for (int e = threadIdx.x; e < NW * GR * SEG; e += NTH) {
+        const int lr = e / SEG, qq = e % SEG;
+        const int m = (lr / GR) * C::WM + g * 32 + lr % GR;
+        bool valid;
+        const int64_t ob = row_base(m, valid);
+        if (valid && n0 + qq * 8 + 8 <= cout_store)
+          *reinterpret_cast<uint4 *>(ot + lr * NT + qq * 8) = *reinterpret_cast<const uint4 *>(res + ob + n0 + qq * 8);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int mb = g; mb < g + C::MBG; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int lr = wave * GR + (mb - g) * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) {
+          const int col = nb * 32 + lrow;
+          float v = acc[mb][nb][r] + bias[n0 + col];
+          if (res) v += (float)ot[lr * NT + col];
+          ot[lr * NT + col] = (bf16_t)(v > 0.0f ? v : 0.0f);
+        }
+      }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NW * GR * SEG; e += NTH) {
+      const int lr = e / SEG, qq = e % SEG;
+      const int m = (lr / GR) * C::WM + g * 32 + lr % GR;
+      bool valid;
+      const int64_t ob = row_base(m, valid);
+      if (valid && n0 + qq * 8 + 8 <= cout_store)
+        *reinterpret_cast<uint4 *>(out + ob + n0 + qq * 8) = *reinterpret_cast<const uint4 *>(ot + lr * NT + qq * 8);
+    }
+  }
+}
+
+template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
+hipError_t launch_q(const ConvLayer &L, const void *in, const void *res, void *out, int n_poses, int D,
+                    hipStream_t s) {
+  const int Do = (D + 2 * ((KS - 1) / 2) - KS) / S + 1;
+  const int ntz = (Do + TZ - 1) / TZ, nty = (Do + TY - 1) / TY, ntx = (Do + TX - 1) / TX;
+  const dim3 grid(ntz * nty * ntx, n_poses, L.cout_pad32 / NT);
+  hipLaunchKernelGGL((k_conv4<KS, S, TZ, TY, TX, NW, NT>), grid, dim3(NW * 64), 0, s,
+                     reinterpret_cast<const bf16_t *>(in), reinterpret_cast<const bf16_t *>(L.wpk4), L.bias,
+                     reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), D, Do, L.cin_pad,
+                     (L.cin + 3) / 4, L.cout_pad32, L.cout_store, nty, ntx, (int)L.wbytes4);
+  return hipGetLastError();
+}
+
 struct Variant {
   const char *name;
   int ks, s, tz, ty, tx, nw, nt;
-  int pairs;  // 1: bf16 8-channel tap-pair kernel (k_conv8, weights in wpk8)
+  int pairs;  // 1: bf16 8-channel tap-pair kernel (k_conv8, weights in wpk8); 2: 4-channel tap quads (k_conv4, wpk4)
   hipError_t (*launch_bf16)(const ConvLayer &, const void *, const void *, void *, int, int, hipStream_t);
   hipError_t (*launch_f32)(const ConvLayer &, const void *, const void *, void *, int, int, hipStream_t);
 };
@@ -614,6 +832,11 @@ hipError_t launch_t(const ConvLayer &L, const void *in, const void *res, void *o
   Variant {                                                                                              \
     "p8k" #KS "s" #S "_t" #TZ "x" #TY "x" #TX "_w" #NW "c" #WN "_n" #NT, KS, S, TZ, TY, TX, NW, NT, 1,   \
         &launch_p<KS, S, TZ, TY, TX, NW, NT, WN, 1>, nullptr                                             \
+  }
+#define CF_VARIANT4(KS, S, TZ, TY, TX, NW, NT)                                                   \
+  Variant {                                                                                      \
+    "q4k" #KS "s" #S "_t" #TZ "x" #TY "x" #TX "_w" #NW "_n" #NT, KS, S, TZ, TY, TX, NW, NT, 2,   \
+        &launch_q<KS, S, TZ, TY, TX, NW, NT>, nullptr                                            \
   }
 // ... and PP poses per workgroup
 #define CF_VARIANT8P(KS, S, TZ, TY, TX, NW, NT, WN, PP)                                                           \
@@ -670,7 +893,11 @@ const Variant kVariants[] = {
     // two poses per workgroup: 384 rows share each weight fragment (the 5.6 MB of
     // weights of the 64 -> 128 layer exceed an XCD's L2, so weight traffic per row
     // sets its speed); 12^3 outputs in 9 whole tiles
-    CF_VARIANT8P(7, 2, 4, 4, 12, 8, 128, 2, 2)    // 40
+    CF_VARIANT8P(7, 2, 4, 4, 12, 8, 128, 2, 2),   // 40
+    // 4-channel tap quads for the 19-channel grid
+    CF_VARIANT4(7, 2, 8, 8, 8, 4, 64),   // 41: 21^3 halo at 8 bytes per voxel, two workgroups per CU
+    CF_VARIANT4(5, 2, 8, 8, 8, 4, 32),   // 42
+    CF_VARIANT4(5, 1, 8, 8, 8, 4, 32)    // 43
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -688,6 +915,7 @@ bool conv_variant_ok(int v, const ConvLayer &L, int bf16, int D_in) {
   if (v == kFftVariant) return bf16 && fft_conv_ok(L, D_in);
   if (v < 0 || v >= kNumVariants) return false;
   const Variant &V = kVariants[v];
+  if (V.pairs == 2) return bf16 && L.wpk4 && V.ks == L.k && V.s == L.stride && L.cout_pad32 % V.nt == 0 && L.cin_pad % 4 == 0;
   if (V.pairs) return bf16 && L.wpk8 && V.ks == L.k && V.s == L.stride && L.cout_pad32 % V.nt == 0 && L.cin_pad % 8 == 0;
   const int cc = bf16 ? 16 : 8;
   return V.ks == L.k && V.s == L.stride && L.cout_pad32 % V.nt == 0 && L.cin_pad % cc == 0;
@@ -695,11 +923,11 @@ bool conv_variant_ok(int v, const ConvLayer &L, int bf16, int D_in) {
 
 int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
   // measured on MI355X at 48^3: bf16 7^3 stride-1 layers in the frequency domain
-  // (2x the tap-pair kernel), else tap pairs for stride 1 and the 128-column
-  // stride-2 layer, two poses per workgroup there; fp32 has no tap-pair kernel
+  // (3x the tap-pair kernel), tap quads for the 19-channel first layer, tap pairs
+  // for the 128-column stride-2 layer (two poses per workgroup); fp32 has neither
   if (bf16 && L.k == 7 && conv_variant_ok(kFftVariant, L, bf16, D_in)) return kFftVariant;
-  const int pref[] = {12, 40, 17, 20, 19, 23, 26, 28, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18, 21,
-                      22, 24, 25, 27, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39};
+  const int pref[] = {12, 40, 41, 17, 20, 19, 23, 26, 28, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18,
+                      21, 22, 24, 25, 27, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39, 42, 43};
   for (int v : pref)
     if (conv_variant_ok(v, L, bf16, D_in)) return v;
   return -1;

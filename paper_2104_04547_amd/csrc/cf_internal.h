@@ -72,6 +72,8 @@ struct ConvLayer {
   int64_t wbytes;  // size of the packed weights in bytes
   void *wpk8;      // bf16 only: weights packed for the tap-pair kernel
   int64_t wbytes8;
+  void *wpk4;      // bf16, input channels not a multiple of 8: weights packed for the tap-quad kernel
+  int64_t wbytes4;
   float *bias;     // folded bias [cout_pad32]
   void *gspec;     // bf16 stride-1 layers: in-plane spectra of the weights (frequency-domain path)
   int64_t gspec_bytes;
