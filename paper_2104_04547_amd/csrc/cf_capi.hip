@@ -285,19 +285,50 @@ int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s, hipEvent_t 
   std::vector<const void *> t;
   t.push_back(c->grid.p);
   int D = G;
-  for (size_t i = 0; i < c->conv.size(); ++i) {
+  const int nl = (int)c->conv.size();
+  // the activation t[k] is read from memory by a later layer (as input of a direct
+  // kernel, or as a residual)
+  auto stored = [&](int k) {
+    for (int j = k; j < nl; ++j)
+      if (c->conv[j].res_src == k) return true;
+    return false;
+  };
+  bool pend = false;  // the previous layer's output is still a spectrum in the work buffer
+  for (int i = 0; i < nl; ++i) {
     const auto &L = c->conv[i];
     const void *res = L.res_src >= 0 ? t[L.res_src] : nullptr;
     const int Do = conv_out_dim(D, L.k, L.stride);
-    if (c->timing && cf::conv_variant_is_fft(var[i])) {
-      // the frequency-domain path's three kernels, timed one by one
-      static const char *kStage[3] = {"fwd2d", "zconv", "inv2d"};
-      for (int st = 0; st < 3; ++st) {
-        hipEvent_t e = tbegin(c, s);
-        CF_HIP(cf::launch_fft_conv(L, t[i], res, c->act[i].p, np, D, c->convwork.p, s, st));
-        double flop = 0.0, bytes = 0.0;
-        cf::fft_conv_stage_cost(st, L, D, np, &flop, &bytes);
-        tend(c, s, e, "conv" + std::to_string(i) + ".fft32." + kStage[st], flop, bytes);
+    if (cf::conv_variant_is_fft(var[i])) {
+      // frequency-domain layer: forward transform (or, after another such layer,
+      // that layer's inverse and this forward in one kernel), z-correlation, and the
+      // inverse -- deferred into the next layer's kernel when it is one too
+      double flop = 0.0, bytes = 0.0, f2 = 0.0, b2 = 0.0;
+      hipEvent_t e = tbegin(c, s);
+      if (pend) {
+        const auto &Lp = c->conv[i - 1];
+        const void *resp = Lp.res_src >= 0 ? t[Lp.res_src] : nullptr;
+        const bool keep = stored(i);
+        CF_HIP(cf::launch_fft_mid(Lp, L, resp, keep ? c->act[i - 1].p : nullptr, np, D, c->convwork.p, s));
+        cf::fft_conv_stage_cost(2, Lp, D, np, &flop, &bytes);
+        cf::fft_conv_stage_cost(0, L, D, np, &f2, &b2);
+        // the activation between them moves only if stored (written once, not read back)
+        const double act = (double)np * D * D * D * Lp.cout_store * 2.0;
+        tend(c, s, e, "conv" + std::to_string(i - 1) + ".fft32.mid", flop + f2, bytes + b2 - act * (keep ? 1.0 : 2.0));
+      } else {
+        CF_HIP(cf::launch_fft_conv(L, t[i], res, c->act[i].p, np, D, c->convwork.p, s, 0));
+        cf::fft_conv_stage_cost(0, L, D, np, &flop, &bytes);
+        tend(c, s, e, "conv" + std::to_string(i) + ".fft32.fwd2d", flop, bytes);
+      }
+      e = tbegin(c, s);
+      CF_HIP(cf::launch_fft_conv(L, t[i], res, c->act[i].p, np, D, c->convwork.p, s, 1));
+      cf::fft_conv_stage_cost(1, L, D, np, &flop, &bytes);
+      tend(c, s, e, "conv" + std::to_string(i) + ".fft32.zconv", flop, bytes);
+      pend = i + 1 < nl && cf::conv_variant_is_fft(var[i + 1]) && Do == D && cf::fft_conv_fusable(L, c->conv[i + 1], D);
+      if (!pend) {
+        e = tbegin(c, s);
+        CF_HIP(cf::launch_fft_conv(L, t[i], res, c->act[i].p, np, D, c->convwork.p, s, 2));
+        cf::fft_conv_stage_cost(2, L, D, np, &flop, &bytes);
+        tend(c, s, e, "conv" + std::to_string(i) + ".fft32.inv2d", flop, bytes);
       }
       D = Do;
       t.push_back(c->act[i].p);

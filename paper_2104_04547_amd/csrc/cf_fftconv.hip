@@ -231,6 +231,159 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
+// ---------------------------------------------------------------- fused inverse + forward
+
+// Between two frequency-domain layers: the inverse of layer i (bias, residual,
+// ReLU, bf16 rounding exactly as k_fft_inv2d stores it) feeds the forward
+// transform of layer i + 1 in registers, so the activation makes no round trip
+// through memory; it is stored only when a later layer reads it (out != null).
+// One workgroup per (z, pose, chunk); the chunking of layer i's output is the
+// chunking of layer i + 1's input.  LDS: the spectrum / column transforms
+// (fft_lds_bytes) and, with a residual or a stored output, the activation plane
+// [y][x][8] bf16.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_mid(
+    const bf16_t *__restrict__ ys, const float *__restrict__ bias, const bf16_t *__restrict__ res,
+    bf16_t *__restrict__ out, bf16_t *__restrict__ xs, int np, int D, int nch, int cout_store, int lds_spec) {
+  int chunk, z, p;
+  xcd_order(z, p, chunk);
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  bf16_t *Y = reinterpret_cast<bf16_t *>(dyn_lds);                 // [col][re | im][8]
+  float2 *T = reinterpret_cast<float2 *>(dyn_lds);                 // [kx][y][8]
+  bf16_t *R = reinterpret_cast<bf16_t *>(dyn_lds + lds_spec);      // [y][x][8]: residual in, activation out
+  const int tid = threadIdx.x, DP = D + 1;
+  const int64_t rowb = (int64_t)nch * 16;
+  const int64_t base = (((int64_t)p * D + z) * D * D) * cout_store + chunk * 8;
+  for (int e = tid; e < kCols * 2; e += 256) {
+    const int col = e >> 1, h = e & 1;
+    *reinterpret_cast<uint4 *>(Y + col * 16 + h * 8) =
+        *reinterpret_cast<const uint4 *>(ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * 8);
+  }
+  if (res)
+    for (int v = tid; v < D * D; v += 256)
+      *reinterpret_cast<uint4 *>(R + v * 8) = *reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store);
+  __syncthreads();
+  // inverse columns along ky (as k_fft_inv2d)
+  {
+    const bool colw = tid < kNX * 8;
+    const int kx = tid >> 3, c = tid & 7;
+    const bool odd = c & 1;
+    const uint32_t *Yw = reinterpret_cast<const uint32_t *>(Y);
+    float re[32], im[32];
+    if (colw) {
+#pragma unroll
+      for (int ky = 0; ky < 32; ++ky) {
+        const uint32_t two = Yw[(ky * kNX + kx) * 8 + (odd ? 4 : 0) + (c >> 1)];
+        const float lo = __uint_as_float(two << 16), hi = __uint_as_float(two & 0xffff0000u);
+        const float other = __shfl_xor(odd ? lo : hi, 1);
+        re[ky] = odd ? other : lo;
+        im[ky] = odd ? hi : other;
+      }
+    }
+    __syncthreads();
+    if (colw) {
+      fft32<true>(re, im);
+#pragma unroll
+      for (int y = 0; y < kDMax; ++y)
+        if (y < D) T[(kx * DP + y) * 8 + c] = make_float2(re[y], im[y]);
+    }
+  }
+  __syncthreads();
+  // rows along x: inverse of two channels, epilogue, bf16, then their forward
+  // transform (the next layer's input rows)
+  {
+    const bool roww = tid < D * 4;
+    const int y = tid >> 2, c0 = (tid & 3) * 2;
+    float re[32], im[32];
+    if (roww) {
+#pragma unroll
+      for (int k = 0; k < kNX; ++k) {
+        const float4 ab = *reinterpret_cast<const float4 *>(T + (k * DP + y) * 8 + c0);
+        float2 a = make_float2(ab.x, ab.y), b = make_float2(ab.z, ab.w);
+        if (k == 0 || k == kNX - 1) {
+          a.y = 0.0f;
+          b.y = 0.0f;
+        }
+        re[k] = a.x - b.y;
+        im[k] = a.y + b.x;
+        if (k > 0 && k < kNX - 1) {
+          re[32 - k] = a.x + b.y;
+          im[32 - k] = b.x - a.y;
+        }
+      }
+    }
+    __syncthreads();  // T is in registers; its LDS becomes the next layer's row spectra
+    if (roww) {
+      fft32<true>(re, im);
+      constexpr float kScale = 1.0f / (kN * kN);
+      const float b0 = bias[chunk * 8 + c0], b1 = bias[chunk * 8 + c0 + 1];
+#pragma unroll
+      for (int x = 0; x < 32; ++x) {
+        if (x < D) {
+          float v0 = re[x] * kScale + b0, v1 = im[x] * kScale + b1;
+          if (res) {
+            const uint32_t two = *reinterpret_cast<const uint32_t *>(R + (y * D + x) * 8 + c0);
+            v0 += __uint_as_float(two << 16);
+            v1 += __uint_as_float(two & 0xffff0000u);
+          }
+          const bf16_t h0 = (bf16_t)(v0 > 0.0f ? v0 : 0.0f), h1 = (bf16_t)(v1 > 0.0f ? v1 : 0.0f);
+          if (out)
+            *reinterpret_cast<uint32_t *>(R + (y * D + x) * 8 + c0) =
+                (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+          re[x] = (float)h0;
+          im[x] = (float)h1;
+        } else {
+          re[x] = 0.0f;
+          im[x] = 0.0f;
+        }
+      }
+      fft32<false>(re, im);
+#pragma unroll
+      for (int k = 0; k < kNX; ++k) {
+        const int m = (32 - k) & 31;
+        *reinterpret_cast<float4 *>(T + (k * DP + y) * 8 + c0) = make_float4(
+            0.5f * (re[k] + re[m]), 0.5f * (im[k] - im[m]), 0.5f * (im[k] + im[m]), -0.5f * (re[k] - re[m]));
+      }
+    }
+  }
+  __syncthreads();
+  if (out)
+    for (int v = tid; v < D * D; v += 256)
+      *reinterpret_cast<uint4 *>(out + base + (int64_t)v * cout_store) = *reinterpret_cast<const uint4 *>(R + v * 8);
+  // forward columns along y (as k_fft_fwd2d)
+  float re[32], im[32];
+  const bool colw = tid < kNX * 8;
+  const int kx = tid >> 3, c = tid & 7;
+  if (colw) {
+#pragma unroll
+    for (int y = 0; y < 32; ++y) {
+      const float2 v = y < D ? T[(kx * DP + y) * 8 + c] : make_float2(0.0f, 0.0f);
+      re[y] = v.x;
+      im[y] = v.y;
+    }
+    fft32<false>(re, im);
+  }
+  __syncthreads();
+  uint32_t *O = reinterpret_cast<uint32_t *>(T);
+  if (colw) {
+    const bool odd = c & 1;
+#pragma unroll
+    for (int ky = 0; ky < 32; ++ky) {
+      const float mine = odd ? re[ky] : im[ky];
+      const float other = __shfl_xor(mine, 1);
+      const float lo = odd ? other : re[ky], hi = odd ? im[ky] : other;
+      const uint32_t packed = (uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)lo) |
+                              ((uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)hi) << 16);
+      O[(ky * kNX + kx) * 8 + (odd ? 4 : 0) + (c >> 1)] = packed;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kCols * 2; e += 256) {
+    const int col = e >> 1, h = e & 1;
+    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * 8) =
+        *reinterpret_cast<const uint4 *>(O + col * 8 + h * 4);
+  }
+}
+
 // ---------------------------------------------------------------- z-correlation
 
 // One (column, block of ppb poses): rows r = (pose pl, z), pl = r / D; the panel in
@@ -608,8 +761,13 @@ bool fft_conv_ok(const ConvLayer &L, int D) {
 
 int64_t fft_conv_gspec_bytes(const ConvLayer &L) { return (int64_t)kCols * nch_of(L) * L.k * nbt_of(L) * 1024; }
 
+// work buffer: the input spectrum rows at offset 0 (room for 8 chunks, the most a
+// layer takes), the output spectrum rows after them; fixed offsets, so that one
+// layer's output spectrum is where the next layer's fused transform finds it
+int64_t fft_spec_in_elems(int D, int np) { return (int64_t)kCols * np * D * 8 * 16; }
+
 int64_t fft_conv_work_bytes(const ConvLayer &L, int D, int np) {
-  return (int64_t)kCols * np * D * (nch_of(L) + L.cout / 8) * 32;
+  return (fft_spec_in_elems(D, np) + (int64_t)kCols * np * D * (L.cout / 8) * 16) * 2;
 }
 
 hipError_t fft_conv_prepare(ConvLayer &L, const float *w_folded_dev, hipStream_t s) {
@@ -634,12 +792,28 @@ void fft_conv_stage_cost(int stage, const ConvLayer &L, int D, int np, double *f
   }
 }
 
+bool fft_conv_fusable(const ConvLayer &L, const ConvLayer &Ln, int D) {
+  return fft_conv_ok(L, D) && fft_conv_ok(Ln, D) && L.cout == Ln.cin && Ln.cin_pad == L.cout_store;
+}
+
+hipError_t launch_fft_mid(const ConvLayer &L, const ConvLayer &Ln, const void *res, void *out, int np, int D,
+                          void *work, hipStream_t s) {
+  if (!fft_conv_fusable(L, Ln, D) || !work) return hipErrorInvalidValue;
+  const int nch = L.cout / 8;
+  bf16_t *xs = reinterpret_cast<bf16_t *>(work);
+  bf16_t *ys = xs + fft_spec_in_elems(D, np);
+  const size_t spec = fft_lds_bytes(D), lds = spec + ((res || out) ? (size_t)D * D * 16 : 0);
+  hipLaunchKernelGGL(k_fft_mid, dim3(D, np, nch), dim3(256), lds, s, ys, L.bias, reinterpret_cast<const bf16_t *>(res),
+                     reinterpret_cast<bf16_t *>(out), xs, np, D, nch, L.cout_store, (int)spec);
+  return hipGetLastError();
+}
+
 hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, void *out, int np, int D, void *work,
                            hipStream_t s, int stage) {
   if (!fft_conv_ok(L, D) || !work) return hipErrorInvalidValue;
   const int nch = nch_of(L), nco = L.cout / 8;
   bf16_t *xs = reinterpret_cast<bf16_t *>(work);
-  bf16_t *ys = xs + (int64_t)kCols * np * D * nch * 16;
+  bf16_t *ys = xs + fft_spec_in_elems(D, np);
   if (stage < 0 || stage == 0)
     hipLaunchKernelGGL(k_fft_fwd2d, dim3(D, np, nch), dim3(256), fft_lds_bytes(D), s,
                        reinterpret_cast<const bf16_t *>(in), xs, np, D, L.cin_pad, nch);

@@ -112,6 +112,13 @@ hipError_t fft_conv_prepare(ConvLayer &L, const float *w_folded_dev, hipStream_t
 // stage -1: the whole layer; 0, 1, 2: forward plane FFTs, z-correlation, inverse
 hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, void *out, int n_poses, int D,
                            void *work, hipStream_t s, int stage = -1);
+// two consecutive frequency-domain layers whose activation between them can stay
+// in the transform kernels; launch_fft_mid runs layer L's inverse (its spectrum in
+// the work buffer) and layer Ln's forward transform in one kernel, storing the
+// activation only when out != null
+bool fft_conv_fusable(const ConvLayer &L, const ConvLayer &Ln, int D);
+hipError_t launch_fft_mid(const ConvLayer &L, const ConvLayer &Ln, const void *res, void *out, int n_poses, int D,
+                          void *work, hipStream_t s);
 // algorithmic FLOP and HBM bytes of one stage for n_poses
 void fft_conv_stage_cost(int stage, const ConvLayer &L, int D, int n_poses, double *flop, double *bytes);
 bool conv_variant_is_fft(int v);
