@@ -645,27 +645,27 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv4Cf
     // addressing is recomputed per chunk rather than hoisted and held in registers
 #pragma unroll 1
     for (int it0 = 0; it0 < C::HITER; it0 += C::HB) {
-      uint2 hv[C::HB];
+      uint2 hv[C::HB];  // static indices only, so the batch stays in registers
 #pragma unroll
-      for (int it = it0; it < it0 + C::HB && it < C::HITER; ++it) {
-        const int v = it * NTH + (int)threadIdx.x;
-        hv[it - it0] = make_uint2(0, 0);
-        if (v < NV) {
+      for (int i = 0; i < C::HB; ++i) {
+        const int v = (it0 + i) * NTH + (int)threadIdx.x;
+        hv[i] = make_uint2(0, 0);
+        if (it0 + i < C::HITER && v < NV) {
           const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
           const int gz = oz + hz, gy = oy + hy, gx = ox + hx;
           if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gx < (unsigned)D)
-            hv[it - it0] = *reinterpret_cast<const uint2 *>(
+            hv[i] = *reinterpret_cast<const uint2 *>(
                 in + ((pose_in + ((int64_t)gz * D + gy) * D + gx) * cin_pad + chunk * 4));
         }
       }
 #pragma unroll
-      for (int it = it0; it < it0 + C::HB && it < C::HITER; ++it) {
-        const int v = it * NTH + (int)threadIdx.x;
-        if (v < NV) {
+      for (int i = 0; i < C::HB; ++i) {
+        const int v = (it0 + i) * NTH + (int)threadIdx.x;
+        if (it0 + i < C::HITER && v < NV) {
           const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
           const int off = stored_index(hz, C::HZ, S) * C::SLAB + stored_index(hy, C::HY, S) * C::ROW +
                           stored_index(hx, C::HX, S) * 8;
-          *reinterpret_cast<uint2 *>(halo + off) = hv[it - it0];
+          *reinterpret_cast<uint2 *>(halo + off) = hv[i];
         }
       }
     }

@@ -49,7 +49,8 @@ _CONV = re.compile(r"k_conv<([^,]+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (
 _PLAIN = re.compile(r"(?:cf::\(anonymous namespace\)::)?(k_\w+)")
 
 
-_MANGLED_CONV = re.compile(r"k_conv(8?)I(DF16b|f)?((?:Li\d+E)+)E")
+_MANGLED_CONV = re.compile(r"k_conv([48]?)I(DF16b|f)?((?:Li\d+E)+)E")
+_CONV4 = re.compile(r"k_conv4<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+)>")
 
 
 def _split(wn: int) -> str:
@@ -73,8 +74,12 @@ def short_name(name: str) -> str:
             ks, s, tz, ty, tx, nw, nt = v[:7]
             wn = v[7] if len(v) >= 8 else 1
             pp = v[8] if len(v) == 9 else 1
-            pre = "conv.p8" if p8 else ("conv.f32." if t == "f" else "conv.")
+            pre = {"8": "conv.p8", "4": "conv.q4"}.get(p8) or ("conv.f32." if t == "f" else "conv.")
             return f"{pre}k{ks}s{s}_t{tz}x{ty}x{tx}_w{nw}{_split(wn)}_n{nt}{_poses(pp)}"
+    m = _CONV4.search(name)
+    if m:
+        ks, s, tz, ty, tx, nw, nt = m.groups()
+        return f"conv.q4k{ks}s{s}_t{tz}x{ty}x{tx}_w{nw}_n{nt}"
     m = _CONV8.search(name)
     if m:
         ks, s, tz, ty, tx, nw, nt, wn, pp = m.groups()
