@@ -154,7 +154,9 @@ void tend(cf_ctx *c, hipStream_t s, hipEvent_t e0, const std::string &key, doubl
 }
 
 size_t elem_size(const cf_ctx *c) { return c->bf16 ? 2 : 4; }
-int grid_cpad(const cf_ctx *c) { return c->bf16 ? 32 : 24; }
+// internal grid: bf16 in 4-channel chunk-major layout (20 channels, read by the
+// tap-quad kernels), fp32 channels-last padded to 24
+int grid_cpad(const cf_ctx *c) { return c->bf16 ? 20 : 24; }
 
 // bytes per pose of the conv-stack tensors at grid size G
 int64_t pose_bytes(const cf_ctx *c, int G) {
@@ -605,6 +607,7 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     L.stride = st;
     L.res_src = rs;
     L.cin_pad = cin_pad;
+    L.in_cm4 = (i == 0 && c->bf16) ? 1 : 0;
     L.cout_pad32 = (co + 31) / 32 * 32;
     L.cout_store = c->bf16 ? (co + 15) / 16 * 16 : (co + 7) / 8 * 8;
     std::vector<float> bf(L.cout_pad32, 0.0f);
@@ -918,7 +921,8 @@ int cf_cnn3d_fwd(cf_ctx *c, const void *grid, int32_t n_poses, int G, float *cnn
   for (int p0 = 0; p0 < n_poses; p0 += chunk) {
     const int np = std::min(chunk, n_poses - p0);
     const char *src = reinterpret_cast<const char *>(grid) + (size_t)p0 * vox * CF_NCH * elem_size(c);
-    CF_HIP(cf::launch_grid_repack(src, c->bf16, (int)(np * vox), c->grid.p, c->bf16, grid_cpad(c), s));
+    CF_HIP(cf::launch_grid_repack(src, c->bf16, (int)(np * vox), c->grid.p, c->bf16, grid_cpad(c), s,
+                                  c->bf16 ? (int64_t)vox : 0));
     if ((rc = run_cnn(c, G, np, cnn_latent + (size_t)p0 * c->lc, s))) return rc;
   }
   return CF_OK;
@@ -987,7 +991,7 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
       cen = (const int32_t *)c->centers.p;
     }
     hipEvent_t e = tbegin(c, s);
-    CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, p0, np, G, c->grid.p, c->bf16 ? 3 : 2,
+    CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, p0, np, G, c->grid.p, c->bf16 ? 4 : 2,
                             grid_cpad(c), c->status, s));
     tend(c, s, e, "splat", 0.0, atoms * (12.0 + 4.0 * CF_NCH) + (double)np * G * G * G * CF_NCH * elem_size(c));
     if ((rc = run_cnn(c, G, np, (float *)c->cnn_lat.p, s, c->ev_fork))) return rc;

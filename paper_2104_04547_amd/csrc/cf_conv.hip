@@ -595,7 +595,7 @@ template <int KS, int S, int TZ, int TY, int TX, int NW, int NT>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv4Cfg<KS, S, TZ, TY, TX, NW, NT>::WPE))) void k_conv4(
     const bf16_t *__restrict__ in, const bf16_t *__restrict__ wpk, const float *__restrict__ bias,
     const bf16_t *__restrict__ res, bf16_t *__restrict__ out, int D, int Do, int cin_pad, int nchunks, int cout_pad32,
-    int cout_store, int nty, int ntx, int wbytes) {
+    int cout_store, int nty, int ntx, int wbytes, int chunk_major) {
   using C = Conv4Cfg<KS, S, TZ, TY, TX, NW, NT>;
   __shared__ __attribute__((aligned(16))) char lds[C::LDS];
   int *tab = reinterpret_cast<int *>(lds);  // [QUADS * 4] tap offsets into the halo
@@ -655,7 +655,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv4Cf
           const int gz = oz + hz, gy = oy + hy, gx = ox + hx;
           if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gx < (unsigned)D)
             hv[i] = *reinterpret_cast<const uint2 *>(
-                in + ((pose_in + ((int64_t)gz * D + gy) * D + gx) * cin_pad + chunk * 4));
+                chunk_major
+                    ? in + ((((int64_t)pose * nchunks + chunk) * D + gz) * D + gy) * D * 4 + (int64_t)gx * 4
+                    : in + ((pose_in + ((int64_t)gz * D + gy) * D + gx) * cin_pad + chunk * 4));
         }
       }
 #pragma unroll
@@ -779,7 +781,7 @@ hipError_t launch_q(const ConvLayer &L, const void *in, const void *res, void *o
   hipLaunchKernelGGL((k_conv4<KS, S, TZ, TY, TX, NW, NT>), grid, dim3(NW * 64), 0, s,
                      reinterpret_cast<const bf16_t *>(in), reinterpret_cast<const bf16_t *>(L.wpk4), L.bias,
                      reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), D, Do, L.cin_pad,
-                     (L.cin + 3) / 4, L.cout_pad32, L.cout_store, nty, ntx, (int)L.wbytes4);
+                     (L.cin + 3) / 4, L.cout_pad32, L.cout_store, nty, ntx, (int)L.wbytes4, L.in_cm4);
   return hipGetLastError();
 }
 
@@ -897,7 +899,10 @@ const Variant kVariants[] = {
     // 4-channel tap quads for the 19-channel grid
     CF_VARIANT4(7, 2, 8, 8, 8, 4, 64),   // 41: 21^3 halo at 8 bytes per voxel, two workgroups per CU
     CF_VARIANT4(5, 2, 8, 8, 8, 4, 32),   // 42
-    CF_VARIANT4(5, 1, 8, 8, 8, 4, 32)    // 43
+    CF_VARIANT4(5, 1, 8, 8, 8, 4, 32),   // 43
+    CF_VARIANT4(7, 1, 8, 8, 8, 4, 32),   // 44  (the bf16 grid is read by tap-quad kernels only: one per
+    CF_VARIANT4(3, 1, 8, 8, 8, 4, 32),   // 45   first-layer shape)
+    CF_VARIANT4(3, 2, 8, 8, 8, 4, 32)    // 46
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -927,7 +932,7 @@ int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
   // for the 128-column stride-2 layer (two poses per workgroup); fp32 has neither
   if (bf16 && L.k == 7 && conv_variant_ok(kFftVariant, L, bf16, D_in)) return kFftVariant;
   const int pref[] = {12, 40, 41, 17, 20, 19, 23, 26, 28, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18,
-                      21, 22, 24, 25, 27, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39, 42, 43};
+                      21, 22, 24, 25, 27, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39, 42, 43, 44, 45, 46};
   for (int v : pref)
     if (conv_variant_ok(v, L, bf16, D_in)) return v;
   return -1;

@@ -74,6 +74,7 @@ struct ConvLayer {
   int64_t wbytes8;
   void *wpk4;      // bf16, input channels not a multiple of 8: weights packed for the tap-quad kernel
   int64_t wbytes4;
+  int in_cm4;      // the input is the bf16 grid in 4-channel chunk-major layout [P][cin_pad / 4][D^3][4]
   float *bias;     // folded bias [cout_pad32]
   void *gspec;     // bf16 stride-1 layers: in-plane spectra of the weights (frequency-domain path)
   int64_t gspec_bytes;
@@ -82,12 +83,14 @@ struct ConvLayer {
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_centers(const int32_t *atom_off, int n_atoms, const int32_t *xyz, const uint8_t *is_lig,
                           int p0, int n_poses, int32_t *center_out, int64_t *status, hipStream_t s);
-// out_mode: 0 = float [19], 1 = bf16 [19], 2 = float padded [cpad], 3 = bf16 padded [cpad]
+// out_mode: 0 = float [19], 1 = bf16 [19], 2 = float padded [cpad], 3 = bf16 padded [cpad],
+// 4 = bf16 4-channel chunk-major [P][cpad / 4][G^3][4]
 hipError_t launch_splat(const int32_t *atom_off, int n_atoms, const int32_t *xyz, const float *feat,
                         const int32_t *centers, int p0, int n_poses, int G, void *grid, int out_mode,
                         int cpad, int64_t *status, hipStream_t s);
+// chunk4_vpp > 0: bf16 4-channel chunk-major output with that many voxels per pose
 hipError_t launch_grid_repack(const void *src, int src_bf16, int n_vox, void *dst, int dst_bf16,
-                              int cpad, hipStream_t s);
+                              int cpad, hipStream_t s, int64_t chunk4_vpp = 0);
 
 hipError_t launch_graph(const int32_t *atom_off, int n_atoms, const int32_t *xyz, int p0, int n_poses, int r_cov,
                         int r_nc, int32_t *cov_row, int32_t *cov_col, int64_t cov_cap, int32_t *nc_row,

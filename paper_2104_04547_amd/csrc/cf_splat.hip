@@ -72,7 +72,8 @@ __global__ __launch_bounds__(64) void k_centers(const int32_t *__restrict__ atom
   }
 }
 
-// MODE 0: float [19]; 1: bf16 [19]; 2: float [cpad]; 3: bf16 [cpad] (channels >= 19 zero)
+// MODE 0: float [19]; 1: bf16 [19]; 2: float [cpad]; 3: bf16 [cpad] (channels >= 19 zero);
+// 4: bf16 in 4-channel chunks, chunk-major per pose: [P][cpad / 4][G^3][4]
 template <int MODE>
 __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_off, int n_atoms,
                                                const int32_t *__restrict__ xyz,
@@ -159,6 +160,27 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
       else
         reinterpret_cast<bf16_t *>(grid)[gv * CF_NCH + ch] = (bf16_t)val;
     }
+  } else if (MODE == 4) {
+    // chunk slowest, voxel fastest: consecutive threads write consecutive 8-byte voxels
+    const int ng = cpad / 4;
+    const int64_t g3 = (int64_t)G * G * G;
+    for (int e = threadIdx.x; e < nvox * ng; e += blockDim.x) {
+      const int g = e / nvox, v = e - g * nvox;
+      const int k = v % G, jj = (v / G) % kTB, ii = v / (G * kTB);
+      const int64_t vloc = ((int64_t)(i0 + ii) * G + (j0 + jj)) * G + k;
+      float val[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ch = g * 4 + q;
+        val[q] = ch < CF_NCH ? (float)acc[v * CF_NCH + ch] * kSplatInvScale : 0.0f;
+      }
+      const uint32_t lo = (uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)val[0]) |
+                          ((uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)val[1]) << 16);
+      const uint32_t hi = (uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)val[2]) |
+                          ((uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)val[3]) << 16);
+      *reinterpret_cast<uint2 *>(reinterpret_cast<bf16_t *>(grid) + (((int64_t)pl * ng + g) * g3 + vloc) * 4) =
+          make_uint2(lo, hi);
+    }
   } else {
     const int ng = cpad / 8;
     for (int e = threadIdx.x; e < nvox * ng; e += blockDim.x) {
@@ -185,8 +207,35 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
   }
 }
 
-// Public [19]-channel grid -> internal padded [cpad] grid (conversion between
-// precisions allowed).
+// Public [19]-channel grid -> the internal layout (conversion between precisions
+// allowed): padded [cpad] channels-last, or with chunk4 = voxels per pose the bf16
+// 4-channel chunk-major layout [P][cpad / 4][G^3][4].
+__global__ __launch_bounds__(256) void k_grid_repack4(const void *__restrict__ src, int src_bf16, int64_t n_vox,
+                                                      bf16_t *__restrict__ dst, int cpad, int64_t vpp) {
+  const int ng = cpad / 4;
+  const int64_t total = n_vox * ng;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    // (pose, chunk, voxel) with the voxel fastest
+    const int64_t pose = e / (vpp * ng), r = e - pose * vpp * ng;
+    const int g = (int)(r / vpp);
+    const int64_t v = pose * vpp + (r - (int64_t)g * vpp);
+    bf16_t val[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = g * 4 + q;
+      float f = 0.0f;
+      if (ch < CF_NCH)
+        f = src_bf16 ? (float)reinterpret_cast<const bf16_t *>(src)[v * CF_NCH + ch]
+                     : reinterpret_cast<const float *>(src)[v * CF_NCH + ch];
+      val[q] = (bf16_t)f;
+    }
+    uint2 o;
+    __builtin_memcpy(&o, val, 8);
+    *reinterpret_cast<uint2 *>(dst + e * 4) = o;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_grid_repack(const void *__restrict__ src, int src_bf16,
                                                      int64_t n_vox, void *__restrict__ dst,
                                                      int dst_bf16, int cpad) {
@@ -240,13 +289,21 @@ hipError_t launch_splat(const int32_t *atom_off, int n_atoms, const int32_t *xyz
     case 1: hipLaunchKernelGGL(k_splat<1>, grd, dim3(256), lds, s, atom_off, n_atoms, xyz, feat, centers, p0, G, grid, cpad, status); break;
     case 2: hipLaunchKernelGGL(k_splat<2>, grd, dim3(256), lds, s, atom_off, n_atoms, xyz, feat, centers, p0, G, grid, cpad, status); break;
     case 3: hipLaunchKernelGGL(k_splat<3>, grd, dim3(256), lds, s, atom_off, n_atoms, xyz, feat, centers, p0, G, grid, cpad, status); break;
+    case 4: hipLaunchKernelGGL(k_splat<4>, grd, dim3(256), lds, s, atom_off, n_atoms, xyz, feat, centers, p0, G, grid, cpad, status); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_grid_repack(const void *src, int src_bf16, int n_vox, void *dst, int dst_bf16,
-                              int cpad, hipStream_t s) {
+                              int cpad, hipStream_t s, int64_t chunk4_vpp) {
+  if (chunk4_vpp > 0) {
+    const int64_t total = (int64_t)n_vox * (cpad / 4);
+    const int blocks = (int)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+    hipLaunchKernelGGL(k_grid_repack4, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, src, src_bf16,
+                       (int64_t)n_vox, reinterpret_cast<bf16_t *>(dst), cpad, chunk4_vpp);
+    return hipGetLastError();
+  }
   const int64_t total = (int64_t)n_vox * (cpad / 8);
   const int blocks = (int)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
   hipLaunchKernelGGL(k_grid_repack, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, src, src_bf16,
