@@ -46,8 +46,10 @@ constexpr int kPanelRows = 288;                                // LDS rows of on
 // One workgroup per (z, pose, chunk), grid (D, np, nch) in XCD order: the chunks
 // of one plane run under one L2, where their 32-byte pieces of each spectrum row
 // (and of each input voxel) meet.  in: [P][D][D][D][cin_pad] bf16.
+template <int DT>
 __global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in, bf16_t *__restrict__ xs, int np,
-                                                   int D, int cin_pad, int nch) {
+                                                   int D_rt, int cin_pad, int nch) {
+  const int D = DT ? DT : D_rt;
   int chunk, z, p;
   xcd_order(z, p, chunk);
   // one dynamic LDS block (fft_lds_bytes): the plane, then (after its rows are in
@@ -132,9 +134,11 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in
 
 // One workgroup per (z, pose, output chunk), grid (D, np, nco) in XCD order.
 // out, res: [P][D][D][D][cout_store] bf16.
+template <int DT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_inv2d(const bf16_t *__restrict__ ys, const float *__restrict__ bias,
                                                    const bf16_t *__restrict__ res, bf16_t *__restrict__ out, int np,
-                                                   int D, int nco, int cout_store) {
+                                                   int D_rt, int nco, int cout_store) {
+  const int D = DT ? DT : D_rt;
   int chunk, z, p;
   xcd_order(z, p, chunk);
   // one dynamic LDS block (fft_lds_bytes): the spectrum, then (after its columns
@@ -241,9 +245,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // chunking of layer i + 1's input.  LDS: the spectrum / column transforms
 // (fft_lds_bytes) and, with a residual or a stored output, the activation plane
 // [y][x][8] bf16.
+template <int DT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_mid(
     const bf16_t *__restrict__ ys, const float *__restrict__ bias, const bf16_t *__restrict__ res,
-    bf16_t *__restrict__ out, bf16_t *__restrict__ xs, int np, int D, int nch, int cout_store, int lds_spec) {
+    bf16_t *__restrict__ out, bf16_t *__restrict__ xs, int np, int D_rt, int nch, int cout_store, int lds_spec) {
+  const int D = DT ? DT : D_rt;
   int chunk, z, p;
   xcd_order(z, p, chunk);
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
@@ -803,8 +809,12 @@ hipError_t launch_fft_mid(const ConvLayer &L, const ConvLayer &Ln, const void *r
   bf16_t *xs = reinterpret_cast<bf16_t *>(work);
   bf16_t *ys = xs + fft_spec_in_elems(D, np);
   const size_t spec = fft_lds_bytes(D), lds = spec + ((res || out) ? (size_t)D * D * 16 : 0);
-  hipLaunchKernelGGL(k_fft_mid, dim3(D, np, nch), dim3(256), lds, s, ys, L.bias, reinterpret_cast<const bf16_t *>(res),
-                     reinterpret_cast<bf16_t *>(out), xs, np, D, nch, L.cout_store, (int)spec);
+#define CF_MID(DT)                                                                                            \
+  hipLaunchKernelGGL(k_fft_mid<DT>, dim3(D, np, nch), dim3(256), lds, s, ys, L.bias,                           \
+                     reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), xs, np, D, nch, \
+                     L.cout_store, (int)spec)
+  if (D == 24) CF_MID(24); else if (D == 12) CF_MID(12); else CF_MID(0);
+#undef CF_MID
   return hipGetLastError();
 }
 
@@ -814,9 +824,13 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
   const int nch = nch_of(L), nco = L.cout / 8;
   bf16_t *xs = reinterpret_cast<bf16_t *>(work);
   bf16_t *ys = xs + fft_spec_in_elems(D, np);
-  if (stage < 0 || stage == 0)
-    hipLaunchKernelGGL(k_fft_fwd2d, dim3(D, np, nch), dim3(256), fft_lds_bytes(D), s,
-                       reinterpret_cast<const bf16_t *>(in), xs, np, D, L.cin_pad, nch);
+  if (stage < 0 || stage == 0) {
+#define CF_FWD(DT)                                                                                 \
+  hipLaunchKernelGGL(k_fft_fwd2d<DT>, dim3(D, np, nch), dim3(256), fft_lds_bytes(D), s,             \
+                     reinterpret_cast<const bf16_t *>(in), xs, np, D, L.cin_pad, nch)
+    if (D == 24) CF_FWD(24); else if (D == 12) CF_FWD(12); else CF_FWD(0);
+#undef CF_FWD
+  }
   if ((stage < 0 || stage == 1) && L.cout == 64 && (kRowsZH / D) * (D + L.k - 1) <= kPanelRowsH) {
     const int ppb = kRowsZH / D;
     const dim3 zg((np + ppb - 1) / ppb, kCols, 1);
@@ -845,10 +859,14 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
     }
 #undef CF_ZCONV
   }
-  if (stage < 0 || stage == 2)
-    hipLaunchKernelGGL(k_fft_inv2d, dim3(D, np, nco), dim3(256), fft_lds_bytes(D), s, ys, L.bias,
-                       reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), np, D, nco,
-                       L.cout_store);
+  if (stage < 0 || stage == 2) {
+#define CF_INV(DT)                                                                                        \
+  hipLaunchKernelGGL(k_fft_inv2d<DT>, dim3(D, np, nco), dim3(256), fft_lds_bytes(D), s, ys, L.bias,        \
+                     reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), np, D, nco, \
+                     L.cout_store)
+    if (D == 24) CF_INV(24); else if (D == 12) CF_INV(12); else CF_INV(0);
+#undef CF_INV
+  }
   return hipGetLastError();
 }
 
