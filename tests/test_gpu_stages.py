@@ -160,6 +160,33 @@ def test_graphs_ties_at_the_cutoff(scorers):
     assert np.array_equal(nr, wr) and np.array_equal(ncol, wc)
 
 
+def test_graphs_large_and_wide_poses(scorers):
+    """A pose of more atoms than one j tile (1024) of the all-pairs sweep, a pose
+    spanning more than 2^31 units on x (64-bit difference path) and a lone atom."""
+    _say("cf_build_graphs 1500-atom pose, 2^31-wide pose, 1-atom pose")
+    rng = np.random.default_rng(5)
+    big = rng.integers(-16 * 1024, 16 * 1024, size=(1500, 3)).astype(np.int32)  # 32 A box
+    wide = rng.integers(-3 * 1024, 3 * 1024, size=(60, 3)).astype(np.int64)
+    wide[:30, 0] -= 1_100_000_000
+    wide[30:, 0] += 1_100_000_000
+    wide = wide.astype(np.int32)
+    lone = np.array([[7, 8, 9]], np.int32)
+    x = np.concatenate([big, wide, lone])
+    off = np.array([0, 1500, 1560, 1561], np.int32)
+    b = synth.PoseBatch(off, x, np.zeros((len(x), 19), np.float32), np.zeros(len(x), np.uint8),
+                        np.array([0, 0, 0], np.int32))
+    arch = synth.ARCHS["full"]
+    s = scorers[("full", "fp32")]
+    t = s.build_graphs(_db(b), cov_capacity=400_000, nc_capacity=2_000_000)
+    rc, _, _ = s.status()
+    assert rc == 0
+    (cr, cc), (nr, ncol) = _csr_host(t, len(x))
+    wr, wc = oracle.radius_graph_batch(b, arch.r_cov_u)
+    assert np.array_equal(cr, wr) and np.array_equal(cc, wc)
+    wr, wc = oracle.radius_graph_batch(b, arch.r_nc_u)
+    assert np.array_equal(nr, wr) and np.array_equal(ncol, wc)
+
+
 def test_graphs_capacity_overflow_reports_needed_counts(scorers):
     _say("cf_build_graphs capacity overflow")
     from paper_2104_04547_amd import cfabi
