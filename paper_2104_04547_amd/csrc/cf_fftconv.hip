@@ -37,6 +37,161 @@ constexpr int kDMax = 30;                                      // D + k - 1 <= 3
 constexpr int kRowsZ = 192;                                    // (pose, z) rows per z-correlation block
 constexpr int kPanelRows = 288;                                // LDS rows of one block incl. z halo
 
+// ---------------------------------------------------------------- plane transforms
+
+// Thread roles in the plane kernels (256 threads): the column transforms along
+// ky / y run on threads 0 .. 127 (waves 0 and 1), one (kxp, channel) each with
+// kxp = tid >> 3; the row transforms along x run on threads 128 .. 128 + 4 D - 1
+// (waves 2 and 3), two channels of one y each.  The phases alternate, so two
+// workgroups on one CU keep all four SIMDs busy.
+//
+// Columns: kxp 1 .. 15 is the complex column kx = kxp; kxp 0 carries the DC and
+// Nyquist columns (kx 0 and 16) together.  Along y both are real sequences (the
+// row transform of real data is real at kx 0 and 16), so they travel as the real
+// and imaginary parts of one complex column t0 + i t16, which the row kernels
+// read and write in place of column 0 (column 16 of T stays unused).  Forward:
+// Z = FFT(t0 + i t16), X0[k] = (Z[k] + conj Z[-k]) / 2, X16[k] = (Z[k] - conj
+// Z[-k]) / 2i, split by all threads from Z staged in fp32 (Zp).  Inverse: all
+// threads first form Zp = H(Y0) + i H(Y16) from the spectrum, H the Hermitian part
+// (H(Y)[k] = (Y[k] + conj Y[-k]) / 2); its inverse is Re IFFT(Y0) + i Re IFFT(Y16),
+// the real parts that the row transform takes.
+constexpr int kColThreads = 128;
+
+// LDS of the plane kernels: the plane region (the larger of the row spectra
+// [17][D + 1][8] complex and the bf16 spectrum of a plane), then Zp [32][8] complex
+__host__ __device__ constexpr int plane_lds_bytes(int D) {
+  return kNX * (D + 1) * 8 * 8 > kCols * 16 * 2 ? kNX * (D + 1) * 8 * 8 : kCols * 16 * 2;
+}
+constexpr int kZpBytes = 32 * 8 * 8;
+
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)lo) | ((uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)hi) << 16);
+}
+
+// One complex value of channel c from a spectrum row [col][re | im][8] bf16: lane
+// pairs (c, c ^ 1) read two channels at once (even lanes the re pair, odd lanes
+// the im pair) and swap halves.  Both lanes of a pair must be active.
+__device__ inline void spec_get(const uint32_t *Yw, int col, int c, float &r, float &i) {
+  const bool odd = c & 1;
+  const uint32_t two = Yw[col * 8 + (odd ? 4 : 0) + (c >> 1)];
+  const float lo = __uint_as_float(two << 16), hi = __uint_as_float(two & 0xffff0000u);
+  const float other = __shfl_xor(odd ? lo : hi, 1);
+  r = odd ? other : lo;
+  i = odd ? hi : other;
+}
+
+// The inverse of spec_get: lane pairs swap halves so that each lane stores two
+// channels as one 32-bit word, rounded to bf16.
+__device__ inline void spec_put(uint32_t *O, int col, int c, float r, float i) {
+  const bool odd = c & 1;
+  const float other = __shfl_xor(odd ? r : i, 1);
+  O[col * 8 + (odd ? 4 : 0) + (c >> 1)] = pack_bf16x2(odd ? other : r, odd ? i : other);
+}
+
+// inverse, all 256 threads (ky = tid >> 3, c = tid & 7): Zp[ky][c] = H(Y0)[ky] + i H(Y16)[ky]
+__device__ inline void dc_nyquist_pack(const bf16_t *Y, float2 *Zp, int tid) {
+  const uint32_t *Yw = reinterpret_cast<const uint32_t *>(Y);
+  const int ky = tid >> 3, c = tid & 7, m = (32 - ky) & 31;
+  float ar, ai, br, bi, cr, ci, dr, di;
+  spec_get(Yw, ky * kNX, c, ar, ai);               // Y0[ky]
+  spec_get(Yw, m * kNX, c, br, bi);                // Y0[-ky]
+  spec_get(Yw, ky * kNX + kNX - 1, c, cr, ci);     // Y16[ky]
+  spec_get(Yw, m * kNX + kNX - 1, c, dr, di);      // Y16[-ky]
+  const float h0r = 0.5f * (ar + br), h0i = 0.5f * (ai - bi);
+  const float h1r = 0.5f * (cr + dr), h1i = 0.5f * (ci - di);
+  Zp[ky * 8 + c] = make_float2(h0r - h1i, h0i + h1r);
+}
+
+// forward, all 256 threads: X0 and X16 at ky from Zp (the transform of t0 + i t16)
+__device__ inline void dc_nyquist_split(const float2 *Zp, uint32_t *O, int tid) {
+  const int ky = tid >> 3, c = tid & 7, m = (32 - ky) & 31;
+  const float2 a = Zp[ky * 8 + c], b = Zp[m * 8 + c];
+  spec_put(O, ky * kNX, c, 0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+  spec_put(O, ky * kNX + kNX - 1, c, 0.5f * (a.y + b.y), -0.5f * (a.x - b.x));
+}
+
+// inverse columns, step 1 (before the barrier that frees the spectrum): columns 1 .. 15
+__device__ inline void col_inv_load(const bf16_t *Y, int kxp, int c, float (&re)[32], float (&im)[32]) {
+  const uint32_t *Yw = reinterpret_cast<const uint32_t *>(Y);
+#pragma unroll
+  for (int ky = 0; ky < 32; ++ky) spec_get(Yw, ky * kNX + kxp, c, re[ky], im[ky]);
+}
+
+// inverse columns, step 2 (after it): the packed column from Zp
+__device__ inline void col_inv_load_dc(const float2 *Zp, int c, float (&re)[32], float (&im)[32]) {
+#pragma unroll
+  for (int ky = 0; ky < 32; ++ky) {
+    const float2 v = Zp[ky * 8 + c];
+    re[ky] = v.x;
+    im[ky] = v.y;
+  }
+}
+
+// inverse columns, after fft32<true>: rows y < D of T = [kx][y (pitch D + 1)][8] complex
+__device__ inline void col_inv_store(float2 *T, int kxp, int c, int D, const float (&re)[32], const float (&im)[32]) {
+  const int DP = D + 1;
+#pragma unroll
+  for (int y = 0; y < kDMax; ++y)
+    if (y < D) T[(kxp * DP + y) * 8 + c] = make_float2(re[y], im[y]);
+}
+
+// forward columns: column kxp of T into registers, zero-padded to 32
+__device__ inline void col_fwd_load(const float2 *T, int kxp, int c, int D, float (&re)[32], float (&im)[32]) {
+  const int DP = D + 1;
+#pragma unroll
+  for (int y = 0; y < 32; ++y) {
+    const float2 v = y < D ? T[(kxp * DP + y) * 8 + c] : make_float2(0.0f, 0.0f);
+    re[y] = v.x;
+    im[y] = v.y;
+  }
+}
+
+// forward columns, after fft32<false>: the spectrum column into O = [col][re | im][8]
+// bf16, or the packed column into Zp
+__device__ inline void col_fwd_store(uint32_t *O, float2 *Zp, int kxp, int c, const float (&re)[32],
+                                     const float (&im)[32]) {
+  if (kxp) {
+#pragma unroll
+    for (int ky = 0; ky < 32; ++ky) spec_put(O, ky * kNX + kxp, c, re[ky], im[ky]);
+  } else {
+#pragma unroll
+    for (int ky = 0; ky < 32; ++ky) Zp[ky * 8 + c] = make_float2(re[ky], im[ky]);
+  }
+}
+
+// rows, forward: the row spectra of two real channels from one complex transform
+// z = a + i b: A[k] = (Z[k] + conj Z[-k]) / 2, B[k] = (Z[k] - conj Z[-k]) / 2i for
+// k = 1 .. 15; at k = 0 the packed column (A0 + i A16, B0 + i B16), all four real
+__device__ inline void row_fwd_store(float2 *T, int y, int c0, int D, const float (&re)[32], const float (&im)[32]) {
+  const int DP = D + 1;
+  *reinterpret_cast<float4 *>(T + y * 8 + c0) = make_float4(re[0], re[16], im[0], im[16]);
+#pragma unroll
+  for (int k = 1; k < kNX - 1; ++k) {
+    const int m = 32 - k;
+    *reinterpret_cast<float4 *>(T + (k * DP + y) * 8 + c0) = make_float4(
+        0.5f * (re[k] + re[m]), 0.5f * (im[k] - im[m]), 0.5f * (im[k] + im[m]), -0.5f * (re[k] - re[m]));
+  }
+}
+
+// rows, inverse: the Hermitian halves of two channels into one complex sequence
+// A + i B; DC and Nyquist (real) come from the packed column
+__device__ inline void row_inv_load(const float2 *T, int y, int c0, int D, float (&re)[32], float (&im)[32]) {
+  const int DP = D + 1;
+  const float4 dc = *reinterpret_cast<const float4 *>(T + y * 8 + c0);  // A0, A16, B0, B16
+  re[0] = dc.x;
+  im[0] = dc.z;
+  re[16] = dc.y;
+  im[16] = dc.w;
+#pragma unroll
+  for (int k = 1; k < kNX - 1; ++k) {
+    const float4 ab = *reinterpret_cast<const float4 *>(T + (k * DP + y) * 8 + c0);
+    re[k] = ab.x - ab.w;
+    im[k] = ab.y + ab.z;
+    re[32 - k] = ab.x + ab.w;
+    im[32 - k] = ab.z - ab.y;
+  }
+}
+
 // ---------------------------------------------------------------- forward
 
 // LDS layouts are padded so that the lanes of one access hit distinct banks:
@@ -66,8 +221,9 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in
   __syncthreads();
   // rows along x, two channels per complex transform
   {
-    const bool roww = tid < D * 4;
-    const int y = tid >> 2, c0 = (tid & 3) * 2;
+    const int r = tid - kColThreads;
+    const bool roww = r >= 0 && r < D * 4;
+    const int y = r >> 2, c0 = (r & 3) * 2;
     float re[32], im[32];
 #pragma unroll
     for (int x = 0; x < 32; ++x) {
@@ -83,44 +239,24 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in
     __syncthreads();  // the plane is in registers; its LDS becomes the row spectra
     if (roww) {
       fft32<false>(re, im);
-#pragma unroll
-      for (int k = 0; k < kNX; ++k) {
-        const int m = (32 - k) & 31;
-        *reinterpret_cast<float4 *>(T + (k * DP + y) * 8 + c0) = make_float4(
-            0.5f * (re[k] + re[m]), 0.5f * (im[k] - im[m]), 0.5f * (im[k] + im[m]), -0.5f * (re[k] - re[m]));
-      }
+      row_fwd_store(T, y, c0, D, re, im);
     }
   }
   __syncthreads();
-  // columns along y, one channel per transform
+  // columns along y
   float re[32], im[32];
-  const bool colw = tid < kNX * 8;
-  const int kx = tid >> 3, c = tid & 7;
+  const bool colw = tid < kColThreads;
+  const int kxp = tid >> 3, c = tid & 7;
   if (colw) {
-#pragma unroll
-    for (int y = 0; y < 32; ++y) {
-      const float2 v = y < D ? T[(kx * DP + y) * 8 + c] : make_float2(0.0f, 0.0f);
-      re[y] = v.x;
-      im[y] = v.y;
-    }
+    col_fwd_load(T, kxp, c, D, re, im);
     fft32<false>(re, im);
   }
   __syncthreads();
-  // [col][re | im][8]: lane pairs (c, c ^ 1) swap halves so that each lane
-  // stores two channels at once (even lanes the re pair, odd lanes the im pair)
-  uint32_t *O = reinterpret_cast<uint32_t *>(T);
-  if (colw) {
-    const bool odd = c & 1;
-#pragma unroll
-    for (int ky = 0; ky < 32; ++ky) {
-      const float mine = odd ? re[ky] : im[ky];       // what the partner needs
-      const float other = __shfl_xor(mine, 1);
-      const float lo = odd ? other : re[ky], hi = odd ? im[ky] : other;  // channels c & ~1, c | 1
-      const uint32_t packed = (uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)lo) |
-                              ((uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)hi) << 16);
-      O[(ky * kNX + kx) * 8 + (odd ? 4 : 0) + (c >> 1)] = packed;
-    }
-  }
+  uint32_t *O = reinterpret_cast<uint32_t *>(T);  // [col][re | im][8]
+  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D));
+  if (colw) col_fwd_store(O, Zp, kxp, c, re, im);
+  __syncthreads();
+  dc_nyquist_split(Zp, O, tid);
   __syncthreads();
   const int64_t rowb = (int64_t)nch * 16;  // bf16 elements per (col, pose, z) row
   for (int e = tid; e < kCols * 2; e += 256) {
@@ -255,8 +391,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
   bf16_t *Y = reinterpret_cast<bf16_t *>(dyn_lds);                 // [col][re | im][8]
   float2 *T = reinterpret_cast<float2 *>(dyn_lds);                 // [kx][y][8]
+  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D));  // [32][8] packed DC / Nyquist column
   bf16_t *R = reinterpret_cast<bf16_t *>(dyn_lds + lds_spec);      // [y][x][8]: residual in, activation out
-  const int tid = threadIdx.x, DP = D + 1;
+  const int tid = threadIdx.x;
   const int64_t rowb = (int64_t)nch * 16;
   const int64_t base = (((int64_t)p * D + z) * D * D) * cout_store + chunk * 8;
   for (int e = tid; e < kCols * 2; e += 256) {
@@ -268,55 +405,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int v = tid; v < D * D; v += 256)
       *reinterpret_cast<uint4 *>(R + v * 8) = *reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store);
   __syncthreads();
+  const bool colw = tid < kColThreads;
+  const int kxp = tid >> 3, c = tid & 7;
   // inverse columns along ky (as k_fft_inv2d)
   {
-    const bool colw = tid < kNX * 8;
-    const int kx = tid >> 3, c = tid & 7;
-    const bool odd = c & 1;
-    const uint32_t *Yw = reinterpret_cast<const uint32_t *>(Y);
     float re[32], im[32];
-    if (colw) {
-#pragma unroll
-      for (int ky = 0; ky < 32; ++ky) {
-        const uint32_t two = Yw[(ky * kNX + kx) * 8 + (odd ? 4 : 0) + (c >> 1)];
-        const float lo = __uint_as_float(two << 16), hi = __uint_as_float(two & 0xffff0000u);
-        const float other = __shfl_xor(odd ? lo : hi, 1);
-        re[ky] = odd ? other : lo;
-        im[ky] = odd ? hi : other;
-      }
-    }
+    dc_nyquist_pack(Y, Zp, tid);
+    if (colw && kxp) col_inv_load(Y, kxp, c, re, im);
     __syncthreads();
     if (colw) {
+      if (!kxp) col_inv_load_dc(Zp, c, re, im);
       fft32<true>(re, im);
-#pragma unroll
-      for (int y = 0; y < kDMax; ++y)
-        if (y < D) T[(kx * DP + y) * 8 + c] = make_float2(re[y], im[y]);
+      col_inv_store(T, kxp, c, D, re, im);
     }
   }
   __syncthreads();
   // rows along x: inverse of two channels, epilogue, bf16, then their forward
   // transform (the next layer's input rows)
   {
-    const bool roww = tid < D * 4;
-    const int y = tid >> 2, c0 = (tid & 3) * 2;
+    const int r = tid - kColThreads;
+    const bool roww = r >= 0 && r < D * 4;
+    const int y = r >> 2, c0 = (r & 3) * 2;
     float re[32], im[32];
-    if (roww) {
-#pragma unroll
-      for (int k = 0; k < kNX; ++k) {
-        const float4 ab = *reinterpret_cast<const float4 *>(T + (k * DP + y) * 8 + c0);
-        float2 a = make_float2(ab.x, ab.y), b = make_float2(ab.z, ab.w);
-        if (k == 0 || k == kNX - 1) {
-          a.y = 0.0f;
-          b.y = 0.0f;
-        }
-        re[k] = a.x - b.y;
-        im[k] = a.y + b.x;
-        if (k > 0 && k < kNX - 1) {
-          re[32 - k] = a.x + b.y;
-          im[32 - k] = b.x - a.y;
-        }
-      }
-    }
+    if (roww) row_inv_load(T, y, c0, D, re, im);
     __syncthreads();  // T is in registers; its LDS becomes the next layer's row spectra
     if (roww) {
       fft32<true>(re, im);
@@ -343,12 +454,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         }
       }
       fft32<false>(re, im);
-#pragma unroll
-      for (int k = 0; k < kNX; ++k) {
-        const int m = (32 - k) & 31;
-        *reinterpret_cast<float4 *>(T + (k * DP + y) * 8 + c0) = make_float4(
-            0.5f * (re[k] + re[m]), 0.5f * (im[k] - im[m]), 0.5f * (im[k] + im[m]), -0.5f * (re[k] - re[m]));
-      }
+      row_fwd_store(T, y, c0, D, re, im);
     }
   }
   __syncthreads();
@@ -357,31 +463,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       *reinterpret_cast<uint4 *>(out + base + (int64_t)v * cout_store) = *reinterpret_cast<const uint4 *>(R + v * 8);
   // forward columns along y (as k_fft_fwd2d)
   float re[32], im[32];
-  const bool colw = tid < kNX * 8;
-  const int kx = tid >> 3, c = tid & 7;
   if (colw) {
-#pragma unroll
-    for (int y = 0; y < 32; ++y) {
-      const float2 v = y < D ? T[(kx * DP + y) * 8 + c] : make_float2(0.0f, 0.0f);
-      re[y] = v.x;
-      im[y] = v.y;
-    }
+    col_fwd_load(T, kxp, c, D, re, im);
     fft32<false>(re, im);
   }
   __syncthreads();
   uint32_t *O = reinterpret_cast<uint32_t *>(T);
-  if (colw) {
-    const bool odd = c & 1;
-#pragma unroll
-    for (int ky = 0; ky < 32; ++ky) {
-      const float mine = odd ? re[ky] : im[ky];
-      const float other = __shfl_xor(mine, 1);
-      const float lo = odd ? other : re[ky], hi = odd ? im[ky] : other;
-      const uint32_t packed = (uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)lo) |
-                              ((uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)hi) << 16);
-      O[(ky * kNX + kx) * 8 + (odd ? 4 : 0) + (c >> 1)] = packed;
-    }
-  }
+  if (colw) col_fwd_store(O, Zp, kxp, c, re, im);
+  __syncthreads();
+  dc_nyquist_split(Zp, O, tid);
   __syncthreads();
   for (int e = tid; e < kCols * 2; e += 256) {
     const int col = e >> 1, h = e & 1;
@@ -743,13 +833,9 @@ __global__ void k_fft_gspec(const float *__restrict__ w, bf16_t *__restrict__ gp
 
 int nch_of(const ConvLayer &L) { return (L.cin + 7) / 8; }
 
-// dynamic LDS of the plane transforms: the larger of the row spectra [17][D + 1][8]
-// complex and the bf16 spectrum of a plane (the input plane and output staging fit
-// in either)
-size_t fft_lds_bytes(int D) {
-  const size_t t = (size_t)kNX * (D + 1) * 8 * sizeof(float2), y = (size_t)kCols * 16 * sizeof(bf16_t);
-  return t > y ? t : y;
-}
+// dynamic LDS of the plane transforms: the plane region (the input plane and the
+// output staging fit in it) and the packed DC / Nyquist column
+size_t fft_lds_bytes(int D) { return (size_t)plane_lds_bytes(D) + kZpBytes; }
 int nbt_of(const ConvLayer &L) { return L.cout * 2 / 32; }
 
 }  // namespace
