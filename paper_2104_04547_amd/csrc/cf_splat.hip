@@ -29,6 +29,13 @@ __device__ inline int64_t floordiv(int64_t a, int64_t b) {  // b > 0
   return (a % b != 0 && a < 0) ? q - 1 : q;
 }
 
+// value of lane b (wave-uniform b)
+__device__ inline int rdlane(int v, int b) { return __builtin_amdgcn_readlane(v, b); }
+__device__ inline int64_t rdlane64(int64_t v, int b) {
+  const uint32_t lo = (uint32_t)rdlane((int)(uint32_t)v, b), hi = (uint32_t)rdlane((int)(uint32_t)(v >> 32), b);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ inline int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -100,8 +107,11 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
     const int a = base + lane;
     bool ov = false;
     int lo0 = 0, lo1 = 0, lo2 = 0;
+    int64_t X0 = 0, X1 = 0, X2 = 0;
     if (a < aend) {
-      const int64_t X0 = xyz[3 * a] - c0, X1 = xyz[3 * a + 1] - c1, X2 = xyz[3 * a + 2] - c2;
+      X0 = xyz[3 * a] - c0;
+      X1 = xyz[3 * a + 1] - c1;
+      X2 = xyz[3 * a + 2] - c2;
       lo0 = (int)floordiv(X0 + off - kRcut + 1023, 1024);
       lo1 = (int)floordiv(X1 + off - kRcut + 1023, 1024);
       lo2 = (int)floordiv(X2 + off - kRcut + 1023, 1024);
@@ -111,17 +121,25 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
       ov = lo0 <= i0 + kTA - 1 && hi0 >= i0 && lo1 <= j0 + kTB - 1 && hi1 >= j0 && lo2 <= G - 1 &&
            hi2 >= 0;
     }
+    // the lanes of overlapping atoms hold their features; the sweep below reads
+    // them (and the coordinates) from that lane instead of from memory
+    float fr[CF_NCH];
+#pragma unroll
+    for (int ch = 0; ch < CF_NCH; ++ch) fr[ch] = 0.0f;
+    if (ov) {
+#pragma unroll
+      for (int ch = 0; ch < CF_NCH; ++ch) fr[ch] = feat[(int64_t)CF_NCH * a + ch];
+    }
     uint64_t m = __ballot(ov);
     while (m) {
       const int b = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      const int ai = base + b;
-      const int l0 = __shfl(lo0, b, 64), l1 = __shfl(lo1, b, 64), l2 = __shfl(lo2, b, 64);
-      const int64_t X0 = xyz[3 * ai] - c0, X1 = xyz[3 * ai + 1] - c1, X2 = xyz[3 * ai + 2] - c2;
+      const int l0 = rdlane(lo0, b), l1 = rdlane(lo1, b), l2 = rdlane(lo2, b);
+      const int64_t X0b = rdlane64(X0, b), X1b = rdlane64(X1, b), X2b = rdlane64(X2, b);
       const int v0 = l0 + (lane >> 4), v1 = l1 + ((lane >> 2) & 3), v2 = l2 + (lane & 3);
-      const int64_t d0 = X0 - 512LL * (2 * v0 - G + 1);
-      const int64_t d1 = X1 - 512LL * (2 * v1 - G + 1);
-      const int64_t d2 = X2 - 512LL * (2 * v2 - G + 1);
+      const int64_t d0 = X0b - 512LL * (2 * v0 - G + 1);
+      const int64_t d1 = X1b - 512LL * (2 * v1 - G + 1);
+      const int64_t d2 = X2b - 512LL * (2 * v2 - G + 1);
       const int64_t D = d0 * d0 + d1 * d1 + d2 * d2;
       const bool in = D <= (int64_t)kRcut * kRcut;
       const float w = in ? expf(-(float)D * kInv2s2) : 0.0f;
@@ -134,9 +152,9 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
       const bool tile = in && v0 >= i0 && v0 < i0 + kTA && v1 >= j0 && v1 < j0 + kTB && v2 >= 0 && v2 < G;
       if (tile) {
         int *dst = acc + (((v0 - i0) * kTB + (v1 - j0)) * G + v2) * CF_NCH;
-        const float *F = feat + (int64_t)CF_NCH * ai;
+#pragma unroll
         for (int ch = 0; ch < CF_NCH; ++ch) {
-          const float fv = F[ch];
+          const float fv = __int_as_float(rdlane(__float_as_int(fr[ch]), b));
           if (!(fabsf(fv) <= kFeatMax)) {
             dev_fail(status, kDevBadFeature);
             continue;
