@@ -72,21 +72,22 @@ __device__ inline void sg_aggregate(const float *__restrict__ cur, const int32_t
         e0 = e1;
       }
       // branch-free body (a column outside the pose reads the atom's own row and
-      // adds nothing) so that the loads of several neighbours overlap
+      // adds nothing; it is reported once after the loop) so that the loads of
+      // several neighbours are in flight together
+      bool anybad = false;
 #pragma unroll 8
       for (int64_t q = e0; q < e1; ++q) {
         int64_t j = colp[q];
         if (csr_global) j -= base;
         const bool bad = j < lb || j >= lb + n;
-        if (bad) dev_fail(status, kDevBadGraph);
+        anybad |= bad;
         const float4 v = *reinterpret_cast<const float4 *>(cur + (bad ? lb + i : j) * H + c4);
-        if (!bad) {
-          s.x += v.x;
-          s.y += v.y;
-          s.z += v.z;
-          s.w += v.w;
-        }
+        s.x += bad ? 0.0f : v.x;
+        s.y += bad ? 0.0f : v.y;
+        s.z += bad ? 0.0f : v.z;
+        s.w += bad ? 0.0f : v.w;
       }
+      if (anybad) dev_fail(status, kDevBadGraph);
       hc = *reinterpret_cast<const float4 *>(cur + (lb + i) * H + c4);
     }
     *reinterpret_cast<float4 *>(A + a * ld + c4) = s;
