@@ -28,6 +28,7 @@ namespace cf {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kGather = 8;  // neighbour rows per batch of the neighbour sums
 
 __device__ inline float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
 
@@ -71,21 +72,28 @@ __device__ inline void sg_aggregate(const float *__restrict__ cur, const int32_t
         dev_fail(status, kDevBadGraph);
         e0 = e1;
       }
-      // branch-free body (a column outside the pose reads the atom's own row and
-      // adds nothing; it is reported once after the loop) so that the loads of
-      // several neighbours are in flight together
+      // whole batches of kGather neighbours with a branch-free body (slots past the
+      // row and columns outside the pose read the atom's own row and add nothing; a
+      // bad column is reported once after the loop), so that every batch's index and
+      // row loads are in flight together and no neighbour waits alone in a remainder
       bool anybad = false;
-#pragma unroll 8
-      for (int64_t q = e0; q < e1; ++q) {
-        int64_t j = colp[q];
-        if (csr_global) j -= base;
-        const bool bad = j < lb || j >= lb + n;
-        anybad |= bad;
-        const float4 v = *reinterpret_cast<const float4 *>(cur + (bad ? lb + i : j) * H + c4);
-        s.x += bad ? 0.0f : v.x;
-        s.y += bad ? 0.0f : v.y;
-        s.z += bad ? 0.0f : v.z;
-        s.w += bad ? 0.0f : v.w;
+      for (int64_t q0 = e0; q0 < e1; q0 += kGather) {
+        int64_t jj[kGather];
+#pragma unroll
+        for (int u = 0; u < kGather; ++u) jj[u] = colp[q0 + u < e1 ? q0 + u : e1 - 1];
+#pragma unroll
+        for (int u = 0; u < kGather; ++u) {
+          const int64_t j = csr_global ? jj[u] - base : jj[u];
+          const bool live = q0 + u < e1;
+          const bool bad = j < lb || j >= lb + n;
+          anybad |= live && bad;
+          const bool use = live && !bad;
+          const float4 v = *reinterpret_cast<const float4 *>(cur + (use ? j : lb + i) * H + c4);
+          s.x += use ? v.x : 0.0f;
+          s.y += use ? v.y : 0.0f;
+          s.z += use ? v.z : 0.0f;
+          s.w += use ? v.w : 0.0f;
+        }
       }
       if (anybad) dev_fail(status, kDevBadGraph);
       hc = *reinterpret_cast<const float4 *>(cur + (lb + i) * H + c4);
