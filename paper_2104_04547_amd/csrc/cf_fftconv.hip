@@ -55,6 +55,10 @@ constexpr int kPanelRows = 288;                                // LDS rows of on
 // threads first form Zp = H(Y0) + i H(Y16) from the spectrum, H the Hermitian part
 // (H(Y)[k] = (Y[k] + conj Y[-k]) / 2); its inverse is Re IFFT(Y0) + i Re IFFT(Y16),
 // the real parts that the row transform takes.
+//
+// The plane kernels take the grid edge as a template argument DT (0: D_rt at run
+// time): with D a constant, the bounds tests inside the unrolled transforms fold
+// away instead of turning into register-copy blocks.
 constexpr int kColThreads = 128;
 
 // LDS of the plane kernels: the plane region (the larger of the row spectra
@@ -427,9 +431,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const bool roww = r >= 0 && r < D * 4;
     const int y = r >> 2, c0 = (r & 3) * 2;
     float re[32], im[32];
-    if (roww) row_inv_load(T, y, c0, D, re, im);
-    __syncthreads();  // T is in registers; its LDS becomes the next layer's row spectra
+    // no barrier between reading and rewriting T here: a row thread reads and then
+    // overwrites only its own (y, channel pair) slots, and the column threads wait
     if (roww) {
+      row_inv_load(T, y, c0, D, re, im);
       fft32<true>(re, im);
       constexpr float kScale = 1.0f / (kN * kN);
       const float b0 = bias[chunk * 8 + c0], b1 = bias[chunk * 8 + c0 + 1];
@@ -899,7 +904,7 @@ hipError_t launch_fft_mid(const ConvLayer &L, const ConvLayer &Ln, const void *r
   hipLaunchKernelGGL(k_fft_mid<DT>, dim3(D, np, nch), dim3(256), lds, s, ys, L.bias,                           \
                      reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), xs, np, D, nch, \
                      L.cout_store, (int)spec)
-  if (D == 24) CF_MID(24); else if (D == 12) CF_MID(12); else CF_MID(0);
+  if (D == 24) CF_MID(24); else if (D == 16) CF_MID(16); else if (D == 12) CF_MID(12); else CF_MID(0);
 #undef CF_MID
   return hipGetLastError();
 }
@@ -914,7 +919,7 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
 #define CF_FWD(DT)                                                                                 \
   hipLaunchKernelGGL(k_fft_fwd2d<DT>, dim3(D, np, nch), dim3(256), fft_lds_bytes(D), s,             \
                      reinterpret_cast<const bf16_t *>(in), xs, np, D, L.cin_pad, nch)
-    if (D == 24) CF_FWD(24); else if (D == 12) CF_FWD(12); else CF_FWD(0);
+    if (D == 24) CF_FWD(24); else if (D == 16) CF_FWD(16); else if (D == 12) CF_FWD(12); else CF_FWD(0);
 #undef CF_FWD
   }
   if ((stage < 0 || stage == 1) && L.cout == 64 && (kRowsZH / D) * (D + L.k - 1) <= kPanelRowsH) {
@@ -950,7 +955,7 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
   hipLaunchKernelGGL(k_fft_inv2d<DT>, dim3(D, np, nco), dim3(256), fft_lds_bytes(D), s, ys, L.bias,        \
                      reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), np, D, nco, \
                      L.cout_store)
-    if (D == 24) CF_INV(24); else if (D == 12) CF_INV(12); else CF_INV(0);
+    if (D == 24) CF_INV(24); else if (D == 16) CF_INV(16); else if (D == 12) CF_INV(12); else CF_INV(0);
 #undef CF_INV
   }
   return hipGetLastError();
