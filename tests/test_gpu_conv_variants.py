@@ -18,10 +18,15 @@ def _say(msg):
     sys.stdout.flush()
 
 
+# residual layers at D = 12 (G 24), 16 (G 32) and 20 (G 40): the frequency-domain
+# plane kernels are compiled for D = 24, 16 and 12 and take D at run time otherwise
+CASES = [("tiny", 24), ("full", 24), ("full", 32), ("full", 40), ("paper", 24), ("paper", 40)]
+
+
 @pytest.fixture(scope="module")
 def cases():
     out = {}
-    for arch_name, G in (("tiny", 24), ("full", 24), ("full", 40), ("paper", 24), ("paper", 40)):
+    for arch_name, G in CASES:
         arch, w = weights(arch_name)
         b = synth.make_poses("c1" if G == 24 else "c2", 3)  # odd: a lone pose in two-pose tiles
         cen = np.stack([oracle.pose_center(b.xyz[b.atom_off[p]:b.atom_off[p + 1]][
@@ -32,7 +37,7 @@ def cases():
     return out
 
 
-@pytest.mark.parametrize("arch_name,G", [("tiny", 24), ("full", 24), ("full", 40), ("paper", 24), ("paper", 40)])
+@pytest.mark.parametrize("arch_name,G", CASES)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_every_conv_variant_matches_oracle(cases, arch_name, G, prec):
     import torch
