@@ -257,7 +257,7 @@ int cf_timing_read(cf_ctx *ctx, cf_kernel_stat *out, int32_t max_entries, int32_
 /* ---- Selection after scoring --------------------------------------------------
  * Per-compound aggregation: the paper represents each compound by its strongest
  * prediction over all its docked poses (the maximum Coherent Fusion pK; up to 10
- * poses per site, Sec. 5.1).  Segment c covers scores[compound_off[c] ..
+ * poses per site, Sec. 5.2).  Segment c covers scores[compound_off[c] ..
  * compound_off[c+1]); best_score[c] is its maximum and best_pose[c] the lowest
  * index attaining it.  NaN scores are ignored; an empty (or all-NaN) segment gives
  * -inf and -1.  Offsets outside [0, n_scores] are reported by cf_stream_status.

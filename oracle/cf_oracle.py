@@ -372,7 +372,7 @@ def _score_one(x, f, l, w, arch, G):
 
 
 # --------------------------------------------------------------------------------
-# Selection after scoring (Sec. 5.1: a compound is represented by its strongest
+# Selection after scoring (Sec. 5.2: a compound is represented by its strongest
 # prediction over all its docked poses -- the maximum Fusion pK; Sec. 3.4: the best
 # 100 of a million screened compounds are bought)
 # --------------------------------------------------------------------------------

@@ -2,7 +2,7 @@
 //
 // In the paper's screen each compound has up to 10 docked poses per binding site
 // (40 over four sites) and is represented by its strongest prediction -- the
-// maximum Coherent Fusion pK over its poses (Sec. 5.1); compounds are then ranked
+// maximum Coherent Fusion pK over its poses (Sec. 5.2); compounds are then ranked
 // and the best few purchased for assays (the 100-of-1,000,000 example, Sec. 3.4).
 //
 // cf_compound_max: one thread per segment (segments are short), NaN scores are
