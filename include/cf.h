@@ -51,7 +51,8 @@ typedef enum {
   CF_ERR_CAPACITY = -2,    /* a caller-provided CSR is too small; see cf_stream_status */
   CF_ERR_OOM = -3,         /* device allocation failed or would exceed the HBM budget */
   CF_ERR_HIP = -4,         /* a HIP runtime call failed */
-  CF_ERR_UNSUPPORTED = -5  /* valid request outside what this build implements */
+  CF_ERR_UNSUPPORTED = -5, /* valid request outside what this build implements */
+  CF_ERR_CANCELLED = -6    /* serving request cancelled before it was scheduled */
 } cf_status;
 
 typedef enum {
@@ -296,13 +297,25 @@ typedef struct {
 int cf_engine_create(const void *host_model_blob, size_t nbytes, int precision, const cf_engine_config *cfg,
                      cf_engine **out);
 /* Host pointers: atom_off [n_poses+1] (atom_off[0] = 0), xyz [N][3], feat [N][19],
- * is_lig [N]; G a multiple of 4 in 8..96.  Returns a ticket for cf_engine_poll. */
+ * is_lig [N]; G a multiple of 4 in 8..96.  Returns a ticket for cf_engine_poll.
+ * Offsets and features (finite, |value| <= 64) are checked here, so a malformed
+ * request is rejected before it can share a batch.  Should the device still
+ * report an error for a batch (e.g. neighbour lists overflowing the batch's edge
+ * capacity), each of its requests is scored again alone and only the one at
+ * fault returns the error; every request's scores are the ones it gets alone. */
 int cf_engine_submit(cf_engine *e, int32_t n_poses, const int32_t *atom_off, const int32_t *xyz, const float *feat,
                      const uint8_t *is_lig, int32_t G, uint64_t *ticket);
 /* *done = 1 once scored: scores_out (host [n_poses]) and *latency_ms (submit to
  * scores on the host) are filled, the ticket is released and the request's
  * status (device-side checks included) is returned. */
 int cf_engine_poll(cf_engine *e, uint64_t ticket, float *scores_out, int32_t *done, double *latency_ms);
+/* Cancel a request that is still queued: it leaves the queue and is never scored;
+ * *cancelled = 1, and cf_engine_poll then reports it done with CF_ERR_CANCELLED
+ * (releasing the ticket).  A request already packed into a batch on the device
+ * runs to completion (*cancelled = 0).  The paper's screening jobs isolate
+ * failures by rescheduling work (Sec. 4.3); a serving caller withdraws work this
+ * way (a deadline passed, a client went away). */
+int cf_engine_cancel(cf_engine *e, uint64_t ticket, int32_t *cancelled);
 int cf_engine_wait_all(cf_engine *e);
 int cf_engine_info(cf_engine *e, int64_t *poses_done, int64_t *batches, int64_t *graph_replays, int64_t *queued);
 const char *cf_engine_last_error(cf_engine *e);

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcf.so")
 
 CF_OK, CF_ERR_INVALID_ARG, CF_ERR_CAPACITY, CF_ERR_OOM, CF_ERR_HIP, CF_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+CF_ERR_CANCELLED = -6
 CF_PREC_FP32, CF_PREC_BF16 = 0, 1
 CF_NCH = 19
 CF_MAX_POSE_ATOMS = 4096
@@ -28,7 +29,7 @@ EXPORTS = ["cf_create", "cf_destroy", "cf_pose_centers", "cf_voxelize", "cf_buil
            "cf_sgcnn_fwd", "cf_score_poses", "cf_stream_status", "cf_last_error", "cf_model_info",
            "cf_autotune", "cf_conv_variants", "cf_timing_enable", "cf_timing_read",
            "cf_engine_create", "cf_engine_submit", "cf_engine_poll", "cf_engine_wait_all", "cf_engine_info",
-           "cf_engine_last_error", "cf_engine_destroy", "cf_set_conv_variants", "cf_conv_variant_count",
+           "cf_engine_last_error", "cf_engine_destroy", "cf_engine_cancel", "cf_set_conv_variants", "cf_conv_variant_count",
            "cf_conv_variant_name", "cf_compound_max", "cf_top_k", "cf_fusion_fwd"]
 
 
@@ -107,6 +108,7 @@ def load(path: str = LIB_PATH):
         "cf_engine_poll": ([vp, ctypes.c_uint64, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
                            ctypes.c_int),
         "cf_engine_wait_all": ([vp], ctypes.c_int),
+        "cf_engine_cancel": ([vp, ctypes.c_uint64, ctypes.POINTER(i32)], ctypes.c_int),
         "cf_engine_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
                            ctypes.c_int),
         "cf_engine_last_error": ([vp], ctypes.c_char_p),
@@ -337,6 +339,15 @@ def cf_engine_poll(eng, ticket: int, n_poses: int):
     if rc != CF_OK:
         raise CfError(rc, load().cf_engine_last_error(eng).decode(errors="replace"))
     return (True, out, lat.value) if done.value else (False, None, None)
+
+
+def cf_engine_cancel(eng, ticket: int) -> bool:
+    """True if the request was still queued and is now withdrawn."""
+    c = ctypes.c_int32(0)
+    rc = load().cf_engine_cancel(eng, ticket, ctypes.byref(c))
+    if rc != CF_OK:
+        raise CfError(rc, load().cf_engine_last_error(eng).decode(errors="replace"))
+    return bool(c.value)
 
 
 def cf_engine_wait_all(eng):

@@ -12,12 +12,15 @@
 // with empty poses to a power-of-two bucket so its kernel sequence can be
 // captured once per (grid size, bucket) as a hipGraph and replayed.  Scores do
 // not depend on the batch a pose lands in: every kernel computes each pose
-// independently and in a fixed order.
+// independently and in a fixed order.  Hence a batch whose device checks fail is
+// scored again one request at a time, so that only the request at fault reports
+// the error and every other request still gets the scores it would get alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -30,6 +33,7 @@
 #include <vector>
 
 #include "cf_internal.h"
+#include "cf_queue.h"
 
 namespace {
 
@@ -46,6 +50,7 @@ struct Request {
   int status = CF_OK;
   bool done = false;
   double latency_ms = 0.0;
+  int64_t atoms() const { return off[n_poses]; }
 };
 
 struct Slot {
@@ -82,7 +87,7 @@ struct cf_engine {
   std::vector<Slot> slots;
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<Request *> pending;
+  cf::RequestQueue<Request> pending;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
   uint64_t next_id = 1;
   std::thread worker;
@@ -112,16 +117,18 @@ void free_slot(Slot &s) {
   if (s.ctx) cf_destroy(s.ctx);
 }
 
-// Launch one packed batch on a free slot.  Called by the worker with mu held.
-int launch_batch(cf_engine *e, Slot &s, std::vector<Request *> &take, int G) {
-  const int cap_p = e->cfg.slot_poses;
+// Pack requests into the slot's pinned staging (pose rows in request order,
+// padded with empty poses up to `bucket`) and copy them to the slot's device
+// buffers on its stream.  Returns the number of real poses in *np_out.
+int stage_requests(cf_engine *e, Slot &s, const std::vector<Request *> &take, int bucket_cap, int *np_out,
+                   int *bucket_out, int64_t *na_out) {
   int np = 0;
   int64_t na = 0;
   s.members.clear();
   s.h_off[0] = 0;
   for (Request *r : take) {
     s.members.push_back({r, np});
-    const int64_t ra = r->off[r->n_poses];
+    const int64_t ra = r->atoms();
     memcpy(s.h_xyz + 3 * na, r->xyz.data(), sizeof(int32_t) * 3 * ra);
     memcpy(s.h_feat + (size_t)CF_NCH * na, r->feat.data(), sizeof(float) * CF_NCH * ra);
     memcpy(s.h_lig + na, r->lig.data(), ra);
@@ -129,7 +136,7 @@ int launch_batch(cf_engine *e, Slot &s, std::vector<Request *> &take, int G) {
     np += r->n_poses;
     na += ra;
   }
-  const int bucket = bucket_for(np, cap_p);
+  const int bucket = bucket_cap > 0 ? bucket_for(np, bucket_cap) : np;
   for (int p = np; p < bucket; ++p) s.h_off[p + 1] = (int32_t)na;  // empty padding poses
   hipStream_t st = s.stream;
   if (hipMemcpyAsync(s.d_off, s.h_off, sizeof(int32_t) * (bucket + 1), hipMemcpyHostToDevice, st) ||
@@ -139,6 +146,20 @@ int launch_batch(cf_engine *e, Slot &s, std::vector<Request *> &take, int G) {
     e->last_error = "engine H2D copy failed";
     return CF_ERR_HIP;
   }
+  *np_out = np;
+  *bucket_out = bucket;
+  *na_out = na;
+  return CF_OK;
+}
+
+// Launch one packed batch on a free slot.  Called by the worker with mu held.
+int launch_batch(cf_engine *e, Slot &s, std::vector<Request *> &take, int G) {
+  const int cap_p = e->cfg.slot_poses;
+  int np = 0, bucket = 0;
+  int64_t na = 0;
+  int rc = stage_requests(e, s, take, cap_p, &np, &bucket, &na);
+  if (rc) return rc;
+  hipStream_t st = s.stream;
   // The batch descriptor uses the slot's capacity as n_atoms: buffers hold that
   // many rows, and fixed arguments let one captured graph serve every batch of
   // this (G, bucket).
@@ -150,7 +171,6 @@ int launch_batch(cf_engine *e, Slot &s, std::vector<Request *> &take, int G) {
   b.feat = s.d_feat;
   b.is_lig = s.d_lig;
   b.center = nullptr;
-  int rc = CF_OK;
   if (e->cfg.use_graphs) {
     auto key = std::make_pair(G, bucket);
     drop_stale_graphs(s);
@@ -186,19 +206,53 @@ int launch_batch(cf_engine *e, Slot &s, std::vector<Request *> &take, int G) {
   return CF_OK;
 }
 
+// Score one request alone on the slot (eager launches, synchronous) and return
+// its status; its scores go to r->scores.
+int score_alone(cf_engine *e, Slot &s, Request *r) {
+  int np = 0, bucket = 0;
+  int64_t na = 0;
+  int rc = stage_requests(e, s, std::vector<Request *>{r}, 0, &np, &bucket, &na);
+  if (rc == CF_OK) {
+    cf_pose_batch b{};
+    b.n_poses = np;
+    b.n_atoms = (int32_t)na;
+    b.atom_off = s.d_off;
+    b.xyz = s.d_xyz;
+    b.feat = s.d_feat;
+    b.is_lig = s.d_lig;
+    rc = cf_score_poses(s.ctx, &b, r->G, s.d_scores, s.stream);
+  }
+  if (rc == CF_OK && hipMemcpyAsync(s.h_scores, s.d_scores, sizeof(float) * np, hipMemcpyDeviceToHost, s.stream))
+    rc = CF_ERR_HIP;
+  const int st = cf_stream_status(s.ctx, s.stream, nullptr, nullptr);
+  if (rc == CF_OK) rc = st;
+  r->scores.assign(s.h_scores, s.h_scores + r->n_poses);
+  return rc;
+}
+
 void finish_slot(cf_engine *e, Slot &s) {
   int64_t need_c = 0, need_n = 0;
   const int st = cf_stream_status(s.ctx, s.stream, &need_c, &need_n);
   if (st != CF_OK) e->last_error = std::string("device status: ") + cf_last_error();
-  const auto now = Clock::now();
+  const auto members = s.members;  // score_alone restages the slot
   int np = 0;
-  for (auto &m : s.members) {
+  for (auto &m : members) {
     Request *r = m.first;
     r->scores.assign(s.h_scores + m.second, s.h_scores + m.second + r->n_poses);
     r->status = st;
+    np += r->n_poses;
+  }
+  // A device-detected error (e.g. one pose's neighbour lists overflowing the
+  // batch's edge capacity) is reported for the whole batch: score each request
+  // alone to find which one is at fault.  The others' scores equal what the batch
+  // would have given them (scores never depend on the batch).
+  if (st != CF_OK && members.size() > 1)
+    for (auto &m : members) m.first->status = score_alone(e, s, m.first);
+  const auto now = Clock::now();
+  for (auto &m : members) {
+    Request *r = m.first;
     r->latency_ms = std::chrono::duration<double, std::milli>(now - r->t_submit).count();
     r->done = true;
-    np += r->n_poses;
   }
   e->poses_done += np;
   e->in_flight -= np;
@@ -219,22 +273,8 @@ void worker_main(cf_engine *e) {
     for (Slot &s : e->slots) {
       if (s.busy || e->pending.empty()) continue;
       // pack queued requests with the head's grid size, in arrival order
-      const int G = e->pending.front()->G;
-      std::vector<Request *> take;
-      int np = 0;
-      int64_t na = 0;
-      for (auto it = e->pending.begin(); it != e->pending.end();) {
-        Request *r = *it;
-        const int64_t ra = r->off[r->n_poses];
-        if (r->G == G && np + r->n_poses <= e->cfg.slot_poses && na + ra <= e->cfg.slot_atoms) {
-          take.push_back(r);
-          np += r->n_poses;
-          na += ra;
-          it = e->pending.erase(it);
-        } else {
-          ++it;
-        }
-      }
+      std::vector<Request *> take = e->pending.take_batch(e->cfg.slot_poses, e->cfg.slot_atoms);
+      const int G = take.front()->G;
       const int rc = launch_batch(e, s, take, G);
       if (rc != CF_OK) {
         e->last_error = std::string("batch launch failed: ") + cf_last_error();
@@ -319,6 +359,11 @@ int cf_engine_submit(cf_engine *e, int32_t n_poses, const int32_t *atom_off, con
   }
   const int64_t na = atom_off[n_poses];
   if (na > e->cfg.slot_atoms) return efail(e, CF_ERR_INVALID_ARG, "request has more atoms than a slot holds");
+  // the device checks the same bound, but for a whole batch: reject a bad
+  // request here so that it never shares a batch with others
+  for (int64_t i = 0; i < (int64_t)CF_NCH * na; ++i)
+    if (!(std::fabs(feat[i]) <= cf::kFeatMax))
+      return efail(e, CF_ERR_INVALID_ARG, "feature value not finite or |value| > 64");
   auto r = std::make_unique<Request>();
   r->n_poses = n_poses;
   r->G = G;
@@ -331,7 +376,7 @@ int cf_engine_submit(cf_engine *e, int32_t n_poses, const int32_t *atom_off, con
     std::lock_guard<std::mutex> lk(e->mu);
     r->id = e->next_id++;
     *ticket = r->id;
-    e->pending.push_back(r.get());
+    e->pending.push(r.get());
     e->reqs.emplace(r->id, std::move(r));
   }
   e->cv.notify_all();
@@ -346,11 +391,31 @@ int cf_engine_poll(cf_engine *e, uint64_t ticket, float *scores_out, int32_t *do
   Request *r = it->second.get();
   *done = r->done ? 1 : 0;
   if (!r->done) return CF_OK;
+  if (r->status == CF_ERR_CANCELLED) {
+    e->reqs.erase(it);
+    return efail(e, CF_ERR_CANCELLED, "request was cancelled");
+  }
   if (scores_out) memcpy(scores_out, r->scores.data(), sizeof(float) * r->scores.size());
   if (latency_ms) *latency_ms = r->latency_ms;
   const int st = r->status;
   e->reqs.erase(it);
   return st;
+}
+
+int cf_engine_cancel(cf_engine *e, uint64_t ticket, int32_t *cancelled) {
+  if (!e || !cancelled) return efail(e, CF_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(e->mu);
+  *cancelled = 0;
+  auto it = e->reqs.find(ticket);
+  if (it == e->reqs.end()) return efail(e, CF_ERR_INVALID_ARG, "unknown ticket");
+  Request *r = it->second.get();
+  if (!r->done && e->pending.cancel(r)) {
+    r->status = CF_ERR_CANCELLED;
+    r->done = true;
+    *cancelled = 1;
+  }
+  e->cv.notify_all();
+  return CF_OK;
 }
 
 int cf_engine_wait_all(cf_engine *e) {
@@ -371,11 +436,7 @@ int cf_engine_info(cf_engine *e, int64_t *poses_done, int64_t *batches, int64_t 
   if (poses_done) *poses_done = e->poses_done;
   if (batches) *batches = e->batches;
   if (graph_replays) *graph_replays = e->replays;
-  if (queued) {
-    int64_t q = 0;
-    for (Request *r : e->pending) q += r->n_poses;
-    *queued = q;
-  }
+  if (queued) *queued = e->pending.queued_poses();
   return CF_OK;
 }
 

@@ -39,6 +39,9 @@ class Engine:
                 raise TimeoutError("engine request did not finish")
             time.sleep(0.0005)
 
+    def cancel(self, ticket: int) -> bool:
+        return cfabi.cf_engine_cancel(self.h, ticket)
+
     def wait_all(self):
         cfabi.cf_engine_wait_all(self.h)
 

@@ -10,6 +10,10 @@ the HIP path.  Outputs (JSON, floats written with repr so they round-trip):
   <cfg>_G<G>_oracle.json  per pose: oracle centre, CNN latent, SG latent and
                        calibrated score, for poses [0, n) of a workload config
 
+  <cfg>_G<G>_scores.json calibrated oracle scores (and edge counts) of poses
+                       [0, n) when only the first --latents of them are
+                       stored with their latents
+
 Usage:  python tests/golden/make_golden.py c1 24 64
         python tests/golden/make_golden.py c2 48 64 --calibrate
         python tests/golden/make_golden.py c4 32 8
@@ -60,6 +64,9 @@ def main():
     ap.add_argument("--workers", type=int, default=os.cpu_count())
     ap.add_argument("--head-arch", default=None)
     ap.add_argument("--arch", default=None, help="another architecture on the config's poses")
+    ap.add_argument("--latents", type=int, default=None,
+                    help="store latents for the first this many poses; scores of all n go to _scores.json")
+    ap.add_argument("--cache", default=None, help="append-only JSONL of computed rows (resumable runs)")
     a = ap.parse_args()
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     import numpy as np
@@ -72,8 +79,29 @@ def main():
 
     t0 = time.time()
     arch_name = a.arch or synth.CONFIGS[a.cfg]["arch"]
+    tag = "" if arch_name == synth.CONFIGS[a.cfg]["arch"] else f"_{arch_name}"
+    path = os.path.join(HERE, f"{a.cfg}_G{a.G}{tag}_oracle.json")
+    have = {}
+    if a.latents is not None and os.path.exists(path):   # rows stored earlier by this script
+        for r in json.load(open(path))["poses"]:
+            have[r["pose"]] = (r["pose"], r["center"], r["cnn_lat"], r["sg_lat"], r["n_cov_edges"], r["n_nc_edges"])
+    if a.cache and os.path.exists(a.cache):
+        for line in open(a.cache):
+            r = json.loads(line)
+            if r[0] < a.n:
+                have[r[0]] = tuple(r)
+    todo = [p for p in range(a.n) if p not in have]
+    print(f"{len(have)} rows known, {len(todo)} to compute", flush=True)
     with get_context("spawn").Pool(a.workers) as pool:
-        rows = sorted(pool.map(_latents, [(a.cfg, a.G, p, arch_name) for p in range(a.n)], chunksize=1))
+        cache = open(a.cache, "a") if a.cache else None
+        for i, r in enumerate(pool.imap_unordered(_latents, [(a.cfg, a.G, p, arch_name) for p in todo])):
+            have[r[0]] = r
+            if cache:
+                cache.write(json.dumps(r) + "\n")
+                cache.flush()
+            if (i + 1) % 64 == 0:
+                print(f"{i + 1}/{len(todo)} poses in {time.time() - t0:.0f}s", flush=True)
+    rows = [have[p] for p in range(a.n)]
     arch = synth.ARCHS[arch_name]
     w = synth.make_weights(arch)
     calib_path = os.path.join(HERE, "calib.json")
@@ -87,16 +115,25 @@ def main():
                                 raw_std=float(raw.std()), source=f"{a.cfg} poses 0..63, G={a.G}")
         json.dump(calib, open(calib_path, "w"), indent=1)
     cw = synth.apply_calibration(w, calib[arch_name]["scale"], calib[arch_name]["shift"])
+    n_lat = a.n if a.latents is None else min(a.latents, a.n)
     out = dict(config=a.cfg, G=a.G, arch=arch_name, seed_poses=0, seed_weights=1,
                calibration=calib[arch_name], poses=[])
+    scores = dict(config=a.cfg, G=a.G, arch=arch_name, seed_poses=0, seed_weights=1,
+                  calibration=calib[arch_name], score=[], n_cov_edges=[], n_nc_edges=[])
     for (p, c, cnn, sg, ecov, enc) in rows:
-        s = oracle.fusion_head(np.array(cnn), np.array(sg), cw, arch)
-        out["poses"].append(dict(pose=p, center=c, cnn_lat=cnn, sg_lat=sg, score=float(s),
-                                 n_cov_edges=ecov, n_nc_edges=enc))
-    tag = "" if arch_name == synth.CONFIGS[a.cfg]["arch"] else f"_{arch_name}"
-    path = os.path.join(HERE, f"{a.cfg}_G{a.G}{tag}_oracle.json")
+        s = float(oracle.fusion_head(np.array(cnn), np.array(sg), cw, arch))
+        if p < n_lat:
+            out["poses"].append(dict(pose=p, center=c, cnn_lat=cnn, sg_lat=sg, score=s,
+                                     n_cov_edges=ecov, n_nc_edges=enc))
+        scores["score"].append(s)
+        scores["n_cov_edges"].append(ecov)
+        scores["n_nc_edges"].append(enc)
     json.dump(out, open(path, "w"))
-    print(f"wrote {path} ({a.n} poses) in {time.time() - t0:.1f}s")
+    print(f"wrote {path} ({n_lat} poses) in {time.time() - t0:.1f}s")
+    if a.latents is not None:
+        spath = os.path.join(HERE, f"{a.cfg}_G{a.G}{tag}_scores.json")
+        json.dump(scores, open(spath, "w"))
+        print(f"wrote {spath} ({a.n} poses)")
 
 
 def calibrate_head(cfg, G, head_arch):
