@@ -270,6 +270,18 @@ int cf_compound_max(cf_ctx *ctx, const float *scores, int32_t n_scores, const in
  * index, NaN last; idx_out [k], val_out [k] or NULL.  0 <= k <= min(n, 1024). */
 int cf_top_k(cf_ctx *ctx, const float *values, int32_t n, int32_t k, int32_t *idx_out, float *val_out,
              void *stream);
+/* cf_top_k without a context, for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, ordering and results as cf_top_k, but its scratch
+ * (histogram, select state and up to 1024 keys, 9,280 bytes) is a static device
+ * array of the library, one copy per GPU held until the process ends, whose
+ * address is looked up once per device on the first call there.  Calls no
+ * hipMalloc / hipFree and clears what must start at zero with a kernel.  k > 1024
+ * returns CF_ERR_UNSUPPORTED.  Calls on one GPU share the array: two calls whose
+ * work overlaps on that GPU (different streams, or different host threads without
+ * ordering) race and may return wrong results; calls ordered on one stream are
+ * safe. */
+int cf_top_k_noalloc(const float *values, int32_t n, int32_t k, int32_t *idx_out, float *val_out, void *stream);
 
 /* ---- Serving engine (continuous batching) ------------------------------------
  * The request-driven form of the paper's per-GPU scoring loop (Sec. 4.2): each

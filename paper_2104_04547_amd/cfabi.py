@@ -30,7 +30,8 @@ EXPORTS = ["cf_create", "cf_destroy", "cf_pose_centers", "cf_voxelize", "cf_buil
            "cf_autotune", "cf_conv_variants", "cf_timing_enable", "cf_timing_read",
            "cf_engine_create", "cf_engine_submit", "cf_engine_poll", "cf_engine_wait_all", "cf_engine_info",
            "cf_engine_last_error", "cf_engine_destroy", "cf_engine_cancel", "cf_set_conv_variants", "cf_conv_variant_count",
-           "cf_conv_variant_name", "cf_compound_max", "cf_top_k", "cf_fusion_fwd"]
+           "cf_conv_variant_name", "cf_compound_max", "cf_top_k", "cf_fusion_fwd",
+           "cf_top_k_noalloc"]
 
 
 HEAD_KINDS = {"coherent": 0, "mid": 1, "late": 2}   # cf_head_kind
@@ -118,6 +119,7 @@ def load(path: str = LIB_PATH):
         "cf_conv_variant_name": ([i32], ctypes.c_char_p),
         "cf_compound_max": ([vp, vp, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "cf_top_k": ([vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
+        "cf_top_k_noalloc": ([vp, i32, i32, vp, vp, vp], ctypes.c_int),
         "cf_fusion_fwd": ([vp, vp, vp, i32, vp, vp], ctypes.c_int),
     }
     missing = set(EXPORTS) - set(sig)
@@ -291,6 +293,10 @@ def cf_compound_max(ctx, scores_ptr: int, n_scores: int, off_ptr: int, n_compoun
 
 def cf_top_k(ctx, values_ptr: int, n: int, k: int, idx_ptr: int, val_ptr, stream: int = 0):
     _check(load().cf_top_k(ctx, values_ptr, n, k, idx_ptr, val_ptr, stream))
+
+
+def cf_top_k_noalloc(values_ptr: int, n: int, k: int, idx_ptr: int, val_ptr, stream: int = 0):
+    _check(load().cf_top_k_noalloc(values_ptr, n, k, idx_ptr, val_ptr, stream))
 
 
 def cf_timing_enable(ctx, enable: bool = True):

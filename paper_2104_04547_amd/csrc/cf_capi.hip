@@ -1042,9 +1042,22 @@ int cf_top_k(cf_ctx *c, const float *values, int32_t n, int32_t k, int32_t *idx_
   if (n < 0 || k < 0 || k > n) return fail(CF_ERR_INVALID_ARG, "need 0 <= k <= n");
   if (k > 1024) return fail(CF_ERR_UNSUPPORTED, "k must be <= 1024");
   if (k == 0) return CF_OK;
-  int rc = ensure(c, c->sel, 1088 + 8 * (size_t)1024);
+  int rc = ensure(c, c->sel, cf::kTopkScratchBytes);
   if (rc) return rc;
   CF_HIP(cf::launch_topk(values, n, k, idx_out, val_out, c->sel.p, (hipStream_t)stream));
+  return CF_OK;
+}
+
+int cf_top_k_noalloc(const float *values, int32_t n, int32_t k, int32_t *idx_out, float *val_out, void *stream) {
+  if (!values || !idx_out) return fail(CF_ERR_INVALID_ARG, "null argument");
+  if (n < 0 || k < 0 || k > n) return fail(CF_ERR_INVALID_ARG, "need 0 <= k <= n");
+  if (k > cf::kTopkMaxK)
+    return fail(CF_ERR_UNSUPPORTED, "k = " + std::to_string(k) + " exceeds the " + std::to_string(cf::kTopkMaxK) +
+                                        " keys the static top-k scratch holds");
+  if (k == 0) return CF_OK;
+  void *scratch = nullptr;
+  CF_HIP(cf::topk_static_scratch(&scratch));
+  CF_HIP(cf::launch_topk(values, n, k, idx_out, val_out, scratch, (hipStream_t)stream));
   return CF_OK;
 }
 

@@ -169,6 +169,12 @@ hipError_t launch_segmax(const float *scores, int n_scores, const int32_t *off, 
                          int32_t *best_idx, int64_t *status, hipStream_t s);
 // scratch: 1088 + 8 k bytes
 hipError_t launch_topk(const float *v, int n, int k, int32_t *idx_out, float *val_out, void *scratch, hipStream_t s);
+// Top-k scratch: histogram (1024 B) + select state (64 B) + up to kTopkMaxK keys.
+constexpr int kTopkMaxK = 1024;
+constexpr size_t kTopkScratchBytes = 1024 + 64 + 8 * (size_t)kTopkMaxK;
+constexpr int kMaxDevices = 64;
+// Device address of the library's static top-k scratch on the current device.
+hipError_t topk_static_scratch(void **out);
 
 // A fusion head as a list of dense layers over a per-pose feature buffer that
 // starts as [cnn latent (lc) | sg latent (H)]; each layer reads the concatenation

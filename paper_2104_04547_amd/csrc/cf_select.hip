@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <climits>
+#include <mutex>
 
 #include "cf_internal.h"
 
@@ -153,6 +154,36 @@ hipError_t launch_segmax(const float *scores, int n_scores, const int32_t *off, 
   hipLaunchKernelGGL(k_segmax, dim3((n_seg + kSelThreads - 1) / kSelThreads), dim3(kSelThreads), 0, s, scores,
                      n_scores, off, n_seg, best, best_idx, status);
   return hipGetLastError();
+}
+
+// Scratch of the allocation-free top-k: the 256-bin histogram (1 KB), the select
+// state (64 B) and the k <= 1024 collected keys (8 KB).  One copy per GPU, held
+// until the process ends; every allocation-free call on a GPU shares it.
+static __device__ __align__(256) unsigned char scratch[kTopkScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the current device's copy of `scratch`, looked up once per
+// device (the array's name in host code is a host-side stand-in, not a device
+// address).  Later calls read the cached pointer.
+hipError_t topk_static_scratch(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_topk(const float *v, int n, int k, int32_t *idx_out, float *val_out, void *scratch,
