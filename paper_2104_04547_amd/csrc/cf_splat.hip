@@ -89,12 +89,14 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
                                                void *__restrict__ grid, int cpad,
                                                int64_t *__restrict__ status) {
   extern __shared__ int acc[];  // [kTA][kTB][G][19]
+  __shared__ int budget;        // range budget used by the atoms reaching this tile
   const int pl = blockIdx.y;    // pose within this launch
   const int p = p0 + pl;
   const int ntb = G / kTB;
   const int i0 = (blockIdx.x / ntb) * kTA, j0 = (blockIdx.x % ntb) * kTB;
   const int nacc = kTA * kTB * G * CF_NCH;
   for (int e = threadIdx.x; e < nacc; e += blockDim.x) acc[e] = 0;
+  if (threadIdx.x == 0) budget = 0;
   int a0, a1;
   if (!pose_range(atom_off, p, n_atoms, a0, a1) && blockIdx.x == 0 && threadIdx.x == 0)
     dev_fail(status, kDevBadOffsets);
@@ -126,9 +128,23 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
     float fr[CF_NCH];
 #pragma unroll
     for (int ch = 0; ch < CF_NCH; ++ch) fr[ch] = 0.0f;
+    int cost = 0;
     if (ov) {
+      float mf = 0.0f;
+      bool bad = false;
 #pragma unroll
-      for (int ch = 0; ch < CF_NCH; ++ch) fr[ch] = feat[(int64_t)CF_NCH * a + ch];
+      for (int ch = 0; ch < CF_NCH; ++ch) {
+        fr[ch] = feat[(int64_t)CF_NCH * a + ch];
+        bad |= !(fabsf(fr[ch]) <= kFeatMax);
+        mf = fmaxf(mf, fabsf(fr[ch]));
+      }
+      cost = bad ? (int)kFeatMax + 1 : (int)ceilf(mf);  // NaN and |f| > 64 count 65
+    }
+    {
+      int wc = cost;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) wc += __shfl_xor(wc, o, 64);
+      if (lane == 0 && wc) atomicAdd(&budget, wc);
     }
     uint64_t m = __ballot(ov);
     while (m) {
@@ -167,6 +183,7 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
     }
   }
   __syncthreads();
+  if (threadIdx.x == 0 && budget > kSplatBudget) dev_fail(status, kDevGridRange);
   // stream the tile out
   const int nvox = kTA * kTB * G;
   if (MODE == 0 || MODE == 1) {

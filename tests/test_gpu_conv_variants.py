@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import weights
+from helpers import BF16_LATENT_TOL, weights
 
 pytestmark = pytest.mark.gpu
 
@@ -72,7 +72,8 @@ def test_every_conv_variant_matches_oracle(cases, arch_name, G, prec):
             if prec == "fp32":
                 np.testing.assert_allclose(got, want, rtol=1e-4, atol=1e-4 * scale, err_msg=names[v])
             else:
-                np.testing.assert_allclose(got, want, rtol=3e-2, atol=3e-2 * scale, err_msg=names[v])
+                np.testing.assert_allclose(got, want, rtol=BF16_LATENT_TOL, atol=BF16_LATENT_TOL * scale,
+                                           err_msg=names[v])
         assert tried >= 2
     finally:
         s.close()

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import BF16_PK_TOL, golden, score_tol, weights
+from helpers import BF16_PK_TOL, golden, golden_scores, score_tol, weights
 
 pytestmark = pytest.mark.gpu
 
@@ -56,8 +56,8 @@ def _score(s, b, G):
 
 
 @pytest.mark.parametrize("cfg,arch_name,G,n", [("c1", "tiny", 24, 64), ("c2", "full", 48, 64),
-                                               ("c4", "full", 32, 16), ("c4", "full", 64, 8),
-                                               ("c2", "full", 40, 8)])
+                                               ("c4", "full", 32, 16), ("c4", "full", 48, 16),
+                                               ("c4", "full", 64, 8), ("c2", "full", 40, 8)])
 def test_score_fp32_matches_oracle(scorers, cfg, arch_name, G, n):
     gd = golden(cfg, G)
     if gd is None:
@@ -73,7 +73,8 @@ def test_score_fp32_matches_oracle(scorers, cfg, arch_name, G, n):
 
 
 @pytest.mark.parametrize("cfg,arch_name,G,n", [("c1", "tiny", 24, 64), ("c2", "full", 48, 64),
-                                               ("c4", "full", 32, 16), ("c4", "full", 64, 8)])
+                                               ("c4", "full", 32, 16), ("c4", "full", 48, 16),
+                                               ("c4", "full", 64, 8)])
 def test_score_bf16_within_pk_bound(scorers, cfg, arch_name, G, n):
     gd = golden(cfg, G)
     if gd is None:
@@ -86,6 +87,27 @@ def test_score_bf16_within_pk_bound(scorers, cfg, arch_name, G, n):
     err = np.abs(got - want)
     print(f"bf16 {cfg} G={G}: max |err| {err.max():.3e} pK  mean {err.mean():.3e} pK")
     assert err.max() <= BF16_PK_TOL
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_score_full_512_pose_chunk(scorers, prec):
+    # one full 512-pose chunk at 48^3: the production launch shape (spectrum work
+    # buffers of 2 x 1.7 GB, byte offsets past 2^31), every stored score compared
+    want = golden_scores("c2", 48)
+    if want is None or len(want) < 256:
+        pytest.skip("no stored oracle scores for c2 G=48")
+    n = 512
+    _say(f"cf_score_poses {prec} c2 G=48 poses={n} (one chunk)")
+    b = synth.make_poses("c2", n)
+    got = _score(scorers[("full", prec)], b, 48)
+    m = min(n, len(want))
+    err = np.abs(got[:m] - want[:m])
+    print(f"{prec} c2 G=48 {n}-pose chunk: {m} poses compared, max |err| {err.max():.3e}  mean {err.mean():.3e}")
+    if prec == "fp32":
+        assert np.all(err <= score_tol(want[:m])), f"worst pose {int(err.argmax())}"
+    else:
+        assert err.max() <= BF16_PK_TOL
+    assert np.all(np.isfinite(got))
 
 
 def test_score_stage_latents_match_oracle(scorers, torch_mod):

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import weights
+from helpers import BF16_LATENT_TOL, weights
 
 pytestmark = pytest.mark.gpu
 
@@ -119,6 +119,44 @@ def test_voxelize_is_deterministic(scorers):
     a = s.voxelize(db, 48).cpu().numpy()
     c = s.voxelize(db, 48).cpu().numpy()
     assert np.array_equal(a, c)
+
+
+def _coincident_pose(n):
+    """n atoms on the centre of voxel (12, 12, 12) of a 24^3 grid centred on 0, |f| = 64."""
+    rng = np.random.default_rng(n)
+    F = (64.0 * rng.choice([-1.0, 1.0], size=(n, 19))).astype(np.float32)
+    F[:, 0] = 64.0
+    X = np.tile(np.array([[512, 512, 512]], np.int32), (n, 1))
+    lig = np.zeros(n, np.uint8)
+    lig[0] = 1
+    b = synth.PoseBatch(np.array([0, n], np.int32), X, F, lig, np.array([1], np.int32))
+    return b, np.zeros((1, 3), np.int64)
+
+
+def test_voxelize_dense_pose_within_the_range_budget(scorers):
+    # 60 coincident atoms at |f| = 64 use 3840 of a tile's 4096 budget: values up
+    # to 60 * 64 * 0.492 = 1890 feature units, exact in the fixed-point accumulators
+    _say("cf_voxelize 60 coincident atoms |f|=64 G=24")
+    b, cen = _coincident_pose(60)
+    s = scorers[("tiny", "fp32")]
+    got = s.voxelize(_db(b, cen), 24).cpu().numpy().astype(np.float64)
+    assert s.status()[0] == 0
+    want = oracle.splat_batch(b, cen, 24)
+    assert np.abs(want).max() > 1800.0
+    np.testing.assert_allclose(got, want, rtol=2e-6, atol=1e-5)
+
+
+def test_voxelize_reports_a_pose_beyond_the_range_budget(scorers):
+    # 70 coincident atoms at |f| = 64: channel 0 of the centre voxel would reach
+    # 70 * 64 * 0.492 = 2205 > 2048 feature units and wrap an int32 accumulator;
+    # the tile's budget (4480 > 4096) reports it instead
+    from paper_2104_04547_amd import cfabi
+    _say("cf_voxelize 70 coincident atoms |f|=64 G=24 (reported)")
+    b, cen = _coincident_pose(70)
+    s = scorers[("tiny", "fp32")]
+    s.voxelize(_db(b, cen), 24)
+    assert s.status()[0] == cfabi.CF_ERR_INVALID_ARG
+    assert "too dense" in cfabi.load().cf_last_error().decode()
 
 
 # ------------------------------------------------------------------ neighbour lists
@@ -243,8 +281,7 @@ def test_cnn3d_bf16_within_operand_rounding(scorers, torch_mod, arch_name, G):
     got = scorers[(arch_name, "bf16")].cnn3d(torch.from_numpy(grids).to(torch.bfloat16).cuda(), G).cpu().numpy()
     want = np.stack([oracle.cnn3d_forward(g, w, arch)[0] for g in grids])
     scale = np.abs(want).max()
-    # bfloat16 operands (8-bit mantissa) through the conv stack, float32 accumulation
-    np.testing.assert_allclose(got, want, rtol=3e-2, atol=3e-2 * scale)
+    np.testing.assert_allclose(got, want, rtol=BF16_LATENT_TOL, atol=BF16_LATENT_TOL * scale)
 
 
 # ------------------------------------------------------------------ SG-CNN

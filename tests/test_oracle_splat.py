@@ -173,3 +173,22 @@ def test_splat_atoms_outside_grid_contribute_nothing():
     c = np.zeros(3, dtype=np.int64)
     X = np.array([0, 0, 3 * 1024 + 600])   # > 1.5 A beyond the last voxel centre (1.5 A)
     assert not _one_atom(X, G, c).any()
+
+
+def test_splat_coincident_high_feature_atoms_closed_form():
+    # 100 atoms on one voxel centre with |f| = 64 (signs mixed per channel): the
+    # voxel holds the closed-form centre weight 1 / (1 + 6 e^-2 + 12 e^-4) times the
+    # feature sum, far beyond what a 2^-20 fixed-point int32 accumulator holds
+    # (+-2048), and the mass of every channel is conserved.
+    G = 24
+    c = np.array([0, 0, 0], np.int64)
+    n = 100
+    X = np.tile(np.array([[512, 512, 512]], np.int32), (n, 1))      # centre of voxel (12, 12, 12)
+    rng = np.random.default_rng(5)
+    F = (64.0 * rng.choice([-1.0, 1.0], size=(n, 19))).astype(np.float32)
+    F[:, 0] = 64.0                                                   # channel 0: all +64
+    g = oracle.splat_pose(X, F, c, G)
+    Z = 1.0 + 6.0 * math.exp(-2.0) + 12.0 * math.exp(-4.0)
+    np.testing.assert_allclose(g[12, 12, 12], F.astype(np.float64).sum(0) / Z, rtol=1e-13, atol=1e-9)
+    assert g[12, 12, 12, 0] > 2048.0
+    np.testing.assert_allclose(g.sum(axis=(0, 1, 2)), F.astype(np.float64).sum(0), rtol=0, atol=1e-9)
