@@ -184,7 +184,7 @@ int64_t scratch_after(const cf_ctx *c, int G, int64_t n, int64_t atoms) {
   int64_t work = 0;
   for (size_t i = 0; i < c->conv.size(); ++i) {
     // the frequency-domain path's spectra, wherever it may be selected
-    if (c->bf16 && cf::fft_conv_ok(c->conv[i], D)) work = std::max(work, cf::fft_conv_work_bytes(c->conv[i], D, n));
+    if (cf::fft_conv_ok(c->conv[i], D)) work = std::max(work, cf::fft_conv_work_bytes(c->conv[i], D, n));
     D = conv_out_dim(D, c->conv[i].k, c->conv[i].stride);
     const int64_t need = n * D * D * D * c->conv[i].cout_store * (int64_t)elem_size(c);
     if (i < c->act.size()) grow(c->act[i], need);
@@ -314,7 +314,7 @@ int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s, hipEvent_t 
         cf::fft_conv_stage_cost(2, Lp, D, np, &flop, &bytes);
         cf::fft_conv_stage_cost(0, L, D, np, &f2, &b2);
         // the activation between them moves only if stored (written once, not read back)
-        const double act = (double)np * D * D * D * Lp.cout_store * 2.0;
+        const double act = (double)np * D * D * D * Lp.cout_store * elem_size(c);
         tend(c, s, e, "conv" + std::to_string(i - 1) + ".fft32.mid", flop + f2, bytes + b2 - act * (keep ? 1.0 : 2.0));
       } else {
         CF_HIP(cf::launch_fft_conv(L, t[i], res, c->act[i].p, np, D, c->convwork.p, s, 0));
@@ -608,6 +608,7 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     L.res_src = rs;
     L.cin_pad = cin_pad;
     L.in_cm4 = (i == 0 && c->bf16) ? 1 : 0;
+    L.spec_f32 = c->bf16 ? 0 : 1;
     L.cout_pad32 = (co + 31) / 32 * 32;
     L.cout_store = c->bf16 ? (co + 15) / 16 * 16 : (co + 7) / 8 * 8;
     std::vector<float> bf(L.cout_pad32, 0.0f);
@@ -633,7 +634,7 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
       L.wbytes4 = (int64_t)(pk4.size() * sizeof(bf16_t));
       rc = alloc_weight(c, &L.wpk4, pk4.size() * sizeof(bf16_t), pk4.data());
     }
-    if (!rc && c->bf16 && cf::fft_conv_layer_ok(L)) {
+    if (!rc && cf::fft_conv_layer_ok(L)) {
       // frequency-domain path: in-plane spectra of the folded weights, built on the device
       L.gspec_bytes = cf::fft_conv_gspec_bytes(L);
       rc = alloc_weight(c, &L.gspec, (size_t)L.gspec_bytes, nullptr);
@@ -1076,6 +1077,9 @@ int cf_stream_status(cf_ctx *c, void *stream, int64_t *need_cov, int64_t *need_n
     case cf::kDevBadFeature: return fail(CF_ERR_INVALID_ARG, "feature value not finite or |value| > 64");
     case cf::kDevPoseTooLarge: return fail(CF_ERR_INVALID_ARG, "a pose has more than 4096 atoms");
     case cf::kDevBadGraph: return fail(CF_ERR_INVALID_ARG, "neighbour list references an atom of another pose");
+    case cf::kDevGridRange:
+      return fail(CF_ERR_INVALID_ARG, "atoms too dense for the grid accumulators: over one 2 x 4 x G voxel tile the "
+                                      "sum of ceil(max |feature|) of the atoms whose 1.5 A reach overlaps it exceeds 4096");
     default: return fail(CF_ERR_INVALID_ARG, "device reported an invalid input");
   }
 }
@@ -1161,9 +1165,10 @@ int cf_autotune(cf_ctx *c, int G, int32_t n_poses, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   const int np = std::min(n_poses, chunk_poses(c, G, n_poses));
   if ((rc = ensure_act(c, G, np))) return rc;
-  // deterministic non-zero inputs: small constant activations
-  CF_HIP(hipMemsetAsync(c->grid.p, 0x3c, c->grid.n, s));
-  for (auto &b : c->act) CF_HIP(hipMemsetAsync(b.p, 0x3c, b.n, s));
+  // seeded random activations (constant operands would time a higher clock)
+  CF_HIP(cf::launch_fill_random(c->grid.p, (int64_t)c->grid.n, c->bf16, 1, s));
+  for (size_t i = 0; i < c->act.size(); ++i)
+    CF_HIP(cf::launch_fill_random(c->act[i].p, (int64_t)c->act[i].n, c->bf16, 2 + i, s));
   std::vector<int> best;
   const char *ve = getenv("CF_AUTOTUNE_VERBOSE");
   const bool verbose = ve && ve[0] && ve[0] != '0';

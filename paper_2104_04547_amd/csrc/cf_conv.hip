@@ -23,6 +23,8 @@
 //     even/odd-interleaved within a chunk so a lane's four K values are
 //     contiguous).  Accumulation is fp32 in both.
 //   * epilogue: + folded bias, + residual tensor, ReLU, convert, store.
+#include <algorithm>
+
 #include "cf_internal.h"
 
 namespace cf {
@@ -917,7 +919,7 @@ const char *conv_variant_name(int v) {
 }
 
 bool conv_variant_ok(int v, const ConvLayer &L, int bf16, int D_in) {
-  if (v == kFftVariant) return bf16 && fft_conv_ok(L, D_in);
+  if (v == kFftVariant) return (bf16 ? !L.spec_f32 : L.spec_f32) && fft_conv_ok(L, D_in);
   if (v < 0 || v >= kNumVariants) return false;
   const Variant &V = kVariants[v];
   if (V.pairs == 2) return bf16 && L.wpk4 && V.ks == L.k && V.s == L.stride && L.cout_pad32 % V.nt == 0 && L.cin_pad % 4 == 0;
@@ -927,10 +929,11 @@ bool conv_variant_ok(int v, const ConvLayer &L, int bf16, int D_in) {
 }
 
 int conv_default_variant(const ConvLayer &L, int D_in, int bf16) {
-  // measured on MI355X at 48^3: bf16 7^3 stride-1 layers in the frequency domain
-  // (3x the tap-pair kernel), tap quads for the 19-channel first layer, tap pairs
-  // for the 128-column stride-2 layer (two poses per workgroup); fp32 has neither
-  if (bf16 && L.k == 7 && conv_variant_ok(kFftVariant, L, bf16, D_in)) return kFftVariant;
+  // measured on MI355X at 48^3: 7^3 stride-1 layers in the frequency domain (bf16:
+  // 3x the tap-pair kernel), tap quads for the 19-channel first layer, tap pairs
+  // for the 128-column stride-2 layer (two poses per workgroup); fp32 has no tap
+  // kernels
+  if (L.k == 7 && conv_variant_ok(kFftVariant, L, bf16, D_in)) return kFftVariant;
   const int pref[] = {12, 40, 41, 17, 20, 19, 23, 26, 28, 4, 3, 6, 1, 0, 2, 5, 7, 8, 9, 10, 11, 13, 14, 15, 16, 18,
                       21, 22, 24, 25, 27, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39, 42, 43, 44, 45, 46};
   for (int v : pref)
@@ -942,6 +945,33 @@ bool conv_variant_is_fft(int v) { return v == kFftVariant; }
 
 int64_t conv_work_bytes(int v, const ConvLayer &L, int D_in, int n_poses) {
   return v == kFftVariant ? fft_conv_work_bytes(L, D_in, n_poses) : 0;
+}
+
+namespace {
+// Seeded values uniform in [0, 0.5) (SplitMix64 finaliser of seed + index): the
+// autotuner times kernels on data that toggles like real activations, since
+// the chip sustains a higher clock on constant operands.
+__global__ __launch_bounds__(256) void k_fill_random(void *p, int64_t n, int bf16, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const float v = (float)(z >> 40) * (0.5f / 16777216.0f);
+    if (bf16)
+      reinterpret_cast<bf16_t *>(p)[i] = (bf16_t)v;
+    else
+      reinterpret_cast<float *>(p)[i] = v;
+  }
+}
+}  // namespace
+
+hipError_t launch_fill_random(void *p, int64_t bytes, int bf16, uint64_t seed, hipStream_t s) {
+  const int64_t n = bytes / (bf16 ? 2 : 4);
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)blocks), dim3(256), 0, s, p, n, bf16, seed);
+  return hipGetLastError();
 }
 
 hipError_t launch_conv(int variant, const ConvLayer &L, int bf16, const void *in, const void *res,

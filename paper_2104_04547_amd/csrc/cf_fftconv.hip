@@ -25,6 +25,8 @@
 // Spectrum layout (bf16): [col][pose][z][chunk][re | im][8 channels] -- 64 bytes
 // per 8 channels, so a (column, pose block) of the z-correlation is one
 // contiguous run of rows, and one MFMA K step (16 deep) is 8 channels x (re, im).
+#include <type_traits>
+
 #include "cf_internal.h"
 #include "cf_fft32.h"
 
@@ -62,9 +64,10 @@ constexpr int kPanelRows = 288;                                // LDS rows of on
 constexpr int kColThreads = 128;
 
 // LDS of the plane kernels: the plane region (the larger of the row spectra
-// [17][D + 1][8] complex and the bf16 spectrum of a plane), then Zp [32][8] complex
-__host__ __device__ constexpr int plane_lds_bytes(int D) {
-  return kNX * (D + 1) * 8 * 8 > kCols * 16 * 2 ? kNX * (D + 1) * 8 * 8 : kCols * 16 * 2;
+// [17][D + 1][8] complex and the spectrum of a plane, bf16 or fp32), then Zp
+// [32][8] complex
+__host__ __device__ constexpr int plane_lds_bytes(int D, bool f32 = false) {
+  return kNX * (D + 1) * 8 * 8 > kCols * 16 * (f32 ? 4 : 2) ? kNX * (D + 1) * 8 * 8 : kCols * 16 * (f32 ? 4 : 2);
 }
 constexpr int kZpBytes = 32 * 8 * 8;
 
@@ -72,10 +75,19 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
   return (uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)lo) | ((uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)hi) << 16);
 }
 
-// One complex value of channel c from a spectrum row [col][re | im][8] bf16: lane
-// pairs (c, c ^ 1) read two channels at once (even lanes the re pair, odd lanes
-// the im pair) and swap halves.  Both lanes of a pair must be active.
-__device__ inline void spec_get(const uint32_t *Yw, int col, int c, float &r, float &i) {
+// One complex value of channel c from a spectrum row [col][re | im][8]: fp32
+// directly; bf16 by lane pairs (c, c ^ 1) that read two channels at once (even
+// lanes the re pair, odd lanes the im pair) and swap halves, so both lanes of a
+// pair must be active.
+template <bool F32>
+__device__ inline void spec_get(const void *Y, int col, int c, float &r, float &i) {
+  if constexpr (F32) {
+    const float *Yf = reinterpret_cast<const float *>(Y);
+    r = Yf[col * 16 + c];
+    i = Yf[col * 16 + 8 + c];
+    return;
+  }
+  const uint32_t *Yw = reinterpret_cast<const uint32_t *>(Y);
   const bool odd = c & 1;
   const uint32_t two = Yw[col * 8 + (odd ? 4 : 0) + (c >> 1)];
   const float lo = __uint_as_float(two << 16), hi = __uint_as_float(two & 0xffff0000u);
@@ -84,41 +96,50 @@ __device__ inline void spec_get(const uint32_t *Yw, int col, int c, float &r, fl
   i = odd ? hi : other;
 }
 
-// The inverse of spec_get: lane pairs swap halves so that each lane stores two
-// channels as one 32-bit word, rounded to bf16.
-__device__ inline void spec_put(uint32_t *O, int col, int c, float r, float i) {
+// The inverse of spec_get: fp32 directly; bf16 lane pairs swap halves so that
+// each lane stores two channels as one 32-bit word, rounded to bf16.
+template <bool F32>
+__device__ inline void spec_put(void *Ov, int col, int c, float r, float i) {
+  if constexpr (F32) {
+    float *Of = reinterpret_cast<float *>(Ov);
+    Of[col * 16 + c] = r;
+    Of[col * 16 + 8 + c] = i;
+    return;
+  }
+  uint32_t *O = reinterpret_cast<uint32_t *>(Ov);
   const bool odd = c & 1;
   const float other = __shfl_xor(odd ? r : i, 1);
   O[col * 8 + (odd ? 4 : 0) + (c >> 1)] = pack_bf16x2(odd ? other : r, odd ? i : other);
 }
 
 // inverse, all 256 threads (ky = tid >> 3, c = tid & 7): Zp[ky][c] = H(Y0)[ky] + i H(Y16)[ky]
-__device__ inline void dc_nyquist_pack(const bf16_t *Y, float2 *Zp, int tid) {
-  const uint32_t *Yw = reinterpret_cast<const uint32_t *>(Y);
+template <bool F32>
+__device__ inline void dc_nyquist_pack(const void *Y, float2 *Zp, int tid) {
   const int ky = tid >> 3, c = tid & 7, m = (32 - ky) & 31;
   float ar, ai, br, bi, cr, ci, dr, di;
-  spec_get(Yw, ky * kNX, c, ar, ai);               // Y0[ky]
-  spec_get(Yw, m * kNX, c, br, bi);                // Y0[-ky]
-  spec_get(Yw, ky * kNX + kNX - 1, c, cr, ci);     // Y16[ky]
-  spec_get(Yw, m * kNX + kNX - 1, c, dr, di);      // Y16[-ky]
+  spec_get<F32>(Y, ky * kNX, c, ar, ai);               // Y0[ky]
+  spec_get<F32>(Y, m * kNX, c, br, bi);                // Y0[-ky]
+  spec_get<F32>(Y, ky * kNX + kNX - 1, c, cr, ci);     // Y16[ky]
+  spec_get<F32>(Y, m * kNX + kNX - 1, c, dr, di);      // Y16[-ky]
   const float h0r = 0.5f * (ar + br), h0i = 0.5f * (ai - bi);
   const float h1r = 0.5f * (cr + dr), h1i = 0.5f * (ci - di);
   Zp[ky * 8 + c] = make_float2(h0r - h1i, h0i + h1r);
 }
 
 // forward, all 256 threads: X0 and X16 at ky from Zp (the transform of t0 + i t16)
-__device__ inline void dc_nyquist_split(const float2 *Zp, uint32_t *O, int tid) {
+template <bool F32>
+__device__ inline void dc_nyquist_split(const float2 *Zp, void *O, int tid) {
   const int ky = tid >> 3, c = tid & 7, m = (32 - ky) & 31;
   const float2 a = Zp[ky * 8 + c], b = Zp[m * 8 + c];
-  spec_put(O, ky * kNX, c, 0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
-  spec_put(O, ky * kNX + kNX - 1, c, 0.5f * (a.y + b.y), -0.5f * (a.x - b.x));
+  spec_put<F32>(O, ky * kNX, c, 0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+  spec_put<F32>(O, ky * kNX + kNX - 1, c, 0.5f * (a.y + b.y), -0.5f * (a.x - b.x));
 }
 
 // inverse columns, step 1 (before the barrier that frees the spectrum): columns 1 .. 15
-__device__ inline void col_inv_load(const bf16_t *Y, int kxp, int c, float (&re)[32], float (&im)[32]) {
-  const uint32_t *Yw = reinterpret_cast<const uint32_t *>(Y);
+template <bool F32>
+__device__ inline void col_inv_load(const void *Y, int kxp, int c, float (&re)[32], float (&im)[32]) {
 #pragma unroll
-  for (int ky = 0; ky < 32; ++ky) spec_get(Yw, ky * kNX + kxp, c, re[ky], im[ky]);
+  for (int ky = 0; ky < 32; ++ky) spec_get<F32>(Y, ky * kNX + kxp, c, re[ky], im[ky]);
 }
 
 // inverse columns, step 2 (after it): the packed column from Zp
@@ -151,12 +172,13 @@ __device__ inline void col_fwd_load(const float2 *T, int kxp, int c, int D, floa
 }
 
 // forward columns, after fft32<false>: the spectrum column into O = [col][re | im][8]
-// bf16, or the packed column into Zp
-__device__ inline void col_fwd_store(uint32_t *O, float2 *Zp, int kxp, int c, const float (&re)[32],
+// (bf16 or fp32), or the packed column into Zp
+template <bool F32>
+__device__ inline void col_fwd_store(void *O, float2 *Zp, int kxp, int c, const float (&re)[32],
                                      const float (&im)[32]) {
   if (kxp) {
 #pragma unroll
-    for (int ky = 0; ky < 32; ++ky) spec_put(O, ky * kNX + kxp, c, re[ky], im[ky]);
+    for (int ky = 0; ky < 32; ++ky) spec_put<F32>(O, ky * kNX + kxp, c, re[ky], im[ky]);
   } else {
 #pragma unroll
     for (int ky = 0; ky < 32; ++ky) Zp[ky * 8 + c] = make_float2(re[ky], im[ky]);
@@ -203,24 +225,32 @@ __device__ inline void row_inv_load(const float2 *T, int y, int c0, int D, float
 // lanes (y, channel pair) of one x read one contiguous run; the half spectrum of
 // the rows is [kx][y (pitch D + 1)][8] complex.
 // One workgroup per (z, pose, chunk), grid (D, np, nch) in XCD order: the chunks
-// of one plane run under one L2, where their 32-byte pieces of each spectrum row
-// (and of each input voxel) meet.  in: [P][D][D][D][cin_pad] bf16.
-template <int DT>
-__global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in, bf16_t *__restrict__ xs, int np,
+// of one plane run under one L2, where their pieces of each spectrum row (and of
+// each input voxel) meet.  in: [P][D][D][D][cin_pad] of bf16 (F32 = false) or
+// float; spectrum rows of the same type.
+template <int DT, bool F32>
+__global__ __launch_bounds__(256) void k_fft_fwd2d(const void *__restrict__ in_v, void *__restrict__ xs_v, int np,
                                                    int D_rt, int cin_pad, int nch) {
+  using act_t = typename std::conditional<F32, float, bf16_t>::type;
+  constexpr int kEsz = sizeof(act_t), kQ = 2 * kEsz / 2;  // 16-byte pieces per spectrum column of 8 channels
+  const act_t *in = reinterpret_cast<const act_t *>(in_v);
+  act_t *xs = reinterpret_cast<act_t *>(xs_v);
   const int D = DT ? DT : D_rt;
   int chunk, z, p;
   xcd_order(z, p, chunk);
   // one dynamic LDS block (fft_lds_bytes): the plane, then (after its rows are in
   // registers) the row spectra, then the output staging
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
-  bf16_t *plane = reinterpret_cast<bf16_t *>(dyn_lds);  // [x][y][8]
+  act_t *plane = reinterpret_cast<act_t *>(dyn_lds);    // [x][y][8]
   float2 *T = reinterpret_cast<float2 *>(dyn_lds);      // [kx][y][8]
   const int tid = threadIdx.x, DP = D + 1;
-  const bf16_t *src = in + (((int64_t)p * D + z) * D * D) * cin_pad + chunk * 8;
+  const act_t *src = in + (((int64_t)p * D + z) * D * D) * cin_pad + chunk * 8;
   for (int v = tid; v < D * D; v += 256) {
     const int y = v / D, x = v - y * D;
-    *reinterpret_cast<uint4 *>(plane + (x * DP + y) * 8) = *reinterpret_cast<const uint4 *>(src + (int64_t)v * cin_pad);
+#pragma unroll
+    for (int q = 0; q < kEsz / 2; ++q)
+      reinterpret_cast<uint4 *>(plane + (x * DP + y) * 8)[q] =
+          reinterpret_cast<const uint4 *>(src + (int64_t)v * cin_pad)[q];
   }
   __syncthreads();
   // rows along x, two channels per complex transform
@@ -232,9 +262,15 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in
 #pragma unroll
     for (int x = 0; x < 32; ++x) {
       if (roww && x < D) {
-        const uint32_t two = *reinterpret_cast<const uint32_t *>(plane + (x * DP + y) * 8 + c0);
-        re[x] = __uint_as_float(two << 16);
-        im[x] = __uint_as_float(two & 0xffff0000u);
+        if constexpr (F32) {
+          const float2 two = *reinterpret_cast<const float2 *>(plane + (x * DP + y) * 8 + c0);
+          re[x] = two.x;
+          im[x] = two.y;
+        } else {
+          const uint32_t two = *reinterpret_cast<const uint32_t *>(plane + (x * DP + y) * 8 + c0);
+          re[x] = __uint_as_float(two << 16);
+          im[x] = __uint_as_float(two & 0xffff0000u);
+        }
       } else {
         re[x] = 0.0f;
         im[x] = 0.0f;
@@ -256,61 +292,57 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d(const bf16_t *__restrict__ in
     fft32<false>(re, im);
   }
   __syncthreads();
-  uint32_t *O = reinterpret_cast<uint32_t *>(T);  // [col][re | im][8]
-  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D));
-  if (colw) col_fwd_store(O, Zp, kxp, c, re, im);
+  act_t *O = reinterpret_cast<act_t *>(T);  // [col][re | im][8]
+  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D, F32));
+  if (colw) col_fwd_store<F32>(O, Zp, kxp, c, re, im);
   __syncthreads();
-  dc_nyquist_split(Zp, O, tid);
+  dc_nyquist_split<F32>(Zp, O, tid);
   __syncthreads();
-  const int64_t rowb = (int64_t)nch * 16;  // bf16 elements per (col, pose, z) row
-  for (int e = tid; e < kCols * 2; e += 256) {
-    const int col = e >> 1, h = e & 1;
-    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * 8) =
-        *reinterpret_cast<const uint4 *>(O + col * 8 + h * 4);
+  const int64_t rowb = (int64_t)nch * 16;  // elements per (col, pose, z) row
+  for (int e = tid; e < kCols * kQ; e += 256) {
+    const int col = e / kQ, h = e % kQ;
+    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * (16 / kEsz)) =
+        *reinterpret_cast<const uint4 *>(O + col * 16 + h * (16 / kEsz));
   }
 }
 
 // ---------------------------------------------------------------- inverse
 
 // One workgroup per (z, pose, output chunk), grid (D, np, nco) in XCD order.
-// out, res: [P][D][D][D][cout_store] bf16.
-template <int DT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_inv2d(const bf16_t *__restrict__ ys, const float *__restrict__ bias,
-                                                   const bf16_t *__restrict__ res, bf16_t *__restrict__ out, int np,
-                                                   int D_rt, int nco, int cout_store) {
+// out, res: [P][D][D][D][cout_store] of bf16 (F32 = false) or float.
+template <int DT, bool F32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_inv2d(
+    const void *__restrict__ ys_v, const float *__restrict__ bias, const void *__restrict__ res_v,
+    void *__restrict__ out_v, int np, int D_rt, int nco, int cout_store) {
+  using act_t = typename std::conditional<F32, float, bf16_t>::type;
+  constexpr int kEsz = sizeof(act_t), kQ = kEsz;  // 16-byte pieces per spectrum column of 8 channels
+  const act_t *ys = reinterpret_cast<const act_t *>(ys_v);
+  const act_t *res = reinterpret_cast<const act_t *>(res_v);
+  act_t *out = reinterpret_cast<act_t *>(out_v);
   const int D = DT ? DT : D_rt;
   int chunk, z, p;
   xcd_order(z, p, chunk);
   // one dynamic LDS block (fft_lds_bytes): the spectrum, then (after its columns
   // are in registers) the column transforms, then the output plane
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
-  bf16_t *Y = reinterpret_cast<bf16_t *>(dyn_lds);  // [col][re | im][8]
+  act_t *Y = reinterpret_cast<act_t *>(dyn_lds);    // [col][re | im][8]
   float2 *T = reinterpret_cast<float2 *>(dyn_lds);  // [kx][y][8]; later [x][y][8] floats
   const int tid = threadIdx.x, DP = D + 1;
   const int64_t rowb = (int64_t)nco * 16;
-  for (int e = tid; e < kCols * 2; e += 256) {
-    const int col = e >> 1, h = e & 1;
-    *reinterpret_cast<uint4 *>(Y + col * 16 + h * 8) =
-        *reinterpret_cast<const uint4 *>(ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * 8);
+  for (int e = tid; e < kCols * kQ; e += 256) {
+    const int col = e / kQ, h = e % kQ;
+    *reinterpret_cast<uint4 *>(Y + col * 16 + h * (16 / kEsz)) = *reinterpret_cast<const uint4 *>(
+        ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * (16 / kEsz));
   }
   __syncthreads();
-  // columns along ky; lane pairs (c, c ^ 1) load two channels at once (even lanes
-  // the re pair, odd lanes the im pair) and swap halves
+  // columns along ky
   {
     const bool colw = tid < kNX * 8;
     const int kx = tid >> 3, c = tid & 7;
-    const bool odd = c & 1;
-    const uint32_t *Yw = reinterpret_cast<const uint32_t *>(Y);
     float re[32], im[32];
     if (colw) {
 #pragma unroll
-      for (int ky = 0; ky < 32; ++ky) {
-        const uint32_t two = Yw[(ky * kNX + kx) * 8 + (odd ? 4 : 0) + (c >> 1)];
-        const float lo = __uint_as_float(two << 16), hi = __uint_as_float(two & 0xffff0000u);
-        const float other = __shfl_xor(odd ? lo : hi, 1);  // even lanes send the odd channel's re, ...
-        re[ky] = odd ? other : lo;
-        im[ky] = odd ? hi : other;
-      }
+      for (int ky = 0; ky < 32; ++ky) spec_get<F32>(Y, ky * kNX + kx, c, re[ky], im[ky]);
     }
     __syncthreads();  // the spectrum is in registers; its LDS becomes the transforms
     if (colw) {
@@ -361,17 +393,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const float4 f0 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8);
     const float4 f1 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8 + 4);
     f[0] = f0.x; f[1] = f0.y; f[2] = f0.z; f[3] = f0.w; f[4] = f1.x; f[5] = f1.y; f[6] = f1.z; f[7] = f1.w;
-    if (res) {
-      const uint4 r = *reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store);
-      const bf16_t *rb = reinterpret_cast<const bf16_t *>(&r);
+    if constexpr (F32) {
+      if (res) {
+        const float4 r0 = *reinterpret_cast<const float4 *>(res + base + (int64_t)v * cout_store);
+        const float4 r1 = *reinterpret_cast<const float4 *>(res + base + (int64_t)v * cout_store + 4);
+        f[0] += r0.x; f[1] += r0.y; f[2] += r0.z; f[3] += r0.w; f[4] += r1.x; f[5] += r1.y; f[6] += r1.z; f[7] += r1.w;
+      }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) f[q] += (float)rb[q];
+      for (int q = 0; q < 8; ++q) f[q] = f[q] > 0.0f ? f[q] : 0.0f;
+      float4 *dst = reinterpret_cast<float4 *>(out + base + (int64_t)v * cout_store);
+      dst[0] = make_float4(f[0], f[1], f[2], f[3]);
+      dst[1] = make_float4(f[4], f[5], f[6], f[7]);
+    } else {
+      if (res) {
+        const uint4 r = *reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store);
+        const bf16_t *rb = reinterpret_cast<const bf16_t *>(&r);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) f[q] += (float)rb[q];
+      }
+      uint4 o;
+      bf16_t *ob = reinterpret_cast<bf16_t *>(&o);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ob[q] = (bf16_t)(f[q] > 0.0f ? f[q] : 0.0f);
+      *reinterpret_cast<uint4 *>(out + base + (int64_t)v * cout_store) = o;
     }
-    uint4 o;
-    bf16_t *ob = reinterpret_cast<bf16_t *>(&o);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) ob[q] = (bf16_t)(f[q] > 0.0f ? f[q] : 0.0f);
-    *reinterpret_cast<uint4 *>(out + base + (int64_t)v * cout_store) = o;
   }
 }
 
@@ -385,37 +430,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // chunking of layer i + 1's input.  LDS: the spectrum / column transforms
 // (fft_lds_bytes) and, with a residual or a stored output, the activation plane
 // [y][x][8] bf16.
-template <int DT>
+template <int DT, bool F32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_mid(
-    const bf16_t *__restrict__ ys, const float *__restrict__ bias, const bf16_t *__restrict__ res,
-    bf16_t *__restrict__ out, bf16_t *__restrict__ xs, int np, int D_rt, int nch, int cout_store, int lds_spec) {
+    const void *__restrict__ ys_v, const float *__restrict__ bias, const void *__restrict__ res_v,
+    void *__restrict__ out_v, void *__restrict__ xs_v, int np, int D_rt, int nch, int cout_store, int lds_spec) {
+  using act_t = typename std::conditional<F32, float, bf16_t>::type;
+  constexpr int kEsz = sizeof(act_t), kQ = kEsz;  // 16-byte pieces per spectrum column of 8 channels
+  const act_t *ys = reinterpret_cast<const act_t *>(ys_v);
+  const act_t *res = reinterpret_cast<const act_t *>(res_v);
+  act_t *out = reinterpret_cast<act_t *>(out_v);
+  act_t *xs = reinterpret_cast<act_t *>(xs_v);
   const int D = DT ? DT : D_rt;
   int chunk, z, p;
   xcd_order(z, p, chunk);
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
-  bf16_t *Y = reinterpret_cast<bf16_t *>(dyn_lds);                 // [col][re | im][8]
+  act_t *Y = reinterpret_cast<act_t *>(dyn_lds);                  // [col][re | im][8]
   float2 *T = reinterpret_cast<float2 *>(dyn_lds);                 // [kx][y][8]
-  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D));  // [32][8] packed DC / Nyquist column
-  bf16_t *R = reinterpret_cast<bf16_t *>(dyn_lds + lds_spec);      // [y][x][8]: residual in, activation out
+  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D, F32));  // [32][8] packed DC / Nyquist column
+  act_t *R = reinterpret_cast<act_t *>(dyn_lds + lds_spec);        // [y][x][8]: residual in, activation out
   const int tid = threadIdx.x;
   const int64_t rowb = (int64_t)nch * 16;
   const int64_t base = (((int64_t)p * D + z) * D * D) * cout_store + chunk * 8;
-  for (int e = tid; e < kCols * 2; e += 256) {
-    const int col = e >> 1, h = e & 1;
-    *reinterpret_cast<uint4 *>(Y + col * 16 + h * 8) =
-        *reinterpret_cast<const uint4 *>(ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * 8);
+  for (int e = tid; e < kCols * kQ; e += 256) {
+    const int col = e / kQ, h = e % kQ;
+    *reinterpret_cast<uint4 *>(Y + col * 16 + h * (16 / kEsz)) = *reinterpret_cast<const uint4 *>(
+        ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * (16 / kEsz));
   }
   if (res)
     for (int v = tid; v < D * D; v += 256)
-      *reinterpret_cast<uint4 *>(R + v * 8) = *reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store);
+#pragma unroll
+      for (int q = 0; q < kEsz / 2; ++q)
+        reinterpret_cast<uint4 *>(R + v * 8)[q] = reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store)[q];
   __syncthreads();
   const bool colw = tid < kColThreads;
   const int kxp = tid >> 3, c = tid & 7;
   // inverse columns along ky (as k_fft_inv2d)
   {
     float re[32], im[32];
-    dc_nyquist_pack(Y, Zp, tid);
-    if (colw && kxp) col_inv_load(Y, kxp, c, re, im);
+    dc_nyquist_pack<F32>(Y, Zp, tid);
+    if (colw && kxp) col_inv_load<F32>(Y, kxp, c, re, im);
     __syncthreads();
     if (colw) {
       if (!kxp) col_inv_load_dc(Zp, c, re, im);
@@ -424,8 +477,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
   }
   __syncthreads();
-  // rows along x: inverse of two channels, epilogue, bf16, then their forward
-  // transform (the next layer's input rows)
+  // rows along x: inverse of two channels, epilogue (bf16 rounding in the bf16
+  // form), then their forward transform (the next layer's input rows)
   {
     const int r = tid - kColThreads;
     const bool roww = r >= 0 && r < D * 4;
@@ -442,17 +495,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       for (int x = 0; x < 32; ++x) {
         if (x < D) {
           float v0 = re[x] * kScale + b0, v1 = im[x] * kScale + b1;
-          if (res) {
-            const uint32_t two = *reinterpret_cast<const uint32_t *>(R + (y * D + x) * 8 + c0);
-            v0 += __uint_as_float(two << 16);
-            v1 += __uint_as_float(two & 0xffff0000u);
+          if constexpr (F32) {
+            if (res) {
+              const float2 two = *reinterpret_cast<const float2 *>(R + (y * D + x) * 8 + c0);
+              v0 += two.x;
+              v1 += two.y;
+            }
+            v0 = v0 > 0.0f ? v0 : 0.0f;
+            v1 = v1 > 0.0f ? v1 : 0.0f;
+            if (out) *reinterpret_cast<float2 *>(R + (y * D + x) * 8 + c0) = make_float2(v0, v1);
+            re[x] = v0;
+            im[x] = v1;
+          } else {
+            if (res) {
+              const uint32_t two = *reinterpret_cast<const uint32_t *>(R + (y * D + x) * 8 + c0);
+              v0 += __uint_as_float(two << 16);
+              v1 += __uint_as_float(two & 0xffff0000u);
+            }
+            const bf16_t h0 = (bf16_t)(v0 > 0.0f ? v0 : 0.0f), h1 = (bf16_t)(v1 > 0.0f ? v1 : 0.0f);
+            if (out)
+              *reinterpret_cast<uint32_t *>(R + (y * D + x) * 8 + c0) =
+                  (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+            re[x] = (float)h0;
+            im[x] = (float)h1;
           }
-          const bf16_t h0 = (bf16_t)(v0 > 0.0f ? v0 : 0.0f), h1 = (bf16_t)(v1 > 0.0f ? v1 : 0.0f);
-          if (out)
-            *reinterpret_cast<uint32_t *>(R + (y * D + x) * 8 + c0) =
-                (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
-          re[x] = (float)h0;
-          im[x] = (float)h1;
         } else {
           re[x] = 0.0f;
           im[x] = 0.0f;
@@ -465,7 +531,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __syncthreads();
   if (out)
     for (int v = tid; v < D * D; v += 256)
-      *reinterpret_cast<uint4 *>(out + base + (int64_t)v * cout_store) = *reinterpret_cast<const uint4 *>(R + v * 8);
+#pragma unroll
+      for (int q = 0; q < kEsz / 2; ++q)
+        reinterpret_cast<uint4 *>(out + base + (int64_t)v * cout_store)[q] = reinterpret_cast<const uint4 *>(R + v * 8)[q];
   // forward columns along y (as k_fft_fwd2d)
   float re[32], im[32];
   if (colw) {
@@ -473,15 +541,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     fft32<false>(re, im);
   }
   __syncthreads();
-  uint32_t *O = reinterpret_cast<uint32_t *>(T);
-  if (colw) col_fwd_store(O, Zp, kxp, c, re, im);
+  act_t *O = reinterpret_cast<act_t *>(T);
+  if (colw) col_fwd_store<F32>(O, Zp, kxp, c, re, im);
   __syncthreads();
-  dc_nyquist_split(Zp, O, tid);
+  dc_nyquist_split<F32>(Zp, O, tid);
   __syncthreads();
-  for (int e = tid; e < kCols * 2; e += 256) {
-    const int col = e >> 1, h = e & 1;
-    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * 8) =
-        *reinterpret_cast<const uint4 *>(O + col * 8 + h * 4);
+  for (int e = tid; e < kCols * kQ; e += 256) {
+    const int col = e / kQ, h = e % kQ;
+    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * (16 / kEsz)) =
+        *reinterpret_cast<const uint4 *>(O + col * 16 + h * (16 / kEsz));
   }
 }
 
@@ -797,11 +865,167 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
+// The z-correlation with fp32 spectra on the fp32 matrix instruction (32x32x2):
+// the same blocking as k_fft_zconv_h (96 rows of (pose, z), the K walk in halves
+// of at most four channel chunks through an LDS panel), NT = 64 NB real columns
+// over two waves.  One K step (chunk, dz) is 16 deep (8 channels x re, im) and
+// takes eight MFMAs; MFMA j reads K indices j and 8 + j, so a lane's A fragment
+// is 8 contiguous floats of its row (khalf 0: re of the 8 channels, khalf 1: im)
+// and its B fragment the 8 matching weight values, both two 16-byte loads.
+template <int KS, int NB>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k_fft_zconv_f32(
+    const float *__restrict__ xs, const float *__restrict__ gp, float *__restrict__ ys, int np, int D, int nch,
+    int ppb, int gbytes) {
+  constexpr int P = (KS - 1) / 2, NT = 64 * NB, MB = 3, NBT = NT / 32, NTH = 128;
+  constexpr int PH = 4 * 64 + 16;                // panel row pitch (bytes): 4 chunks x 16 floats
+  constexpr int HALF = NT / 2, orow = HALF * 8, opitch = orow + 16;
+  constexpr int kLds = kRowsZH * opitch > kPanelRowsH * PH ? kRowsZH * opitch : kPanelRowsH * PH;
+  __shared__ __attribute__((aligned(16))) char lds[kLds];
+  int pblk, col, zero;
+  xcd_order(pblk, col, zero);
+  (void)zero;
+  const int p0 = pblk * ppb;
+  const int nvalid = min(ppb, np - p0);
+  const int rowf = nch * 16;  // floats per spectrum row
+  const int zrows = D + KS - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave_n = tid >> 6;
+  const int khalf = lane >> 5, lrow = lane & 31;
+  int rowoff[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    const int r = mb * 32 + lrow;
+    const int pl = r / D, zl = r % D;
+    rowoff[mb] = (pl < ppb ? (pl * zrows + zl) * PH : 0) + khalf * 32;
+  }
+  f32x16 acc[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
+
+  const int step_bytes = NBT * 2048, steps = nch * KS;
+  const __amdgpu_buffer_rsrc_t wrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(gp), (short)0, gbytes, 0x00020000);
+  const int wbase = col * steps * step_bytes + (wave_n * NB * 64 + lane) * 32;
+  if (col + 1 < (int)gridDim.y) {
+    // warm L2 with a slice of the next column's weights (as in k_fft_zconv)
+    const int colb = steps * step_bytes, slice = (colb + gridDim.x - 1) / gridDim.x;
+    const int off = (col + 1) * colb + pblk * slice + tid * 128;
+    if (tid * 128 < slice && off + 4 <= gbytes) {
+      const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(wrs, off, 0, 0);
+      if (v == 0x7fc00001u && np < 0) ys[0] = 0.0f;  // keeps the load; never true
+    }
+  }
+  const float *src = xs + ((int64_t)col * np + p0) * D * rowf;
+  for (int h0 = 0; h0 < nch; h0 += 4) {
+    const int nh = min(4, nch - h0);  // chunks in this half
+    if (h0) __syncthreads();           // the previous half's panel is read
+    {
+      constexpr int kIt = (kPanelRowsH * 16 + NTH - 1) / NTH;  // uint4 per thread, 16 per row
+      constexpr int kBatch = 9;
+      const int q16 = nh * 4, total = ppb * zrows * q16;
+#pragma unroll
+      for (int i0 = 0; i0 < kIt; i0 += kBatch) {
+        uint4 pv[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+          const int e = (i0 + i) * NTH + tid;
+          pv[i] = make_uint4(0, 0, 0, 0);
+          if (i0 + i < kIt && e < total) {
+            const int q = e % q16, rr = e / q16, pl = rr / zrows, zr = rr % zrows - P;
+            if (pl < nvalid && zr >= 0 && zr < D)
+              pv[i] = *reinterpret_cast<const uint4 *>(src + ((int64_t)pl * D + zr) * rowf + h0 * 16 + q * 4);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+          const int e = (i0 + i) * NTH + tid;
+          if (i0 + i < kIt && e < total) *reinterpret_cast<uint4 *>(lds + (e / q16) * PH + (e % q16) * 16) = pv[i];
+        }
+      }
+    }
+    __syncthreads();
+    const int hsteps = nh * KS, sbase = h0 * KS;
+    int nchunk = 0, ndz = 0;
+    uint4 bq[NB][2];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        bq[nb][q] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                  wrs, wbase + nb * 2048 + q * 16, sbase * step_bytes, 0));
+    for (int s = 0; s < hsteps; ++s) {
+      const int aoff = ndz * PH + nchunk * 64;
+      if (++ndz == KS) {
+        ndz = 0;
+        ++nchunk;
+      }
+      float a[MB][8];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const float4 a0 = *reinterpret_cast<const float4 *>(lds + rowoff[mb] + aoff);
+        const float4 a1 = *reinterpret_cast<const float4 *>(lds + rowoff[mb] + aoff + 16);
+        a[mb][0] = a0.x; a[mb][1] = a0.y; a[mb][2] = a0.z; a[mb][3] = a0.w;
+        a[mb][4] = a1.x; a[mb][5] = a1.y; a[mb][6] = a1.z; a[mb][7] = a1.w;
+      }
+      float b[NB][8];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        __builtin_memcpy(&b[nb][0], &bq[nb][0], 16);
+        __builtin_memcpy(&b[nb][4], &bq[nb][1], 16);
+      }
+      // the next step's weight fragments are in flight during this step's MFMAs
+      const int sn = min(s + 1, hsteps - 1);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          bq[nb][q] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                    wrs, wbase + nb * 2048 + q * 16, (sbase + sn) * step_bytes, 0));
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mb][j], b[nb][j], acc[mb][nb], 0, 0, 0);
+    }
+  }
+
+  // epilogue through LDS: rows of NT floats in the spectrum layout, then contiguous stores
+  __syncthreads();
+  float *ot = reinterpret_cast<float *>(lds);
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = mb * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int n = (wave_n * NB + nb) * 32 + lrow;
+        const int part = n / HALF, co = n % HALF;
+        ot[(row * opitch) / 4 + (co >> 3) * 16 + part * 8 + (co & 7)] = acc[mb][nb][r];
+      }
+    }
+  __syncthreads();
+  constexpr int q16 = orow / 16;
+  float *dst = ys + ((int64_t)col * np + p0) * D * (orow / 4);
+  for (int e = tid; e < nvalid * D * q16; e += NTH) {
+    const int q = e % q16, row = e / q16;
+    *reinterpret_cast<uint4 *>(dst + (int64_t)row * (orow / 4) + q * 4) =
+        *reinterpret_cast<const uint4 *>(lds + row * opitch + q * 16);
+  }
+}
+
 // ---------------------------------------------------------------- weights
 
-// One thread per (col, chunk, dz, 32-column block, lane): the 8 bf16 of one MFMA
-// B fragment.  w: folded fp32 weights [cout][cin][k][k][k].
-__global__ void k_fft_gspec(const float *__restrict__ w, bf16_t *__restrict__ gp, int cin, int cout, int nch, int KS,
+// One thread per (col, chunk, dz, 32-column block, lane): the 8 values of one MFMA
+// B fragment, bf16 or fp32 (element j is K index 8 * khalf + j, the order both
+// z-correlations read).  w: folded fp32 weights [cout][cin][k][k][k].
+template <typename T>
+__global__ void k_fft_gspec(const float *__restrict__ w, T *__restrict__ gp, int cin, int cout, int nch, int KS,
                             int nbt) {
   const int64_t total = (int64_t)kCols * nch * KS * nbt * 64;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -812,7 +1036,7 @@ __global__ void k_fft_gspec(const float *__restrict__ w, bf16_t *__restrict__ gp
   const int ky = col / kNX, kx = col % kNX, P = (KS - 1) / 2;
   const int n = nbk * 32 + (lane & 31), half = nbt * 16;
   const int part = n / half, co = n % half;
-  bf16_t v[8];
+  T v[8];
   for (int j = 0; j < 8; ++j) {
     const int k = 8 * (lane >> 5) + j, ci = chunk * 8 + (k & 7), xim = k >> 3;
     float gr = 0.0f, gi = 0.0f;
@@ -829,34 +1053,47 @@ __global__ void k_fft_gspec(const float *__restrict__ w, bf16_t *__restrict__ gp
     }
     // Y = X G:  Yr = Xr Gr - Xi Gi,  Yi = Xr Gi + Xi Gr
     const float b = part == 0 ? (xim == 0 ? gr : -gi) : (xim == 0 ? gi : gr);
-    v[j] = (bf16_t)b;
+    v[j] = (T)b;
   }
-  uint4 o;
-  __builtin_memcpy(&o, v, 16);
-  *reinterpret_cast<uint4 *>(gp + t * 8) = o;
+#pragma unroll
+  for (int q = 0; q < (int)sizeof(T) / 2; ++q) {
+    uint4 o;
+    __builtin_memcpy(&o, reinterpret_cast<const char *>(v) + 16 * q, 16);
+    reinterpret_cast<uint4 *>(gp + t * 8)[q] = o;
+  }
 }
 
 int nch_of(const ConvLayer &L) { return (L.cin + 7) / 8; }
 
 // dynamic LDS of the plane transforms: the plane region (the input plane and the
 // output staging fit in it) and the packed DC / Nyquist column
-size_t fft_lds_bytes(int D) { return (size_t)plane_lds_bytes(D) + kZpBytes; }
+size_t fft_lds_bytes(int D, bool f32) { return (size_t)plane_lds_bytes(D, f32) + kZpBytes; }
 int nbt_of(const ConvLayer &L) { return L.cout * 2 / 32; }
+int esz_of(const ConvLayer &L) { return L.spec_f32 ? 4 : 2; }
 
 }  // namespace
 
 bool fft_conv_layer_ok(const ConvLayer &L) {
+  if (L.spec_f32)  // the fp32 z-correlation covers 32 and 64 output channels
+    return L.stride == 1 && (L.k == 3 || L.k == 5 || L.k == 7) && L.cin <= 64 && L.cin_pad % 8 == 0 &&
+           (L.cout == 32 || L.cout == 64) && L.cout_store % 8 == 0;
   return L.stride == 1 && (L.k == 3 || L.k == 5 || L.k == 7) && L.cin <= 64 && L.cin_pad % 8 == 0 &&
          (L.cout == 16 || L.cout == 32 || L.cout == 64) && L.cout_store % 8 == 0;
 }
 
 bool fft_conv_ok(const ConvLayer &L, int D) {
   if (!L.gspec || !fft_conv_layer_ok(L) || D < 1 || D + L.k - 1 > kN || D > kDMax) return false;
+  if (L.spec_f32) {
+    const int ppb = kRowsZH / D;
+    return ppb >= 1 && ppb * (D + L.k - 1) <= kPanelRowsH;
+  }
   const int ppb = kRowsZ / D;
   return ppb >= 1 && ppb * (D + L.k - 1) <= kPanelRows;
 }
 
-int64_t fft_conv_gspec_bytes(const ConvLayer &L) { return (int64_t)kCols * nch_of(L) * L.k * nbt_of(L) * 1024; }
+int64_t fft_conv_gspec_bytes(const ConvLayer &L) {
+  return (int64_t)kCols * nch_of(L) * L.k * nbt_of(L) * 512 * esz_of(L);
+}
 
 // work buffer: the input spectrum rows at offset 0 (room for 8 chunks, the most a
 // layer takes), the output spectrum rows after them; fixed offsets, so that one
@@ -864,47 +1101,58 @@ int64_t fft_conv_gspec_bytes(const ConvLayer &L) { return (int64_t)kCols * nch_o
 int64_t fft_spec_in_elems(int D, int np) { return (int64_t)kCols * np * D * 8 * 16; }
 
 int64_t fft_conv_work_bytes(const ConvLayer &L, int D, int np) {
-  return (fft_spec_in_elems(D, np) + (int64_t)kCols * np * D * (L.cout / 8) * 16) * 2;
+  return (fft_spec_in_elems(D, np) + (int64_t)kCols * np * D * (L.cout / 8) * 16) * esz_of(L);
 }
 
 hipError_t fft_conv_prepare(ConvLayer &L, const float *w_folded_dev, hipStream_t s) {
   const int64_t total = (int64_t)kCols * nch_of(L) * L.k * nbt_of(L) * 64;
-  hipLaunchKernelGGL(k_fft_gspec, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w_folded_dev,
-                     reinterpret_cast<bf16_t *>(L.gspec), L.cin, L.cout, nch_of(L), L.k, nbt_of(L));
+  const dim3 grd((unsigned)((total + 255) / 256));
+  if (L.spec_f32)
+    hipLaunchKernelGGL(k_fft_gspec<float>, grd, dim3(256), 0, s, w_folded_dev, reinterpret_cast<float *>(L.gspec),
+                       L.cin, L.cout, nch_of(L), L.k, nbt_of(L));
+  else
+    hipLaunchKernelGGL(k_fft_gspec<bf16_t>, grd, dim3(256), 0, s, w_folded_dev, reinterpret_cast<bf16_t *>(L.gspec),
+                       L.cin, L.cout, nch_of(L), L.k, nbt_of(L));
   return hipGetLastError();
 }
 
 void fft_conv_stage_cost(int stage, const ConvLayer &L, int D, int np, double *flop, double *bytes) {
-  const double spec_in = (double)kCols * np * D * nch_of(L) * 32, spec_out = (double)kCols * np * D * (L.cout / 8) * 32;
+  const double e = esz_of(L);
+  const double spec_in = (double)kCols * np * D * nch_of(L) * 16 * e, spec_out = (double)kCols * np * D * (L.cout / 8) * 16 * e;
   const double vox = (double)np * D * D * D;
   if (stage == 0) {  // 2-D real FFTs of D x D planes zero-padded to 32 x 32: ~2.5 N^2 log2 N^2 FLOP each
     *flop = 2.5 * kN * kN * 10.0 * np * D * L.cin;
-    *bytes = vox * L.cin_pad * 2.0 + spec_in;
+    *bytes = vox * L.cin_pad * e + spec_in;
   } else if (stage == 1) {  // complex multiply-adds over (dz, ci) per column and output row
     *flop = 8.0 * L.cin * L.cout * L.k * D * kCols * np;
     *bytes = spec_in + spec_out + (double)L.gspec_bytes;
   } else {
     *flop = 2.5 * kN * kN * 10.0 * np * D * L.cout;
-    *bytes = spec_out + vox * L.cout_store * 2.0 * (L.res_src >= 0 ? 2 : 1);
+    *bytes = spec_out + vox * L.cout_store * e * (L.res_src >= 0 ? 2 : 1);
   }
 }
 
 bool fft_conv_fusable(const ConvLayer &L, const ConvLayer &Ln, int D) {
-  return fft_conv_ok(L, D) && fft_conv_ok(Ln, D) && L.cout == Ln.cin && Ln.cin_pad == L.cout_store;
+  return fft_conv_ok(L, D) && fft_conv_ok(Ln, D) && L.cout == Ln.cin && Ln.cin_pad == L.cout_store &&
+         L.spec_f32 == Ln.spec_f32;
 }
 
 hipError_t launch_fft_mid(const ConvLayer &L, const ConvLayer &Ln, const void *res, void *out, int np, int D,
                           void *work, hipStream_t s) {
   if (!fft_conv_fusable(L, Ln, D) || !work) return hipErrorInvalidValue;
   const int nch = L.cout / 8;
-  bf16_t *xs = reinterpret_cast<bf16_t *>(work);
-  bf16_t *ys = xs + fft_spec_in_elems(D, np);
-  const size_t spec = fft_lds_bytes(D), lds = spec + ((res || out) ? (size_t)D * D * 16 : 0);
-#define CF_MID(DT)                                                                                            \
-  hipLaunchKernelGGL(k_fft_mid<DT>, dim3(D, np, nch), dim3(256), lds, s, ys, L.bias,                           \
-                     reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), xs, np, D, nch, \
+  const bool f32 = L.spec_f32;
+  char *xs = reinterpret_cast<char *>(work);
+  char *ys = xs + fft_spec_in_elems(D, np) * esz_of(L);
+  const size_t spec = fft_lds_bytes(D, f32), lds = spec + ((res || out) ? (size_t)D * D * 8 * esz_of(L) : 0);
+#define CF_MID(DT, F)                                                                                   \
+  hipLaunchKernelGGL((k_fft_mid<DT, F>), dim3(D, np, nch), dim3(256), lds, s, ys, L.bias, res, out, xs, np, D, nch, \
                      L.cout_store, (int)spec)
-  if (D == 24) CF_MID(24); else if (D == 16) CF_MID(16); else if (D == 12) CF_MID(12); else CF_MID(0);
+  if (f32) {
+    if (D == 24) CF_MID(24, true); else if (D == 16) CF_MID(16, true); else if (D == 12) CF_MID(12, true); else CF_MID(0, true);
+  } else {
+    if (D == 24) CF_MID(24, false); else if (D == 16) CF_MID(16, false); else if (D == 12) CF_MID(12, false); else CF_MID(0, false);
+  }
 #undef CF_MID
   return hipGetLastError();
 }
@@ -913,33 +1161,56 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
                            hipStream_t s, int stage) {
   if (!fft_conv_ok(L, D) || !work) return hipErrorInvalidValue;
   const int nch = nch_of(L), nco = L.cout / 8;
-  bf16_t *xs = reinterpret_cast<bf16_t *>(work);
-  bf16_t *ys = xs + fft_spec_in_elems(D, np);
+  const bool f32 = L.spec_f32;
+  char *xs = reinterpret_cast<char *>(work);
+  char *ys = xs + fft_spec_in_elems(D, np) * esz_of(L);
   if (stage < 0 || stage == 0) {
-#define CF_FWD(DT)                                                                                 \
-  hipLaunchKernelGGL(k_fft_fwd2d<DT>, dim3(D, np, nch), dim3(256), fft_lds_bytes(D), s,             \
-                     reinterpret_cast<const bf16_t *>(in), xs, np, D, L.cin_pad, nch)
-    if (D == 24) CF_FWD(24); else if (D == 16) CF_FWD(16); else if (D == 12) CF_FWD(12); else CF_FWD(0);
+#define CF_FWD(DT, F)                                                                               \
+  hipLaunchKernelGGL((k_fft_fwd2d<DT, F>), dim3(D, np, nch), dim3(256), fft_lds_bytes(D, F), s, in, xs, np, D, \
+                     L.cin_pad, nch)
+    if (f32) {
+      if (D == 24) CF_FWD(24, true); else if (D == 16) CF_FWD(16, true); else if (D == 12) CF_FWD(12, true); else CF_FWD(0, true);
+    } else {
+      if (D == 24) CF_FWD(24, false); else if (D == 16) CF_FWD(16, false); else if (D == 12) CF_FWD(12, false); else CF_FWD(0, false);
+    }
 #undef CF_FWD
   }
-  if ((stage < 0 || stage == 1) && L.cout == 64 && (kRowsZH / D) * (D + L.k - 1) <= kPanelRowsH) {
+  if ((stage < 0 || stage == 1) && f32) {
+    const int ppb = kRowsZH / D;
+    const dim3 zg((np + ppb - 1) / ppb, kCols, 1);
+    const float *gp = reinterpret_cast<const float *>(L.gspec);
+    const float *xf = reinterpret_cast<const float *>(xs);
+    float *yf = reinterpret_cast<float *>(ys);
+    const int gb = (int)L.gspec_bytes;
+#define CF_ZF(KS, NB) hipLaunchKernelGGL((k_fft_zconv_f32<KS, NB>), zg, dim3(128), 0, s, xf, gp, yf, np, D, nch, ppb, gb)
+    if (L.cout == 64) {
+      if (L.k == 7) CF_ZF(7, 2); else if (L.k == 5) CF_ZF(5, 2); else CF_ZF(3, 2);
+    } else {
+      if (L.k == 7) CF_ZF(7, 1); else if (L.k == 5) CF_ZF(5, 1); else CF_ZF(3, 1);
+    }
+#undef CF_ZF
+  } else if ((stage < 0 || stage == 1) && L.cout == 64 && (kRowsZH / D) * (D + L.k - 1) <= kPanelRowsH) {
     const int ppb = kRowsZH / D;
     const dim3 zg((np + ppb - 1) / ppb, kCols, 1);
     const bf16_t *gp = reinterpret_cast<const bf16_t *>(L.gspec);
+    const bf16_t *xb = reinterpret_cast<const bf16_t *>(xs);
+    bf16_t *yb = reinterpret_cast<bf16_t *>(ys);
     const int gb = (int)L.gspec_bytes;
     if (L.k == 7)
-      hipLaunchKernelGGL((k_fft_zconv_h<7>), zg, dim3(128), 0, s, xs, gp, ys, np, D, nch, ppb, gb);
+      hipLaunchKernelGGL((k_fft_zconv_h<7>), zg, dim3(128), 0, s, xb, gp, yb, np, D, nch, ppb, gb);
     else if (L.k == 5)
-      hipLaunchKernelGGL((k_fft_zconv_h<5>), zg, dim3(128), 0, s, xs, gp, ys, np, D, nch, ppb, gb);
+      hipLaunchKernelGGL((k_fft_zconv_h<5>), zg, dim3(128), 0, s, xb, gp, yb, np, D, nch, ppb, gb);
     else
-      hipLaunchKernelGGL((k_fft_zconv_h<3>), zg, dim3(128), 0, s, xs, gp, ys, np, D, nch, ppb, gb);
+      hipLaunchKernelGGL((k_fft_zconv_h<3>), zg, dim3(128), 0, s, xb, gp, yb, np, D, nch, ppb, gb);
   } else if (stage < 0 || stage == 1) {
     const int ppb = kRowsZ / D;
     const dim3 zg((np + ppb - 1) / ppb, kCols, 1);
     const bf16_t *gp = reinterpret_cast<const bf16_t *>(L.gspec);
+    const bf16_t *xb = reinterpret_cast<const bf16_t *>(xs);
+    bf16_t *yb = reinterpret_cast<bf16_t *>(ys);
     const int gb = (int)L.gspec_bytes;
 #define CF_ZCONV(KS, NT) \
-  hipLaunchKernelGGL((k_fft_zconv<KS, NT>), zg, dim3(NT == 128 ? 256 : 128), 0, s, xs, gp, ys, np, D, nch, ppb, gb)
+  hipLaunchKernelGGL((k_fft_zconv<KS, NT>), zg, dim3(NT == 128 ? 256 : 128), 0, s, xb, gp, yb, np, D, nch, ppb, gb)
     const int nt = L.cout * 2;
     if (L.k == 7) {
       if (nt == 128) CF_ZCONV(7, 128); else if (nt == 64) CF_ZCONV(7, 64); else CF_ZCONV(7, 32);
@@ -951,11 +1222,14 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
 #undef CF_ZCONV
   }
   if (stage < 0 || stage == 2) {
-#define CF_INV(DT)                                                                                        \
-  hipLaunchKernelGGL(k_fft_inv2d<DT>, dim3(D, np, nco), dim3(256), fft_lds_bytes(D), s, ys, L.bias,        \
-                     reinterpret_cast<const bf16_t *>(res), reinterpret_cast<bf16_t *>(out), np, D, nco, \
-                     L.cout_store)
-    if (D == 24) CF_INV(24); else if (D == 16) CF_INV(16); else if (D == 12) CF_INV(12); else CF_INV(0);
+#define CF_INV(DT, F)                                                                                      \
+  hipLaunchKernelGGL((k_fft_inv2d<DT, F>), dim3(D, np, nco), dim3(256), fft_lds_bytes(D, F), s, ys, L.bias, res, \
+                     out, np, D, nco, L.cout_store)
+    if (f32) {
+      if (D == 24) CF_INV(24, true); else if (D == 16) CF_INV(16, true); else if (D == 12) CF_INV(12, true); else CF_INV(0, true);
+    } else {
+      if (D == 24) CF_INV(24, false); else if (D == 16) CF_INV(16, false); else if (D == 12) CF_INV(12, false); else CF_INV(0, false);
+    }
 #undef CF_INV
   }
   return hipGetLastError();

@@ -17,6 +17,12 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr float kSplatScale = 1048576.0f;
 constexpr float kSplatInvScale = 1.0f / 1048576.0f;
 constexpr float kFeatMax = 64.0f;
+// Range budget of one splat tile: the sum over the atoms that reach the tile of
+// ceil(max_channel |feature|).  One atom adds at most 0.4922 feature units (the
+// weight of an atom on a voxel centre) times |feature| to a voxel, so a budget of
+// 4096 keeps every partial sum of every voxel below 2016 * 2^20 + 4096 / 2 units,
+// inside int32.  A tile over budget is reported instead of wrapping silently.
+constexpr int kSplatBudget = 4096;
 
 // Device status word layout (int64[4]): [0] first error code (0 = none),
 // [1] covalent edges needed, [2] non-covalent edges needed, [3] detail.
@@ -28,6 +34,7 @@ enum DevErr : int64_t {
   kDevCapacity = 4,
   kDevPoseTooLarge = 5,
   kDevBadGraph = 6,
+  kDevGridRange = 7,
 };
 
 __device__ inline void dev_fail(int64_t *status, int64_t code) {
@@ -76,8 +83,9 @@ struct ConvLayer {
   int64_t wbytes4;
   int in_cm4;      // the input is the bf16 grid in 4-channel chunk-major layout [P][cin_pad / 4][D^3][4]
   float *bias;     // folded bias [cout_pad32]
-  void *gspec;     // bf16 stride-1 layers: in-plane spectra of the weights (frequency-domain path)
+  void *gspec;     // stride-1 layers: in-plane spectra of the weights (frequency-domain path)
   int64_t gspec_bytes;
+  int spec_f32;    // the frequency-domain path runs on fp32 spectra and activations (the plain form)
 };
 
 // Kernel launchers (defined in the .hip files).
@@ -105,6 +113,8 @@ int conv_default_variant(const ConvLayer &L, int D_in, int bf16);
 int64_t conv_work_bytes(int v, const ConvLayer &L, int D_in, int n_poses);
 hipError_t launch_conv(int variant, const ConvLayer &L, int bf16, const void *in, const void *res,
                        void *out, int n_poses, int D_in, void *work, hipStream_t s);
+// seeded values uniform in [0, 0.5) over `bytes` of bf16 or fp32 elements
+hipError_t launch_fill_random(void *p, int64_t bytes, int bf16, uint64_t seed, hipStream_t s);
 
 // frequency-domain stride-1 conv (cf_fftconv.hip)
 bool fft_conv_layer_ok(const ConvLayer &L);     // layer shape supported (spectra prepared at create)
