@@ -39,6 +39,17 @@ def load_golden(cfg, G, tag=""):
     return json.load(open(path))
 
 
+def load_scores(cfg, G, tag=""):
+    """Stored oracle scores of poses [0, n): every pose of the scores file when the
+    generator wrote one, else the poses stored with their latents."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{cfg}_G{G}{tag}_scores.json")
+    if os.path.exists(path):
+        return np.array(json.load(open(path))["score"], np.float64)
+    gd = load_golden(cfg, G, tag)
+    return None if gd is None else np.array([p["score"] for p in gd["poses"]], np.float64)
+
+
 def time_steps(scorer, db, G, steps, warmup, out, timing=False):
     import torch
     from paper_2104_04547_amd import cfabi
@@ -78,9 +89,9 @@ def by_kernel(stats):
     return out
 
 
-def error_stats(got, gd, n):
+def error_stats(got, want, n):
     import numpy as np
-    want = np.array([p["score"] for p in gd["poses"][:n]])
+    want = np.asarray(want[:n], np.float64)
     err = np.abs(np.asarray(got[:n], dtype=np.float64) - want)
     rel = err / np.maximum(1.0, np.abs(want))
     return dict(n_poses=int(n), max_abs_pk=float(err.max()), mean_abs_pk=float(err.mean()),
@@ -116,37 +127,46 @@ def kernel_traffic(kernel):
     return round(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"], 0)
 
 
-def cpu_baseline(batch, arch, w, G, n, one_core=True):
-    """The FP64 oracle as it stands, on the first n poses, on this host's cores."""
-    import numpy as np
+def _cpu_worker(args):
+    """One process of the CPU baseline: its share of the poses, one BLAS thread."""
+    os.environ["OPENBLAS_NUM_THREADS"] = os.environ["OMP_NUM_THREADS"] = "1"
+    sys.path.insert(0, ROOT)
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    def run(poses):
-        t0 = time.perf_counter()
+    import synth
+    from threadpoolctl import threadpool_limits
+    cfg, poses, arch_name, calib, G = args
+    arch = synth.ARCHS[arch_name]
+    w = synth.apply_calibration(synth.make_weights(arch), calib["scale"], calib["shift"])
+    out = []
+    with threadpool_limits(1):
         for p in poses:
-            a, b = int(batch.atom_off[p]), int(batch.atom_off[p + 1])
-            oracle.score_pose(batch.xyz[a:b], batch.feat[a:b], batch.is_lig[a:b], w, arch, G)
-        return time.perf_counter() - t0
-
-    dt = run(range(n))
-    out = dict(value=n / dt, unit="poses/s", cores=int(threads), kind="oracle",
-               sample=f"first {n} of the workload's poses, full path per pose (splat, conv stack, "
-                      f"graphs, SG-CNN, fusion) in float64 numpy; {dt:.1f} s",
-               seconds=dt)
-    if one_core:
-        try:
-            from threadpoolctl import threadpool_limits
-            with threadpool_limits(1):
-                d1 = run([n])
-            out["value_1core"] = 1.0 / d1
-            out["sample_1core"] = f"pose {n} on one thread; {d1:.1f} s"
-        except ImportError:
-            pass
+            b = synth.make_poses(cfg, 1, pose0=p, threads=1)
+            t0 = time.perf_counter()
+            oracle.score_pose(b.xyz, b.feat, b.is_lig, w, arch, G)
+            out.append(time.perf_counter() - t0)
     return out
+
+
+def cpu_baseline(cfg, arch_name, calib, G, n, workers):
+    """The FP64 oracle as it stands, poses in parallel over this host's cores: the
+    first n poses of the workload, one pose per process at a time, each process on
+    one BLAS thread; plus the single-thread rate from the same per-pose times."""
+    import multiprocessing as mp
+    workers = max(1, min(workers, n))
+    shares = [list(range(i, n, workers)) for i in range(workers)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_cpu_worker, [(cfg, [0], arch_name, calib, 24)] * workers)   # imports and page-in, untimed
+        t0 = time.perf_counter()
+        per_pose = sum(pool.map(_cpu_worker, [(cfg, sh, arch_name, calib, G) for sh in shares]), [])
+        dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="poses/s", cores=int(workers), kind="oracle",
+                sample=f"first {n} of the workload's poses, full path per pose (splat, conv stack, graphs, "
+                       f"SG-CNN, fusion) in float64 numpy, {workers} processes of one thread each; {dt:.1f} s",
+                value_1core=len(per_pose) / sum(per_pose),
+                sample_1core=f"mean time per pose of the same {n} poses on one thread; "
+                             f"{sum(per_pose) / len(per_pose):.2f} s each",
+                seconds=dt)
 
 
 def batching_leg(arch, w, n_poses, steps):
@@ -173,9 +193,9 @@ def batching_leg(arch, w, n_poses, steps):
             r = dict(poses_per_s=round(n_poses / sec, 2), ms_per_step=round(sec * 1e3, 3), conv_variants=v,
                      autotune_s=round(tune_s, 2),
                      conv_tflops=round(arch.flops_per_pose(G) * n_poses / sec / 1e12, 1))
-            gd = load_golden("c4", G)
-            if gd is not None:
-                r["error"] = error_stats(out.cpu().numpy().astype(np.float64), gd, min(len(gd["poses"]), n_poses))
+            want = load_scores("c4", G)
+            if want is not None:
+                r["error"] = error_stats(out.cpu().numpy().astype(np.float64), want, min(len(want), n_poses))
             res[f"G{G}"] = r
             log(f"batching G={G}: {r['poses_per_s']:.1f} poses/s, variants {v}, tuned in {tune_s:.1f}s")
     finally:
@@ -194,7 +214,7 @@ def paper_leg(db, n_poses, steps):
     w = synth.make_weights(arch)
     calib = json.load(open(os.path.join(ROOT, "tests", "golden", "calib.json")))["paper"]
     w = synth.apply_calibration(w, calib["scale"], calib["shift"])
-    gd = load_golden("c2", 48, "_paper")
+    want = load_scores("c2", 48, "_paper")
     out = torch.empty(n_poses, dtype=torch.float32, device="cuda")
     res = {}
     for prec in ("bf16", "fp32"):
@@ -207,8 +227,8 @@ def paper_leg(db, n_poses, steps):
             conv_ms = sum(x["total_ms"] for k, x in st.items() if k.startswith("conv"))
             r["conv_share"] = round(conv_ms / sum(x["total_ms"] for x in st.values()), 4)
             r["sgcnn_ms_per_step"] = round(st["sgcnn"]["total_ms"] / steps, 3)
-            if gd is not None:
-                r["error"] = error_stats(out.cpu().numpy().astype(np.float64), gd, min(len(gd["poses"]), n_poses))
+            if want is not None:
+                r["error"] = error_stats(out.cpu().numpy().astype(np.float64), want, min(len(want), n_poses))
             res[prec] = r
             log(f"paper model {prec}: {r['poses_per_s']:.1f} poses/s, variants {v}, error {r.get('error')}")
         finally:
@@ -216,12 +236,14 @@ def paper_leg(db, n_poses, steps):
     return res
 
 
-def serve_leg(arch, w, res, seconds):
+def serve_leg(arch, w, res, seconds, stream_poses=0):
     """Open-loop Poisson serving: requests of U{1..256} poses (200-1500 atoms),
     grid 48^3 or 64^3 per request, continuous batching on 4 slots with hipGraph
     replay.  Each form's capacity on this request mix is measured first (a burst
     of requests, closed loop); then both forms run at equal load -- 0.7 x the
-    plain form's capacity -- and the precision form also at 0.7 x its own."""
+    plain form's capacity -- and the precision form also at 0.7 x its own
+    (stream_poses > 0: that run streams about that many poses instead of
+    `seconds` of arrivals)."""
     import numpy as np
     import synth
     from paper_2104_04547_amd.serve import Engine, make_requests, run_open_loop, warm_up
@@ -257,6 +279,8 @@ def serve_leg(arch, w, res, seconds):
         for prec, poses_rate, tag in runs:
             rps = poses_rate / mean_req
             n_req = max(20, int(rps * seconds))
+            if stream_poses and tag == "own_capacity":
+                n_req = max(20, int(stream_poses / mean_req))
             reqs = make_requests(pool, n_req, np.random.default_rng(7))
             r = run_open_loop(engines[prec], reqs, rps, seed=11)
             r["offered_poses_per_s"] = poses_rate
@@ -278,14 +302,17 @@ def main():
     ap.add_argument("--poses", type=int, default=4096)
     ap.add_argument("--G", type=int, default=48)
     ap.add_argument("--fp32-steps", type=int, default=2)
-    ap.add_argument("--cpu-poses", type=int, default=3)
+    ap.add_argument("--cpu-poses", type=int, default=48)
+    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=25.0)
-    ap.add_argument("--batch-poses", type=int, default=4096)
-    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--serve-poses", type=int, default=0,
+                    help="stream about this many poses in the precision form's own-capacity run")
+    ap.add_argument("--batch-poses", type=int, default=32768)
+    ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--paper-steps", type=int, default=3)
@@ -344,11 +371,14 @@ def main():
         res[prec] = dict(sec_per_step=sec, poses_per_s=a.poses / sec, stats=stats, scores=scores)
         log(f"{prec}: {sec * 1e3:.1f} ms/step, {a.poses / sec:.1f} poses/s")
         gd = load_golden(cfg, G)
+        want = load_scores(cfg, G)
+        if want is not None:
+            n = min(len(want), a.poses)
+            res[prec]["error"] = error_stats(scores, want, n)
         if gd is not None:
-            n = min(len(gd["poses"]), a.poses)
-            res[prec]["error"] = error_stats(scores, gd, n)
-            res[prec]["cnn_latent_max_rel_error"] = cnn_latent_error(s, batch, gd, G, min(n, 16))
-            log(f"{prec}: error vs oracle {res[prec]['error']}, cnn latent rel {res[prec]['cnn_latent_max_rel_error']:.2e}")
+            res[prec]["cnn_latent_max_rel_error"] = cnn_latent_error(s, batch, gd, G, min(len(gd["poses"]), 16))
+            log(f"{prec}: error vs oracle {res[prec].get('error')}, "
+                f"cnn latent rel {res[prec].get('cnn_latent_max_rel_error')}")
         s.close()
 
     # dominant kernel of the precision form: the kernel (one template instance,
@@ -385,11 +415,11 @@ def main():
 
     serving = None
     if not a.no_serve and "fp32" in res:
-        serving = serve_leg(arch, w, res, a.serve_seconds)
+        serving = serve_leg(arch, w, res, a.serve_seconds, a.serve_poses)
 
     cpu = None
     if not a.no_cpu:
-        cpu = cpu_baseline(batch, arch, w, G, a.cpu_poses)
+        cpu = cpu_baseline(cfg, "full", calib, G, a.cpu_poses, a.cpu_workers)
         log(f"cpu oracle: {cpu['value']:.4f} poses/s on {cpu['cores']} threads, "
             f"{cpu.get('value_1core', float('nan')):.4f} poses/s on one")
 

@@ -60,18 +60,58 @@ class Engine:
             pass
 
 
+class _Span:
+    """Poses [start, start + k) of a pose pool as a request batch: views of the
+    pool's arrays (the pool holds max_poses - 1 poses past its cyclic end, so every
+    span is contiguous) and offsets rebased to 0.  Built when the request is
+    submitted, so a long stream holds no per-request copies."""
+
+    def __init__(self, pool, start: int, k: int):
+        a, b = int(pool.atom_off[start]), int(pool.atom_off[start + k])
+        self.atom_off = np.ascontiguousarray(pool.atom_off[start:start + k + 1] - pool.atom_off[start])
+        self.xyz, self.feat, self.is_lig = pool.xyz[a:b], pool.feat[a:b], pool.is_lig[a:b]
+        self.n_poses = k
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.atom_off[-1])
+
+
+class Requests:
+    """n requests of U{1..max_poses} consecutive poses (cycling through the first
+    `period` poses of the pool), each with a grid size drawn uniformly from `grids`;
+    request i is materialised as views of the pool when it is read."""
+
+    def __init__(self, pool, n_requests: int, rng: np.random.Generator, max_poses: int = 256,
+                 grids: Sequence[int] = (48, 64)):
+        self.pool = pool
+        self.period = pool.n_poses - (max_poses - 1)
+        assert self.period >= 1, "pool needs max_poses - 1 poses past its period"
+        self.k = rng.integers(1, max_poses + 1, size=n_requests)
+        self.G = rng.choice(np.asarray(grids), size=n_requests)
+        starts = np.concatenate([[0], np.cumsum(self.k)[:-1]])
+        self.start = starts % self.period
+
+    def __len__(self):
+        return len(self.k)
+
+    def __getitem__(self, i):
+        return _Span(self.pool, int(self.start[i]), int(self.k[i])), int(self.G[i])
+
+    def __iter__(self):
+        for i in range(len(self)):
+            yield self[i]
+
+    @property
+    def total_poses(self) -> int:
+        return int(self.k.sum())
+
+
 def make_requests(pool, n_requests: int, rng: np.random.Generator, max_poses: int = 256,
                   grids: Sequence[int] = (48, 64)):
     """Requests of U{1..max_poses} consecutive poses from a pose pool, each with a
-    grid size drawn uniformly from `grids`."""
-    reqs = []
-    cursor = 0
-    for _ in range(n_requests):
-        k = int(rng.integers(1, max_poses + 1))
-        idx = [(cursor + i) % pool.n_poses for i in range(k)]
-        cursor = (cursor + k) % pool.n_poses
-        reqs.append((pool.select(idx), int(rng.choice(grids))))
-    return reqs
+    grid size drawn uniformly from `grids` (see Requests)."""
+    return Requests(pool, n_requests, rng, max_poses, grids)
 
 
 def warm_up(engine: Engine, pool, grids: Sequence[int] = (48, 64), n_slots: int = 4):
@@ -100,6 +140,7 @@ def run_open_loop(engine: Engine, requests, rate_rps: float, seed: int = 0) -> D
     """Submit requests at Poisson arrival times (open loop) and collect latencies."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate_rps, size=len(requests))
+    progress_s = 30.0
     pending = {}
     lock = threading.Lock()
     lat: List[float] = []
@@ -119,9 +160,14 @@ def run_open_loop(engine: Engine, requests, rate_rps: float, seed: int = 0) -> D
         finished.set()
 
     t0 = time.perf_counter()
+    t_report = t0 + progress_s
     th = threading.Thread(target=sender, daemon=True)
     th.start()
     while True:
+        if time.perf_counter() > t_report:
+            t_report += progress_s
+            print(f"[serve] {len(lat)} requests, {done_poses[0]} poses done after "
+                  f"{time.perf_counter() - t0:.0f} s", flush=True)
         with lock:
             items = list(pending.items())
         for t, n in items:
