@@ -15,9 +15,12 @@ from .cf_oracle import (U_PER_A, SPLAT_RCUT_U, SPLAT_TWO_SIGMA2_U2, SELU_LAMBDA,
                         cnn3d_forward, radius_graph_pose, radius_graph_batch, gru_cell,
                         sgcnn_pose, sgcnn_batch, selu, fusion_head, late_fusion, score_pose,
                         score_batch, compound_best, top_k)
+from .cf_grad import (conv3d_vjp, batchnorm_vjp, cnn3d_vjp, aggregate_vjp, gru_cell_vjp, sgcnn_vjp,
+                      fusion_head_vjp, score_vjp)
 
 __all__ = ["U_PER_A", "SPLAT_RCUT_U", "SPLAT_TWO_SIGMA2_U2", "SELU_LAMBDA", "SELU_ALPHA",
            "pose_center", "voxel_center", "splat_pose", "splat_batch", "conv3d", "batchnorm",
            "cnn3d_forward", "radius_graph_pose", "radius_graph_batch", "gru_cell", "sgcnn_pose",
            "sgcnn_batch", "selu", "fusion_head", "late_fusion", "score_pose", "score_batch",
-           "compound_best", "top_k"]
+           "compound_best", "top_k", "conv3d_vjp", "batchnorm_vjp", "cnn3d_vjp", "aggregate_vjp",
+           "gru_cell_vjp", "sgcnn_vjp", "fusion_head_vjp", "score_vjp"]
