@@ -255,6 +255,26 @@ typedef struct {
 int cf_timing_enable(cf_ctx *ctx, int enable);
 int cf_timing_read(cf_ctx *ctx, cf_kernel_stat *out, int32_t max_entries, int32_t *n_out);
 
+/* ---- Backward pass (fine-tuning) ----------------------------------------------
+ * Coherent Fusion trains the fusion layers and both branches together, the loss
+ * gradient reaching the 3D-CNN and the SG-CNN through the concatenated latents
+ * (Sec. 2.2; training hyper-parameters in Table V).  cf_backward scores the batch
+ * and returns, for one upstream gradient per pose dscore[p] = dL/ds_p (e.g. s_p -
+ * y_p for a squared-error loss), grad[theta] = sum_p dscore[p] ds_p/dtheta for
+ * every parameter theta of the model blob, in the blob's order and layout
+ * (n_params floats, cf_model_info), BatchNorm running mean and variance included.
+ * grad is overwritten.  scores (device [P]) or NULL receives the scores the
+ * forward computed.  All pointers are device pointers owned by the caller.
+ * Requirements: a CF_PREC_FP32 context (float32 throughout), the Coherent Fusion
+ * head and the unstaged SG-CNN (H_nc = 0); otherwise CF_ERR_UNSUPPORTED.  Unlike
+ * the scoring calls it reads batch->atom_off back to the host (one synchronous
+ * copy on `stream`) to size its per-atom launches, and checks it there.  Poses
+ * are processed in chunks of at most 32; every reduction runs in a fixed order,
+ * so the result is reproducible bit for bit.  Device-detected input errors are
+ * reported by cf_stream_status as for scoring. */
+int cf_backward(cf_ctx *ctx, const cf_pose_batch *batch, int G, const float *dscore, float *grad, float *scores,
+                void *stream);
+
 /* ---- Selection after scoring --------------------------------------------------
  * Per-compound aggregation: the paper represents each compound by its strongest
  * prediction over all its docked poses (the maximum Coherent Fusion pK; up to 10

@@ -85,11 +85,17 @@ def batchnorm_vjp(x, gamma, mean, var, dy, eps: float = BN_EPS):
     return dx, dgamma, dbeta, dmean, dvar
 
 
-def cnn3d_vjp(grid: np.ndarray, w, arch, dlat: np.ndarray) -> Dict[str, np.ndarray]:
+def cnn3d_vjp(grid: np.ndarray, w, arch, dlat: np.ndarray, relu_margin: float = 0.0) -> Dict[str, np.ndarray]:
     """Gradients of the 3D-CNN latent (cf_oracle.cnn3d_forward) given dL/dlatent:
     the forward is rerun keeping every conv output before BN (c), after BN and the
     residual add (u, before the ReLU) and every activation (t); the backward walks
-    the dense layers, the mean pool and the conv layers in reverse."""
+    the dense layers, the mean pool and the conv layers in reverse.
+
+    relu_margin (default 0, the definition) takes each ReLU's gradient as
+    [u > relu_margin]: with a small margin of either sign the result is the
+    gradient a forward pass within that distance of exact arithmetic may yield,
+    since pre-activations that close to 0 may fall on either side of the kink
+    (a tolerance for comparing with float32 forward passes, not another model)."""
     t = [np.moveaxis(np.asarray(grid, np.float64), -1, 0)]
     cs, us = [], []
     from .cf_oracle import batchnorm, conv3d
@@ -113,7 +119,7 @@ def cnn3d_vjp(grid: np.ndarray, w, arch, dlat: np.ndarray) -> Dict[str, np.ndarr
     g: Dict[str, np.ndarray] = {}
     d = np.asarray(dlat, np.float64)
     for n, xin, pre in reversed(list(zip(names, dense_in, dense_pre))):
-        dpre = d * (pre > 0)
+        dpre = d * (pre > relu_margin)
         g[n + ".w"] = np.outer(dpre, xin)
         g[n + ".b"] = dpre
         d = _f64(w, n + ".w").T @ dpre
@@ -122,7 +128,7 @@ def cnn3d_vjp(grid: np.ndarray, w, arch, dlat: np.ndarray) -> Dict[str, np.ndarr
     dt[-1] = np.broadcast_to(d[:, None, None, None] / V, t[-1].shape).copy()
     for i in reversed(range(len(arch.conv))):
         ci, co, k, s, r = arch.conv[i]
-        du = dt[i + 1] * (us[i] > 0)
+        du = dt[i + 1] * (us[i] > relu_margin)
         if r >= 0:
             dt[r] += du
         if arch.bn:
@@ -269,10 +275,11 @@ def fusion_head_vjp(cnn_lat, sg_lat, w, arch, dscore: float):
 # Whole path
 # --------------------------------------------------------------------------------
 
-def score_vjp(batch, w, arch, G: int, dscore) -> Dict[str, np.ndarray]:
+def score_vjp(batch, w, arch, G: int, dscore, relu_margin: float = 0.0) -> Dict[str, np.ndarray]:
     """sum_p dscore[p] * d s_p / d theta for every parameter theta (zero for those
     the score does not depend on).  Grid centres are the rounded ligand centroids
-    (cf_oracle.score_pose); the grid and the graphs carry no parameters."""
+    (cf_oracle.score_pose); the grid and the graphs carry no parameters.
+    relu_margin: see cnn3d_vjp (0 = the definition)."""
     grads = {k: np.zeros(np.shape(v)) for k, v in w.items()}
     for p in range(batch.n_poses):
         a, b = int(batch.atom_off[p]), int(batch.atom_off[p + 1])
@@ -285,7 +292,7 @@ def score_vjp(batch, w, arch, G: int, dscore) -> Dict[str, np.ndarray]:
         nc = radius_graph_pose(xyz, arch.r_nc_u)
         sg_lat = sgcnn_pose(feat, is_lig, cov, nc, w, arch)
         dcnn, dsg, gh = fusion_head_vjp(cnn_lat, sg_lat, w, arch, float(dscore[p]))
-        for part in (gh, cnn3d_vjp(grid, w, arch, dcnn), sgcnn_vjp(feat, is_lig, cov, nc, w, arch, dsg)):
+        for part in (gh, cnn3d_vjp(grid, w, arch, dcnn, relu_margin), sgcnn_vjp(feat, is_lig, cov, nc, w, arch, dsg)):
             for k, v in part.items():
                 grads[k] = grads[k] + np.reshape(v, grads[k].shape)
     return grads

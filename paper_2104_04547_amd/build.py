@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libcf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["cf_splat.hip", "cf_graph.hip", "cf_conv.hip", "cf_fftconv.hip", "cf_head.hip", "cf_sgcnn.hip", "cf_capi.hip",
-           "cf_engine.hip", "cf_select.hip"]
+           "cf_engine.hip", "cf_select.hip", "cf_backward.hip"]
 HEADERS = ["cf_internal.h", "cf_fft32.h", "cf_queue.h"]
 
 FLAGS = [

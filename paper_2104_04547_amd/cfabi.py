@@ -31,7 +31,7 @@ EXPORTS = ["cf_create", "cf_destroy", "cf_pose_centers", "cf_voxelize", "cf_buil
            "cf_engine_create", "cf_engine_submit", "cf_engine_poll", "cf_engine_wait_all", "cf_engine_info",
            "cf_engine_last_error", "cf_engine_destroy", "cf_engine_cancel", "cf_set_conv_variants", "cf_conv_variant_count",
            "cf_conv_variant_name", "cf_compound_max", "cf_top_k", "cf_fusion_fwd",
-           "cf_top_k_noalloc"]
+           "cf_top_k_noalloc", "cf_backward"]
 
 
 HEAD_KINDS = {"coherent": 0, "mid": 1, "late": 2}   # cf_head_kind
@@ -120,6 +120,7 @@ def load(path: str = LIB_PATH):
         "cf_compound_max": ([vp, vp, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "cf_top_k": ([vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
         "cf_top_k_noalloc": ([vp, i32, i32, vp, vp, vp], ctypes.c_int),
+        "cf_backward": ([vp, ctypes.POINTER(cf_pose_batch), ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "cf_fusion_fwd": ([vp, vp, vp, i32, vp, vp], ctypes.c_int),
     }
     missing = set(EXPORTS) - set(sig)
@@ -247,6 +248,10 @@ def cf_fusion_fwd(ctx, cnn_latent_ptr: int, sg_latent_ptr: int, n_poses: int, sc
 
 def cf_score_poses(ctx, batch: cf_pose_batch, G: int, scores_ptr: int, stream: int = 0):
     _check(load().cf_score_poses(ctx, ctypes.byref(batch), G, scores_ptr, stream))
+
+
+def cf_backward(ctx, batch: cf_pose_batch, G: int, dscore_ptr: int, grad_ptr: int, scores_ptr, stream: int = 0):
+    _check(load().cf_backward(ctx, ctypes.byref(batch), G, dscore_ptr, grad_ptr, scores_ptr, stream))
 
 
 def cf_stream_status(ctx, stream: int = 0):

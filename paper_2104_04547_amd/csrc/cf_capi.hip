@@ -39,6 +39,19 @@ struct DevBuf {
 
 }  // namespace
 
+// Offsets (floats) of the blob's parameter tensors, recorded while the blob is
+// read; the backward pass reads the unfolded parameters at these offsets of a
+// device copy of the blob and writes gradients at the same offsets.
+struct TrainOffsets {
+  int64_t conv_w[8], conv_b[8], bn_g[8], bn_b[8], bn_m[8], bn_v[8];
+  int64_t dense_w = -1, dense_b = -1, dense2_w = -1, dense2_b = -1;
+  int64_t embed_w = -1, embed_b = -1;
+  int64_t msg[16];
+  int64_t wih[2], whh[2], bih[2], bhh[2];
+  int64_t gate_w = -1, gate_b = -1, val_w = -1, val_b = -1;
+  int64_t head = -1, head_n = 0;
+};
+
 struct cf_ctx {
   int device = 0;
   int bf16 = 0;
@@ -84,9 +97,15 @@ struct cf_ctx {
   std::vector<Pending> pending;
   std::map<std::string, Stat> stats;
 
+  // backward pass (plain form): the blob's parameters on the device, unfolded
+  float *raw = nullptr;
+  TrainOffsets tr{};
+
   // scratch
   DevBuf grid, centers, cnn_lat, sg_lat, deg, pose_tot, cov_row, cov_col, nc_row, nc_col, hbuf, sel;
   std::vector<DevBuf> act;  // t_1 .. t_L
+  std::vector<DevBuf> dact; // backward: gradients of t_1 .. t_L
+  DevBuf bw_sg, bw_cnn, bw_part, bw_head;  // backward scratch
   DevBuf convwork;          // scratch of the frequency-domain conv (spectra)
   std::map<int, std::vector<int>> variants;  // per G
 };
@@ -271,7 +290,8 @@ int ensure_act(cf_ctx *c, int G, int np) {
 
 // conv stack + pooling on grids already in the internal padded layout in c->grid;
 // after_first (optional) is recorded on s once the first layer is enqueued
-int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s, hipEvent_t after_first = nullptr) {
+int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s, hipEvent_t after_first = nullptr,
+            bool store_all = false) {
   std::vector<int> var;
   int rc = variants_for(c, G, var);
   if (rc) return rc;
@@ -291,6 +311,7 @@ int run_cnn(cf_ctx *c, int G, int np, float *cnn_lat, hipStream_t s, hipEvent_t 
   // the activation t[k] is read from memory by a later layer (as input of a direct
   // kernel, or as a residual)
   auto stored = [&](int k) {
+    if (store_all) return true;
     for (int j = k; j < nl; ++j)
       if (c->conv[j].res_src == k) return true;
     return false;
@@ -567,6 +588,9 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
                (nbytes - sizeof(cf_model_desc)) / sizeof(float)};
   if ((nbytes - sizeof(cf_model_desc)) % sizeof(float)) return fail(CF_ERR_INVALID_ARG, "blob size not float-aligned");
   const size_t total_floats = R.left;
+  const float *const base0 = R.p;
+  TrainOffsets &T = c->tr;
+  auto at = [&](const float *q) -> int64_t { return (int64_t)(q - base0); };
   int cin = CF_NCH;
   int cin_pad = grid_cpad(c);
   std::vector<int> chans{CF_NCH};
@@ -585,10 +609,17 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     const size_t nw = (size_t)co * ci * k * k * k;
     const float *W = R.take(nw), *b = R.take(co);
     if (!W || !b) return fail(CF_ERR_INVALID_ARG, "blob truncated (conv)");
+    T.conv_w[i] = at(W);
+    T.conv_b[i] = at(b);
+    T.bn_g[i] = T.bn_b[i] = T.bn_m[i] = T.bn_v[i] = -1;
     std::vector<double> sc(co, 1.0), sh(co, 0.0);
     if (d.bn) {
       const float *g = R.take(co), *bt = R.take(co), *mu = R.take(co), *var = R.take(co);
       if (!g || !bt || !mu || !var) return fail(CF_ERR_INVALID_ARG, "blob truncated (bn)");
+      T.bn_g[i] = at(g);
+      T.bn_b[i] = at(bt);
+      T.bn_m[i] = at(mu);
+      T.bn_v[i] = at(var);
       for (int o = 0; o < co; ++o) {
         if (!(var[o] + 1e-5 > 0.0)) return fail(CF_ERR_INVALID_ARG, "BatchNorm variance must be > -eps");
         sc[o] = (double)g[o] / std::sqrt((double)var[o] + 1e-5);
@@ -660,12 +691,16 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
   if (d.cnn_dense) {
     const float *W = R.take((size_t)d.cnn_dense * c->c_last), *b = R.take(d.cnn_dense);
     if (!W || !b) return fail(CF_ERR_INVALID_ARG, "blob truncated (cnn dense)");
+    T.dense_w = at(W);
+    T.dense_b = at(b);
     if ((rc = upload_f(c, &c->dense_w, W, (size_t)d.cnn_dense * c->c_last))) return rc;
     if ((rc = upload_f(c, &c->dense_b, b, d.cnn_dense))) return rc;
     c->lc = d.cnn_dense;
     if (d.cnn_dense2) {
       const float *W2 = R.take((size_t)d.cnn_dense2 * d.cnn_dense), *b2 = R.take(d.cnn_dense2);
       if (!W2 || !b2) return fail(CF_ERR_INVALID_ARG, "blob truncated (cnn dense2)");
+      T.dense2_w = at(W2);
+      T.dense2_b = at(b2);
       if ((rc = upload_f(c, &c->dense2_w, W2, (size_t)d.cnn_dense2 * d.cnn_dense))) return rc;
       if ((rc = upload_f(c, &c->dense2_b, b2, d.cnn_dense2))) return rc;
       c->lc = d.cnn_dense2;
@@ -715,6 +750,8 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
   {
     const float *W = R.take((size_t)Hm[0] * CF_NCH), *b = R.take(Hm[0]);
     if (!W || !b) return fail(CF_ERR_INVALID_ARG, "blob truncated (embed)");
+    T.embed_w = at(W);
+    T.embed_b = at(b);
     if ((rc = put(transpose(padm(W, Hm[0], CF_NCH, Hp, CF_NCH, CF_NCH, 0).data(), Hp, CF_NCH), &S.embed_wT))) return rc;
     if ((rc = put(padm(b, 1, Hm[0], 1, Hp, Hm[0], 0), &S.embed_b))) return rc;
   }
@@ -740,6 +777,7 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     for (int q = 0; q < K; ++q, ++r) {
       const float *W = R.take((size_t)h * h);
       if (!W) return fail(CF_ERR_INVALID_ARG, "blob truncated (message)");
+      T.msg[r] = at(W);
       const auto Wp = padm(W, h, h, hp, hp, h, 0);
       if ((rc = put(transpose(Wp.data(), hp, hp), &S.msgT[r]))) return rc;
       if (c->bf16 && hp >= 32 && (rc = upload_split(c, Wp.data(), hp, hp, &S.msg_hi[r], &S.msg_lo[r]))) return rc;
@@ -747,6 +785,10 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     const float *wih = R.take((size_t)3 * h * h), *whh = R.take((size_t)3 * h * h);
     const float *bih = R.take(3 * h), *bhh = R.take(3 * h);
     if (!wih || !whh || !bih || !bhh) return fail(CF_ERR_INVALID_ARG, "blob truncated (gru)");
+    T.wih[stage] = at(wih);
+    T.whh[stage] = at(whh);
+    T.bih[stage] = at(bih);
+    T.bhh[stage] = at(bhh);
     const auto wi = padg(wih, h, h, hp, hp), wh = padg(whh, h, h, hp, hp);
     if ((rc = put(transpose(wi.data(), 3 * hp, hp), &S.w_ihT[stage]))) return rc;
     if ((rc = put(transpose(wh.data(), 3 * hp, hp), &S.w_hhT[stage]))) return rc;
@@ -763,14 +805,23 @@ int build_model(cf_ctx *c, const void *blob, size_t nbytes) {
     const float *gw = R.take((size_t)h * (h + u)), *gb = R.take(h);
     const float *vw = R.take((size_t)h * h), *vb = R.take(h);
     if (!gw || !gb || !vw || !vb) return fail(CF_ERR_INVALID_ARG, "blob truncated (readout)");
+    T.gate_w = at(gw);
+    T.gate_b = at(gb);
+    T.val_w = at(vw);
+    T.val_b = at(vb);
     if ((rc = put(transpose(padm(gw, h, h + u, hp, hp + up, h, hp - h).data(), hp, hp + up), &S.gate_wT))) return rc;
     if ((rc = put(padm(gb, 1, h, 1, hp, h, 0), &S.gate_b))) return rc;
     if ((rc = put(transpose(padm(vw, h, h, hp, hp, h, 0).data(), hp, hp), &S.val_wT))) return rc;
     if ((rc = put(padm(vb, 1, h, 1, hp, h, 0), &S.val_b))) return rc;
   }
+  T.head = at(R.p);
   if ((rc = build_head(c, R))) return rc;
   if (R.left != 0) return fail(CF_ERR_INVALID_ARG, "blob has trailing data");
+  T.head_n = (int64_t)total_floats - T.head;
   c->n_params = (int64_t)total_floats;
+  // the plain form keeps the unfolded parameters for the backward pass
+  if (!c->bf16 && (rc = alloc_weight(c, reinterpret_cast<void **>(&c->raw), total_floats * sizeof(float), base0)))
+    return rc;
   return CF_OK;
 }
 
@@ -783,6 +834,11 @@ void free_ctx(cf_ctx *c) {
     if (b->p) (void)hipFree(b->p);
   for (auto &b : c->act)
     if (b.p) (void)hipFree(b.p);
+  for (auto &b : c->dact)
+    if (b.p) (void)hipFree(b.p);
+  DevBuf *bw[] = {&c->bw_sg, &c->bw_cnn, &c->bw_part, &c->bw_head};
+  for (DevBuf *b : bw)
+    if (b->p) (void)hipFree(b->p);
   if (c->convwork.p) (void)hipFree(c->convwork.p);
   if (c->status) (void)hipFree(c->status);
   hipEvent_t evs[] = {c->ev_fork, c->ev_sg};
@@ -1025,6 +1081,214 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
     CF_HIP(cf::launch_head((float *)c->cnn_lat.p, c->lc, (float *)c->sg_lat.p, H, c->head_prm, c->head, np,
                            scores + p0, s));
     tend(c, s, e, "fusion", 0.0, 0.0);
+  }
+  return CF_OK;
+}
+
+int cf_backward(cf_ctx *c, const cf_pose_batch *b, int G, const float *dscore, float *grad, float *scores,
+                void *stream) {
+  if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
+  int rc = validate_batch(b);
+  if (rc) return rc;
+  if ((rc = validate_G(G))) return rc;
+  if (!dscore || !grad) return fail(CF_ERR_INVALID_ARG, "dscore and grad must not be NULL");
+  if (c->bf16 || !c->raw) return fail(CF_ERR_UNSUPPORTED, "the backward pass runs in the plain (FP32) form");
+  const cf_model_desc &d = c->desc;
+  if (d.head != CF_HEAD_COHERENT) return fail(CF_ERR_UNSUPPORTED, "the backward pass covers the Coherent Fusion head");
+  if (d.H_nc != 0) return fail(CF_ERR_UNSUPPORTED, "the backward pass covers the unstaged SG-CNN");
+  const int H = d.H, R = d.K_c + d.K_n, L = (int)c->conv.size();
+  const int nhid = d.fusion_layers - 1, fh = d.fusion_hidden;
+  if (!cf::bw_head_ok(c->lc + H, fh, nhid)) return fail(CF_ERR_UNSUPPORTED, "fusion head too wide for the backward pass");
+  hipStream_t s = (hipStream_t)stream;
+  // the per-atom launches are sized on the host: read the offsets back once
+  std::vector<int32_t> off((size_t)b->n_poses + 1);
+  CF_HIP(hipMemcpyAsync(off.data(), b->atom_off, off.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CF_HIP(hipStreamSynchronize(s));
+  if (off[0] != 0 || off[b->n_poses] != b->n_atoms) return fail(CF_ERR_INVALID_ARG, "atom_off[0] must be 0 and atom_off[P] = n_atoms");
+  for (int p = 0; p < b->n_poses; ++p)
+    if (off[p + 1] - off[p] < 1 || off[p + 1] - off[p] > CF_MAX_POSE_ATOMS)
+      return fail(CF_ERR_INVALID_ARG, "atom_off malformed (each pose needs 1..4096 atoms)");
+
+  constexpr int kBwChunk = 32;
+  const int chunk = std::min(kBwChunk, chunk_poses(c, G, b->n_poses, b->n_atoms));
+  int64_t max_atoms = 0;
+  for (int p0 = 0; p0 < b->n_poses; p0 += chunk)
+    max_atoms = std::max<int64_t>(max_atoms, off[std::min(b->n_poses, p0 + chunk)] - off[p0]);
+  const int64_t acap = max_atoms;
+  if ((rc = ensure_act(c, G, chunk))) return rc;
+  if ((rc = ensure_atoms(c, acap, chunk))) return rc;
+  if ((rc = ensure(c, c->centers, (size_t)chunk * 3 * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(c, c->cnn_lat, (size_t)chunk * c->lc * sizeof(float)))) return rc;
+  if ((rc = ensure(c, c->sg_lat, (size_t)chunk * c->sgw * sizeof(float)))) return rc;
+  // layer sizes
+  std::vector<int> dims{G};
+  for (auto &Lr : c->conv) dims.push_back(conv_out_dim(dims.back(), Lr.k, Lr.stride));
+  auto vox = [&](int i) { return (int64_t)dims[i] * dims[i] * dims[i]; };
+  if ((int)c->dact.size() != L) c->dact.resize(L);
+  for (int i = 0; i < L; ++i)
+    if ((rc = ensure(c, c->dact[i], (size_t)chunk * vox(i + 1) * c->conv[i].cout_store * sizeof(float)))) return rc;
+  // SG scratch (floats): states H[R+1], messages M[R], gate inputs GI[R], GH[R]
+  // (3H each), then per-atom work rows
+  const int64_t nH = acap * H, n3 = acap * 3 * H;
+  const int64_t sg_floats = (R + 1) * nH + R * nH + 2 * R * n3 + 9 * nH + 2 * n3;
+  if ((rc = ensure(c, c->bw_sg, (size_t)sg_floats * sizeof(float)))) return rc;
+  // CNN scratch: per-pose weight-gradient partials, the pose sum, folded transposed
+  // weights, bias gradient; pool / dense rows
+  int64_t wq = 0;
+  for (int i = 0; i < L; ++i)
+    wq = std::max<int64_t>(wq, (int64_t)c->conv[i].cout * c->conv[i].cin * c->conv[i].k * c->conv[i].k * c->conv[i].k);
+  const int dmax = 256;
+  const int64_t cnn_floats = (int64_t)chunk * wq + 2 * wq + 256 + 8 * (int64_t)chunk * dmax;
+  if ((rc = ensure(c, c->bw_cnn, (size_t)cnn_floats * sizeof(float)))) return rc;
+  // head: per-pose parameter gradients and the latents' gradients
+  const int64_t head_floats = (int64_t)chunk * c->tr.head_n + (int64_t)chunk * (c->lc + H) + 2 * (int64_t)chunk;
+  if ((rc = ensure(c, c->bw_head, (size_t)head_floats * sizeof(float)))) return rc;
+  // partial sums of the ordered reductions (the largest any call below needs)
+  int64_t part = cf::bw_outer_scratch(chunk, (int)c->tr.head_n, 1);
+  part = std::max(part, cf::bw_outer_scratch((int)acap, 3 * H, H));
+  part = std::max(part, cf::bw_outer_scratch((int)acap, H, H + CF_NCH));
+  part = std::max(part, cf::bw_outer_scratch(chunk, (int)wq, 1));
+  part = std::max(part, cf::bw_outer_scratch(chunk, dmax, dmax));
+  for (int i = 0; i < L; ++i) part = std::max(part, cf::bw_outer_scratch((int)(chunk * vox(i + 1)), c->conv[i].cout, 1));
+  if ((rc = ensure(c, c->bw_part, (size_t)part * sizeof(float)))) return rc;
+
+  const float *P = c->raw;
+  const TrainOffsets &T = c->tr;
+  float *pt = (float *)c->bw_part.p;
+  CF_HIP(cf::bw_fill(grad, c->n_params, 0.0f, s));
+  for (int p0 = 0; p0 < b->n_poses; p0 += chunk) {
+    const int np = std::min(chunk, b->n_poses - p0);
+    const int a0 = off[p0], n = off[p0 + np] - a0;
+    const float *x = b->feat + (int64_t)a0 * CF_NCH;
+    const int32_t *cen = b->center ? b->center + 3 * (size_t)p0 : (const int32_t *)c->centers.p;
+    // ---- forward, keeping what the backward reads ----
+    if (!b->center)
+      CF_HIP(cf::launch_centers(b->atom_off, b->n_atoms, b->xyz, b->is_lig, p0, np, (int32_t *)c->centers.p, c->status, s));
+    CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, p0, np, G, c->grid.p, 2, grid_cpad(c),
+                            c->status, s));
+    if ((rc = run_cnn(c, G, np, (float *)c->cnn_lat.p, s, nullptr, true))) return rc;
+    CF_HIP(cf::launch_graph(b->atom_off, b->n_atoms, b->xyz, p0, np, d.r_cov_u, d.r_nc_u, (int32_t *)c->cov_row.p,
+                            (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,
+                            acap * 96, (int32_t *)c->deg.p, acap, (int64_t *)c->pose_tot.p, c->status, s));
+    const int32_t *rp[2] = {(int32_t *)c->cov_row.p, (int32_t *)c->nc_row.p};
+    const int32_t *cl[2] = {(int32_t *)c->cov_col.p, (int32_t *)c->nc_col.p};
+    const int64_t cap[2] = {acap * 16, acap * 96};
+    float *Hs = (float *)c->bw_sg.p;       // [R + 1][n][H]
+    float *Ms = Hs + (R + 1) * nH;         // [R][n][H]
+    float *GI = Ms + R * nH, *GH = GI + R * n3;  // [R][n][3H]
+    float *As = GH + R * n3, *Gp = As + nH, *Vv = Gp + nH, *dH = Vv + nH, *dHd = dH + nH, *dA = dHd + nH;
+    float *dM = dA + nH, *dGp = dM + nH, *dV = dGp + nH, *dGI = dV + nH, *dGH = dGI + n3;
+    auto Hr = [&](int r) { return Hs + (int64_t)r * n * H; };
+    auto stage_of = [&](int r) { return r < d.K_c ? 0 : 1; };
+    CF_HIP(cf::bw_rowmat(x, CF_NCH, n, CF_NCH, P + T.embed_w, CF_NCH, P + T.embed_b, H, Hr(0), H, 0, s));
+    for (int r = 0; r < R; ++r) {
+      const int st = stage_of(r);
+      float *Mr = Ms + (int64_t)r * n * H, *GIr = GI + (int64_t)r * n * 3 * H, *GHr = GH + (int64_t)r * n * 3 * H;
+      CF_HIP(cf::bw_agg(rp[st], cl[st], cap[st], Hr(r), n, H, As, 0, c->status, s));
+      CF_HIP(cf::bw_rowmat(As, H, n, H, P + T.msg[r], H, nullptr, H, Mr, H, 0, s));
+      CF_HIP(cf::bw_rowmat(Mr, H, n, H, P + T.wih[st], H, P + T.bih[st], 3 * H, GIr, 3 * H, 0, s));
+      CF_HIP(cf::bw_rowmat(Hr(r), H, n, H, P + T.whh[st], H, P + T.bhh[st], 3 * H, GHr, 3 * H, 0, s));
+      CF_HIP(cf::bw_gru_fwd(GIr, GHr, Hr(r), n, H, Hr(r + 1), s));
+    }
+    CF_HIP(cf::bw_rowmat(Hr(R), H, n, H, P + T.gate_w, H + CF_NCH, P + T.gate_b, H, Gp, H, 0, s));
+    CF_HIP(cf::bw_rowmat(x, CF_NCH, n, CF_NCH, P + T.gate_w + H, H + CF_NCH, nullptr, H, Gp, H, 1, s));
+    CF_HIP(cf::bw_rowmat(Hr(R), H, n, H, P + T.val_w, H, P + T.val_b, H, Vv, H, 0, s));
+    float *sgl = (float *)c->sg_lat.p;
+    CF_HIP(cf::bw_readout(Gp, Vv, b->is_lig, b->atom_off, p0, np, H, sgl, s));
+    // ---- head ----
+    float *hpart = (float *)c->bw_head.p, *dcnn = hpart + (int64_t)chunk * T.head_n, *dsg = dcnn + (int64_t)chunk * c->lc;
+    CF_HIP(cf::bw_head((float *)c->cnn_lat.p, c->lc, sgl, H, P + T.head, nhid, fh, d.fusion_residual, dscore + p0, np,
+                       scores ? scores + p0 : nullptr, dcnn, dsg, hpart, T.head_n, s));
+    CF_HIP(cf::bw_outer(hpart, (int)T.head_n, nullptr, 0, np, (int)T.head_n, 1, grad + T.head, 1, 1, pt, s));
+    // ---- SG-CNN backward ----
+    CF_HIP(cf::bw_readout_bwd(Gp, Vv, b->is_lig, b->atom_off, p0, np, H, n, dsg, dGp, dV, s));
+    CF_HIP(cf::bw_outer(dGp, H, Hr(R), H, n, H, H, grad + T.gate_w, H + CF_NCH, 1, pt, s));
+    CF_HIP(cf::bw_outer(dGp, H, x, CF_NCH, n, H, CF_NCH, grad + T.gate_w + H, H + CF_NCH, 1, pt, s));
+    CF_HIP(cf::bw_outer(dGp, H, nullptr, 0, n, H, 1, grad + T.gate_b, 1, 1, pt, s));
+    CF_HIP(cf::bw_outer(dV, H, Hr(R), H, n, H, H, grad + T.val_w, H, 1, pt, s));
+    CF_HIP(cf::bw_outer(dV, H, nullptr, 0, n, H, 1, grad + T.val_b, 1, 1, pt, s));
+    CF_HIP(cf::bw_rowmat_t(dGp, H, n, H, P + T.gate_w, H + CF_NCH, H, dH, H, 0, s));
+    CF_HIP(cf::bw_rowmat_t(dV, H, n, H, P + T.val_w, H, H, dH, H, 1, s));
+    for (int r = R - 1; r >= 0; --r) {
+      const int st = stage_of(r);
+      float *Mr = Ms + (int64_t)r * n * H, *GIr = GI + (int64_t)r * n * 3 * H, *GHr = GH + (int64_t)r * n * 3 * H;
+      CF_HIP(cf::bw_gru_bwd(GIr, GHr, Hr(r), dH, n, H, dGI, dGH, dHd, s));
+      CF_HIP(cf::bw_outer(dGI, 3 * H, Mr, H, n, 3 * H, H, grad + T.wih[st], H, 1, pt, s));
+      CF_HIP(cf::bw_outer(dGI, 3 * H, nullptr, 0, n, 3 * H, 1, grad + T.bih[st], 1, 1, pt, s));
+      CF_HIP(cf::bw_outer(dGH, 3 * H, Hr(r), H, n, 3 * H, H, grad + T.whh[st], H, 1, pt, s));
+      CF_HIP(cf::bw_outer(dGH, 3 * H, nullptr, 0, n, 3 * H, 1, grad + T.bhh[st], 1, 1, pt, s));
+      CF_HIP(cf::bw_rowmat_t(dGI, 3 * H, n, 3 * H, P + T.wih[st], H, H, dM, H, 0, s));  // dm
+      CF_HIP(cf::bw_rowmat_t(dGH, 3 * H, n, 3 * H, P + T.whh[st], H, H, dHd, H, 1, s));
+      CF_HIP(cf::bw_agg(rp[st], cl[st], cap[st], Hr(r), n, H, As, 0, c->status, s));  // the round's neighbour sums
+      CF_HIP(cf::bw_outer(dM, H, As, H, n, H, H, grad + T.msg[r], H, 1, pt, s));
+      CF_HIP(cf::bw_rowmat_t(dM, H, n, H, P + T.msg[r], H, H, dA, H, 0, s));
+      // a_i = sum_{j in N(i)} h_j: dh_j += sum_{i : j in N(i)} da_i, and the graphs are
+      // symmetric (a distance test), so that is the neighbour sum of da over N(j)
+      CF_HIP(cf::bw_agg(rp[st], cl[st], cap[st], dA, n, H, dHd, 1, c->status, s));
+      std::swap(dH, dHd);
+    }
+    CF_HIP(cf::bw_outer(dH, H, x, CF_NCH, n, H, CF_NCH, grad + T.embed_w, CF_NCH, 1, pt, s));
+    CF_HIP(cf::bw_outer(dH, H, nullptr, 0, n, H, 1, grad + T.embed_b, 1, 1, pt, s));
+    // ---- 3D-CNN backward ----
+    float *part = (float *)c->bw_cnn.p, *dWf = part + (int64_t)chunk * wq, *WT = dWf + wq, *dbf = WT + wq;
+    float *pool = dbf + 256, *pre1 = pool + (int64_t)chunk * dmax, *lat1 = pre1 + (int64_t)chunk * dmax;
+    float *pre2 = lat1 + (int64_t)chunk * dmax, *dl2 = pre2 + (int64_t)chunk * dmax, *dl1 = dl2 + (int64_t)chunk * dmax;
+    float *dpool = dl1 + (int64_t)chunk * dmax;
+    const auto &Ll = c->conv.back();
+    CF_HIP(cf::bw_pool_mean((float *)c->act[L - 1].p, np, vox(L), Ll.cout_store, Ll.cout, pool, s));
+    const float *dlat = dcnn;
+    if (d.cnn_dense) {
+      const int d1 = d.cnn_dense, d2 = d.cnn_dense2;
+      CF_HIP(cf::bw_rowmat(pool, Ll.cout, np, Ll.cout, P + T.dense_w, Ll.cout, P + T.dense_b, d1, pre1, d1, 0, s));
+      CF_HIP(hipMemcpyAsync(lat1, pre1, (size_t)np * d1 * sizeof(float), hipMemcpyDeviceToDevice, s));
+      CF_HIP(cf::bw_relu_rows(lat1, np, d1, d1, s));
+      if (d2) {
+        CF_HIP(cf::bw_rowmat(lat1, d1, np, d1, P + T.dense2_w, d1, P + T.dense2_b, d2, pre2, d2, 0, s));
+        CF_HIP(hipMemcpyAsync(dl2, dlat, (size_t)np * d2 * sizeof(float), hipMemcpyDeviceToDevice, s));
+        CF_HIP(cf::bw_relu_grad_rows(dl2, pre2, np, d2, s));
+        CF_HIP(cf::bw_outer(dl2, d2, lat1, d1, np, d2, d1, grad + T.dense2_w, d1, 1, pt, s));
+        CF_HIP(cf::bw_outer(dl2, d2, nullptr, 0, np, d2, 1, grad + T.dense2_b, 1, 1, pt, s));
+        CF_HIP(cf::bw_rowmat_t(dl2, d2, np, d2, P + T.dense2_w, d1, d1, dl1, d1, 0, s));
+      } else {
+        CF_HIP(hipMemcpyAsync(dl1, dlat, (size_t)np * d1 * sizeof(float), hipMemcpyDeviceToDevice, s));
+      }
+      CF_HIP(cf::bw_relu_grad_rows(dl1, pre1, np, d1, s));
+      CF_HIP(cf::bw_outer(dl1, d1, pool, Ll.cout, np, d1, Ll.cout, grad + T.dense_w, Ll.cout, 1, pt, s));
+      CF_HIP(cf::bw_outer(dl1, d1, nullptr, 0, np, d1, 1, grad + T.dense_b, 1, 1, pt, s));
+      CF_HIP(cf::bw_rowmat_t(dl1, d1, np, d1, P + T.dense_w, Ll.cout, Ll.cout, dpool, Ll.cout, 0, s));
+    } else {
+      CF_HIP(hipMemcpyAsync(dpool, dlat, (size_t)np * Ll.cout * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    CF_HIP(cf::bw_pool_seed(dpool, np, vox(L), Ll.cout_store, Ll.cout, (float *)c->dact[L - 1].p, s));
+    for (int i = 0; i < L - 1; ++i)
+      CF_HIP(cf::bw_fill((float *)c->dact[i].p, (int64_t)np * vox(i + 1) * c->conv[i].cout_store, 0.0f, s));
+    for (int i = L - 1; i >= 0; --i) {
+      const auto &Lr = c->conv[i];
+      const int taps = Lr.k * Lr.k * Lr.k;
+      float *dY = (float *)c->dact[i].p;
+      const int64_t ny = (int64_t)np * vox(i + 1) * Lr.cout_store;
+      CF_HIP(cf::bw_relu_mask(dY, (float *)c->act[i].p, ny, s));
+      if (Lr.res_src >= 1) CF_HIP(cf::bw_add((float *)c->dact[Lr.res_src - 1].p, dY, ny, s));
+      CF_HIP(cf::bw_outer(dY, Lr.cout_store, nullptr, 0, (int)(np * vox(i + 1)), Lr.cout, 1, dbf, 1, 0, pt, s));
+      const float *X = i == 0 ? (const float *)c->grid.p : (const float *)c->act[i - 1].p;
+      const int xs = i == 0 ? grid_cpad(c) : c->conv[i - 1].cout_store;
+      const int64_t Q = (int64_t)taps * Lr.cin;
+      CF_HIP(cf::bw_conv_wgrad(X, dims[i], xs, Lr.cin, dY, dims[i + 1], Lr.cout_store, Lr.cout, Lr.k, Lr.stride, np,
+                               part, s));
+      CF_HIP(cf::bw_outer(part, (int)(Lr.cout * Q), nullptr, 0, np, (int)(Lr.cout * Q), 1, dWf, 1, 0, pt, s));
+      const bool bn = d.bn != 0;
+      CF_HIP(cf::bw_fold_grad(dWf, dbf, P + T.conv_w[i], P + T.conv_b[i], bn ? P + T.bn_g[i] : nullptr,
+                              bn ? P + T.bn_m[i] : nullptr, bn ? P + T.bn_v[i] : nullptr, Lr.cout, Lr.cin, taps,
+                              grad + T.conv_w[i], grad + T.conv_b[i], bn ? grad + T.bn_g[i] : nullptr,
+                              bn ? grad + T.bn_b[i] : nullptr, bn ? grad + T.bn_m[i] : nullptr,
+                              bn ? grad + T.bn_v[i] : nullptr, s));
+      if (i > 0) {
+        CF_HIP(cf::bw_fold_wt(P + T.conv_w[i], bn ? P + T.bn_g[i] : nullptr, bn ? P + T.bn_v[i] : nullptr, Lr.cout,
+                              Lr.cin, taps, WT, s));
+        CF_HIP(cf::bw_conv_dgrad(dY, dims[i + 1], Lr.cout_store, Lr.cout, WT, Lr.cin, Lr.k, Lr.stride, dims[i], xs, np,
+                                 (float *)c->dact[i - 1].p, s));
+      }
+    }
   }
   return CF_OK;
 }

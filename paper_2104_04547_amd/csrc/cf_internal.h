@@ -172,6 +172,49 @@ hipError_t launch_sgcnn(const SgWeights &W, int bf16, const int32_t *atom_off, i
                         const int32_t *nc_col, int64_t nc_cap, int csr_global, float *hbuf,
                         int64_t hcap_atoms, float *sg_latent, int64_t *status, hipStream_t s);
 
+// ---- backward pass (cf_backward.hip): float32, deterministic reductions ----
+hipError_t bw_fill(float *p, int64_t n, float v, hipStream_t s);
+hipError_t bw_add(float *dst, const float *src, int64_t n, hipStream_t s);
+// Y[i][j] (+)= b[j] + sum_k W[j*ldw + k] X[i*ldx + k], i < n, j < J, k < K
+hipError_t bw_rowmat(const float *X, int ldx, int n, int K, const float *W, int ldw, const float *b, int J, float *Y,
+                     int ldy, int accumulate, hipStream_t s);
+// Y[i][k] (+)= sum_j W[j*ldw + k] X[i*ldx + j], i < n, j < J, k < K
+hipError_t bw_rowmat_t(const float *X, int ldx, int n, int J, const float *W, int ldw, int K, float *Y, int ldy,
+                       int accumulate, hipStream_t s);
+// A[i][f] (+)= sum over CSR row i (chunk-local ids) of S[col][f]
+hipError_t bw_agg(const int32_t *rowp, const int32_t *col, int64_t cap, const float *S, int n, int F, float *A,
+                  int accumulate, int64_t *status, hipStream_t s);
+hipError_t bw_gru_fwd(const float *GI, const float *GH, const float *Hin, int n, int H, float *Hout, hipStream_t s);
+hipError_t bw_gru_bwd(const float *GI, const float *GH, const float *Hin, const float *dHout, int n, int H, float *dGI,
+                      float *dGH, float *dHd, hipStream_t s);
+hipError_t bw_readout(const float *Gpre, const float *V, const uint8_t *is_lig, const int32_t *atom_off, int p0,
+                      int np, int H, float *S, hipStream_t s);
+hipError_t bw_readout_bwd(const float *Gpre, const float *V, const uint8_t *is_lig, const int32_t *atom_off, int p0,
+                          int np, int H, int n_atoms, const float *dS, float *dGpre, float *dV, hipStream_t s);
+// C[a*ldc + b] (+)= sum_{i < n} U[i*ldu + a] V[i*ldv + b] (V null: 1); part holds
+// bw_outer_scratch(n, A, B) floats
+int64_t bw_outer_scratch(int n, int A, int B);
+hipError_t bw_outer(const float *U, int ldu, const float *V, int ldv, int n, int A, int B, float *C, int ldc,
+                    int accumulate, float *part, hipStream_t s);
+hipError_t bw_pool_mean(const float *act, int np, int64_t vox, int cstride, int C, float *pool, hipStream_t s);
+hipError_t bw_pool_seed(const float *dpool, int np, int64_t vox, int cstride, int C, float *dact, hipStream_t s);
+hipError_t bw_relu_mask(float *d, const float *y, int64_t n, hipStream_t s);
+hipError_t bw_relu_rows(float *y, int n, int J, int ld, hipStream_t s);
+hipError_t bw_relu_grad_rows(float *d, const float *pre, int n, int J, hipStream_t s);
+hipError_t bw_fold_wt(const float *W, const float *gamma, const float *var, int cout, int cin, int taps, float *WT,
+                      hipStream_t s);
+hipError_t bw_conv_wgrad(const float *X, int D, int xstride, int cin, const float *dY, int Do, int ystride, int cout,
+                         int KS, int S, int np, float *part, hipStream_t s);
+hipError_t bw_conv_dgrad(const float *dY, int Do, int ystride, int cout, const float *WT, int cin, int KS, int S, int D,
+                         int xstride, int np, float *dX, hipStream_t s);
+hipError_t bw_fold_grad(const float *dWf, const float *dbf, const float *W, const float *b, const float *gamma,
+                        const float *mean, const float *var, int cout, int cin, int taps, float *gW, float *gb,
+                        float *ggamma, float *gbeta, float *gmean, float *gvar, hipStream_t s);
+bool bw_head_ok(int fin, int fh, int nhid);
+hipError_t bw_head(const float *cnn, int lc, const float *sg, int sgw, const float *prm, int nhid, int fh, int residual,
+                   const float *dscore, int np, float *scores, float *dcnn, float *dsg, float *part, int64_t nprm,
+                   hipStream_t s);
+
 // covalent / non-covalent widths (after padding) the staged SG-CNN kernel supports
 bool sgcnn_staged_supported(int hc, int hn);
 

@@ -19,6 +19,7 @@ class Scorer:
             raise RuntimeError("Scorer needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.arch = arch
         self.precision = precision
+        self.param_shapes = {k: np.shape(v) for k, v in params.items()}
         prec = {"bf16": cfabi.CF_PREC_BF16, "fp32": cfabi.CF_PREC_FP32}[precision]
         self.ctx = cfabi.cf_create(cfabi.pack_model(arch, params), prec, hbm_budget_bytes)
         self.lc, self.H, self.n_params, _ = cfabi.cf_model_info(self.ctx)
@@ -89,6 +90,29 @@ class Scorer:
         if out is None:
             out = torch.empty(db.n_poses, dtype=torch.float32, device="cuda")
         cfabi.cf_score_poses(self.ctx, db.c, G, out.data_ptr(), self._stream())
+        return out
+
+    def backward(self, db, G: int, dscore, with_scores: bool = True):
+        """Gradients of sum_p dscore[p] * score_p w.r.t. every blob parameter
+        (cf_backward, plain form): a device vector in blob order, and the scores."""
+        import torch
+        grad = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        scores = torch.empty(db.n_poses, dtype=torch.float32, device="cuda") if with_scores else None
+        dscore = dscore.to(device="cuda", dtype=torch.float32).contiguous()
+        cfabi.cf_backward(self.ctx, db.c, G, dscore.data_ptr(), grad.data_ptr(),
+                          scores.data_ptr() if scores is not None else None, self._stream())
+        return grad, scores
+
+    def unpack_params(self, vec) -> Dict[str, np.ndarray]:
+        """A blob-ordered parameter vector (host or device) as named arrays."""
+        v = vec.detach().cpu().numpy() if hasattr(vec, "detach") else np.asarray(vec)
+        out, o = {}, 0
+        for name in cfabi.blob_param_order(self.arch):
+            shape = self.param_shapes[name]
+            k = int(np.prod(shape)) if len(shape) else 1
+            out[name] = v[o:o + k].reshape(shape)
+            o += k
+        assert o == v.size, "vector length does not match the model"
         return out
 
     def status(self) -> Tuple[int, int, int]:
