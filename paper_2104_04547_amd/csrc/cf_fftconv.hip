@@ -306,11 +306,108 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d(const void *__restrict__ in_v
   }
 }
 
+// Overlap-save forward transform for grids of edge 2 TS beyond the 32-point
+// transforms' reach (D + k - 1 > 32): each plane is 2 x 2 tiles of TS x TS outputs.
+// A tile's input window spans TS + 2P positions per axis, from its origin - P:
+// window position w holds array position (w - P) mod 32 (the left halo wraps to
+// 32 - P .. 31), so the circular correlation of the 32-point DFTs gives the tile's
+// outputs at array positions 0 .. TS - 1 exactly (TS + 2P <= 32).  One workgroup
+// per (z, pose and tile, chunk), grid (2 TS, 4 np, nch); spectrum rows are indexed
+// by (pose, tile) planes, so the z-correlation runs on them unchanged.
+template <int KS, bool F32, int TS>
+__global__ __launch_bounds__(256) void k_fft_fwd2d_t(const void *__restrict__ in_v, void *__restrict__ xs_v, int np,
+                                                     int cin_pad, int nch) {
+  using act_t = typename std::conditional<F32, float, bf16_t>::type;
+  constexpr int kEsz = sizeof(act_t), kQ = kEsz;
+  constexpr int P = (KS - 1) / 2, W = TS + 2 * P, WP = W + 1, Dz = 2 * TS;
+  static_assert(W <= 32 && TS + P < 32 - P + 1, "window exceeds the 32-point transform");
+  const act_t *in = reinterpret_cast<const act_t *>(in_v);
+  act_t *xs = reinterpret_cast<act_t *>(xs_v);
+  int chunk, z, pv;
+  xcd_order(z, pv, chunk);
+  const int p = pv >> 2, y0 = ((pv >> 1) & 1) * TS - P, x0 = (pv & 1) * TS - P;
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  act_t *plane = reinterpret_cast<act_t *>(dyn_lds);    // [wx][wy (pitch WP)][8]
+  float2 *T = reinterpret_cast<float2 *>(dyn_lds);      // [kx][wy (pitch WP)][8]
+  const int tid = threadIdx.x;
+  const act_t *src = in + (((int64_t)p * Dz + z) * Dz * Dz) * cin_pad + chunk * 8;
+  for (int v = tid; v < W * W; v += 256) {
+    const int wy = v / W, wx = v - wy * W;
+    const int y = y0 + wy, x = x0 + wx;
+    const bool inside = y >= 0 && y < Dz && x >= 0 && x < Dz;
+#pragma unroll
+    for (int q = 0; q < kEsz / 2; ++q)
+      reinterpret_cast<uint4 *>(plane + (wx * WP + wy) * 8)[q] =
+          inside ? reinterpret_cast<const uint4 *>(src + ((int64_t)y * Dz + x) * cin_pad)[q] : make_uint4(0, 0, 0, 0);
+  }
+  __syncthreads();
+  // rows along x (window rows wy), array position a <- window column w(a)
+  {
+    const int r = tid - kColThreads;
+    const bool roww = r >= 0 && r < W * 4;
+    const int wy = r >> 2, c0 = (r & 3) * 2;
+    float re[32], im[32];
+#pragma unroll
+    for (int a = 0; a < 32; ++a) {
+      const int w = a < TS + P ? a + P : (a >= 32 - P ? a - 32 + P : -1);
+      re[a] = 0.0f;
+      im[a] = 0.0f;
+      if (roww && w >= 0) {
+        if constexpr (F32) {
+          const float2 two = *reinterpret_cast<const float2 *>(plane + (w * WP + wy) * 8 + c0);
+          re[a] = two.x;
+          im[a] = two.y;
+        } else {
+          const uint32_t two = *reinterpret_cast<const uint32_t *>(plane + (w * WP + wy) * 8 + c0);
+          re[a] = __uint_as_float(two << 16);
+          im[a] = __uint_as_float(two & 0xffff0000u);
+        }
+      }
+    }
+    __syncthreads();  // the plane is in registers; its LDS becomes the row spectra
+    if (roww) {
+      fft32<false>(re, im);
+      row_fwd_store(T, wy, c0, W, re, im);
+    }
+  }
+  __syncthreads();
+  // columns along y: array position a <- window row w(a)
+  float re[32], im[32];
+  const bool colw = tid < kColThreads;
+  const int kxp = tid >> 3, c = tid & 7;
+  if (colw) {
+#pragma unroll
+    for (int a = 0; a < 32; ++a) {
+      const int w = a < TS + P ? a + P : (a >= 32 - P ? a - 32 + P : -1);
+      const float2 v = w >= 0 ? T[(kxp * WP + w) * 8 + c] : make_float2(0.0f, 0.0f);
+      re[a] = v.x;
+      im[a] = v.y;
+    }
+    fft32<false>(re, im);
+  }
+  __syncthreads();
+  act_t *O = reinterpret_cast<act_t *>(T);  // [col][re | im][8]
+  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(W, F32));
+  if (colw) col_fwd_store<F32>(O, Zp, kxp, c, re, im);
+  __syncthreads();
+  dc_nyquist_split<F32>(Zp, O, tid);
+  __syncthreads();
+  const int64_t rowb = (int64_t)nch * 16;
+  for (int e = tid; e < kCols * kQ; e += 256) {
+    const int col = e / kQ, h = e % kQ;
+    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + pv) * Dz + z) * rowb + chunk * 16 + h * (16 / kEsz)) =
+        *reinterpret_cast<const uint4 *>(O + col * 16 + h * (16 / kEsz));
+  }
+}
+
 // ---------------------------------------------------------------- inverse
 
 // One workgroup per (z, pose, output chunk), grid (D, np, nco) in XCD order.
 // out, res: [P][D][D][D][cout_store] of bf16 (F32 = false) or float.
-template <int DT, bool F32>
+// NTL > 1 (overlap-save tiles): the plane of edge NTL * D is NTL x NTL tiles of
+// D x D outputs, each with its own spectrum; grid (NTL * D, np * NTL^2, nco), np
+// counting (pose, tile) planes.
+template <int DT, bool F32, int NTL = 1>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_inv2d(
     const void *__restrict__ ys_v, const float *__restrict__ bias, const void *__restrict__ res_v,
     void *__restrict__ out_v, int np, int D_rt, int nco, int cout_store) {
@@ -319,9 +416,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const act_t *ys = reinterpret_cast<const act_t *>(ys_v);
   const act_t *res = reinterpret_cast<const act_t *>(res_v);
   act_t *out = reinterpret_cast<act_t *>(out_v);
-  const int D = DT ? DT : D_rt;
-  int chunk, z, p;
-  xcd_order(z, p, chunk);
+  const int D = DT ? DT : D_rt;  // in-plane extent of one tile
+  const int Dz = D * NTL;        // grid edge
+  int chunk, z, pv;
+  xcd_order(z, pv, chunk);
+  const int p = pv / (NTL * NTL), y0 = (pv % (NTL * NTL)) / NTL * D, x0 = (pv % NTL) * D;
   // one dynamic LDS block (fft_lds_bytes): the spectrum, then (after its columns
   // are in registers) the column transforms, then the output plane
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
@@ -332,7 +431,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   for (int e = tid; e < kCols * kQ; e += 256) {
     const int col = e / kQ, h = e % kQ;
     *reinterpret_cast<uint4 *>(Y + col * 16 + h * (16 / kEsz)) = *reinterpret_cast<const uint4 *>(
-        ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * (16 / kEsz));
+        ys + (((int64_t)col * np + pv) * Dz + z) * rowb + chunk * 16 + h * (16 / kEsz));
   }
   __syncthreads();
   // columns along ky
@@ -386,9 +485,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         *reinterpret_cast<float2 *>(O + (x * DP + y) * 8 + c0) = make_float2(re[x] * kScale + b0, im[x] * kScale + b1);
   }
   __syncthreads();
-  const int64_t base = (((int64_t)p * D + z) * D * D) * cout_store + chunk * 8;
-  for (int v = tid; v < D * D; v += 256) {
-    const int yy = v / D, xx = v - yy * D;
+  const int64_t base = (((int64_t)p * Dz + z) * Dz * Dz) * cout_store + chunk * 8;
+  for (int v0 = tid; v0 < D * D; v0 += 256) {
+    const int yy = v0 / D, xx = v0 - yy * D;
+    const int64_t v = (int64_t)(y0 + yy) * Dz + x0 + xx;
     float f[8];
     const float4 f0 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8);
     const float4 f1 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8 + 4);
@@ -1071,6 +1171,12 @@ size_t fft_lds_bytes(int D, bool f32) { return (size_t)plane_lds_bytes(D, f32) +
 int nbt_of(const ConvLayer &L) { return L.cout * 2 / 32; }
 int esz_of(const ConvLayer &L) { return L.spec_f32 ? 4 : 2; }
 
+// overlap-save tiling for the grids of edge 32 (2 x 2 tiles of 16 x 16 outputs per
+// plane, each through a window of 16 + k - 1 <= 32 positions)
+constexpr int kTileTS = 16;
+bool fft_tiled(const ConvLayer &L, int D) { return D == 2 * kTileTS && L.k <= 7 && D + L.k - 1 > kN; }
+int fft_planes(const ConvLayer &L, int D, int np) { return fft_tiled(L, D) ? 4 * np : np; }
+
 }  // namespace
 
 bool fft_conv_layer_ok(const ConvLayer &L) {
@@ -1082,7 +1188,8 @@ bool fft_conv_layer_ok(const ConvLayer &L) {
 }
 
 bool fft_conv_ok(const ConvLayer &L, int D) {
-  if (!L.gspec || !fft_conv_layer_ok(L) || D < 1 || D + L.k - 1 > kN || D > kDMax) return false;
+  if (!L.gspec || !fft_conv_layer_ok(L)) return false;
+  if (!fft_tiled(L, D) && (D < 1 || D + L.k - 1 > kN || D > kDMax)) return false;
   if (L.spec_f32) {
     const int ppb = kRowsZH / D;
     return ppb >= 1 && ppb * (D + L.k - 1) <= kPanelRowsH;
@@ -1101,7 +1208,8 @@ int64_t fft_conv_gspec_bytes(const ConvLayer &L) {
 int64_t fft_spec_in_elems(int D, int np) { return (int64_t)kCols * np * D * 8 * 16; }
 
 int64_t fft_conv_work_bytes(const ConvLayer &L, int D, int np) {
-  return (fft_spec_in_elems(D, np) + (int64_t)kCols * np * D * (L.cout / 8) * 16) * esz_of(L);
+  const int npv = fft_planes(L, D, np);
+  return (fft_spec_in_elems(D, npv) + (int64_t)kCols * npv * D * (L.cout / 8) * 16) * esz_of(L);
 }
 
 hipError_t fft_conv_prepare(ConvLayer &L, const float *w_folded_dev, hipStream_t s) {
@@ -1118,23 +1226,25 @@ hipError_t fft_conv_prepare(ConvLayer &L, const float *w_folded_dev, hipStream_t
 
 void fft_conv_stage_cost(int stage, const ConvLayer &L, int D, int np, double *flop, double *bytes) {
   const double e = esz_of(L);
-  const double spec_in = (double)kCols * np * D * nch_of(L) * 16 * e, spec_out = (double)kCols * np * D * (L.cout / 8) * 16 * e;
+  const double npv = fft_planes(L, D, np);  // spectra per z: one per pose, or per (pose, tile)
+  const double spec_in = (double)kCols * npv * D * nch_of(L) * 16 * e, spec_out = (double)kCols * npv * D * (L.cout / 8) * 16 * e;
   const double vox = (double)np * D * D * D;
-  if (stage == 0) {  // 2-D real FFTs of D x D planes zero-padded to 32 x 32: ~2.5 N^2 log2 N^2 FLOP each
-    *flop = 2.5 * kN * kN * 10.0 * np * D * L.cin;
+  if (stage == 0) {  // 2-D real FFTs of planes zero-padded to 32 x 32: ~2.5 N^2 log2 N^2 FLOP each
+    *flop = 2.5 * kN * kN * 10.0 * npv * D * L.cin;
     *bytes = vox * L.cin_pad * e + spec_in;
   } else if (stage == 1) {  // complex multiply-adds over (dz, ci) per column and output row
-    *flop = 8.0 * L.cin * L.cout * L.k * D * kCols * np;
+    *flop = 8.0 * L.cin * L.cout * L.k * D * kCols * npv;
     *bytes = spec_in + spec_out + (double)L.gspec_bytes;
   } else {
-    *flop = 2.5 * kN * kN * 10.0 * np * D * L.cout;
+    *flop = 2.5 * kN * kN * 10.0 * npv * D * L.cout;
     *bytes = spec_out + vox * L.cout_store * e * (L.res_src >= 0 ? 2 : 1);
   }
 }
 
 bool fft_conv_fusable(const ConvLayer &L, const ConvLayer &Ln, int D) {
-  return fft_conv_ok(L, D) && fft_conv_ok(Ln, D) && L.cout == Ln.cin && Ln.cin_pad == L.cout_store &&
-         L.spec_f32 == Ln.spec_f32;
+  // tiled layers are not fused: the next layer's windows need the neighbouring tiles
+  return fft_conv_ok(L, D) && fft_conv_ok(Ln, D) && !fft_tiled(L, D) && L.cout == Ln.cin &&
+         Ln.cin_pad == L.cout_store && L.spec_f32 == Ln.spec_f32;
 }
 
 hipError_t launch_fft_mid(const ConvLayer &L, const ConvLayer &Ln, const void *res, void *out, int np, int D,
@@ -1161,10 +1271,21 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
                            hipStream_t s, int stage) {
   if (!fft_conv_ok(L, D) || !work) return hipErrorInvalidValue;
   const int nch = nch_of(L), nco = L.cout / 8;
-  const bool f32 = L.spec_f32;
+  const bool f32 = L.spec_f32, tiled = fft_tiled(L, D);
+  np = fft_planes(L, D, np);  // spectra per z: poses, or (pose, tile) planes
   char *xs = reinterpret_cast<char *>(work);
   char *ys = xs + fft_spec_in_elems(D, np) * esz_of(L);
-  if (stage < 0 || stage == 0) {
+  if ((stage < 0 || stage == 0) && tiled) {
+#define CF_FWDT(KS, F)                                                                                      \
+  hipLaunchKernelGGL((k_fft_fwd2d_t<KS, F, kTileTS>), dim3(D, np, nch), dim3(256),                            \
+                     fft_lds_bytes(kTileTS + KS - 1, F), s, in, xs, np, L.cin_pad, nch)
+    if (f32) {
+      if (L.k == 7) CF_FWDT(7, true); else if (L.k == 5) CF_FWDT(5, true); else CF_FWDT(3, true);
+    } else {
+      if (L.k == 7) CF_FWDT(7, false); else if (L.k == 5) CF_FWDT(5, false); else CF_FWDT(3, false);
+    }
+#undef CF_FWDT
+  } else if (stage < 0 || stage == 0) {
 #define CF_FWD(DT, F)                                                                               \
   hipLaunchKernelGGL((k_fft_fwd2d<DT, F>), dim3(D, np, nch), dim3(256), fft_lds_bytes(D, F), s, in, xs, np, D, \
                      L.cin_pad, nch)
@@ -1221,7 +1342,14 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
     }
 #undef CF_ZCONV
   }
-  if (stage < 0 || stage == 2) {
+  if ((stage < 0 || stage == 2) && tiled) {
+    if (f32)
+      hipLaunchKernelGGL((k_fft_inv2d<kTileTS, true, 2>), dim3(D, np, nco), dim3(256), fft_lds_bytes(kTileTS, true), s,
+                         ys, L.bias, res, out, np, kTileTS, nco, L.cout_store);
+    else
+      hipLaunchKernelGGL((k_fft_inv2d<kTileTS, false, 2>), dim3(D, np, nco), dim3(256), fft_lds_bytes(kTileTS, false),
+                         s, ys, L.bias, res, out, np, kTileTS, nco, L.cout_store);
+  } else if (stage < 0 || stage == 2) {
 #define CF_INV(DT, F)                                                                                      \
   hipLaunchKernelGGL((k_fft_inv2d<DT, F>), dim3(D, np, nco), dim3(256), fft_lds_bytes(D, F), s, ys, L.bias, res, \
                      out, np, D, nco, L.cout_store)

@@ -77,3 +77,47 @@ def test_every_conv_variant_matches_oracle(cases, arch_name, G, prec):
         assert tried >= 2
     finally:
         s.close()
+
+
+# Stride-1 layers on 32^3 activations (64^3 grids) go past the 32-point transforms
+# (32 + k - 1 > 32) and run as overlap-save tiles: 2 x 2 tiles of 16 x 16 outputs per
+# plane, each through a window of 16 + k - 1 positions.  A narrow stack covers
+# k = 7, 5 and 3, a residual add and 32 / 64 output channels on one pose.
+TILE_ARCH = dict(conv=((19, 32, 5, 2, -1), (32, 32, 7, 1, -1), (32, 32, 5, 1, 2), (32, 64, 3, 1, -1)), cnn_dense=0)
+
+
+@pytest.fixture(scope="module")
+def tiled_case():
+    import dataclasses
+    arch = dataclasses.replace(synth.ARCHS["full"], name="tile_probe", **TILE_ARCH)
+    w = synth.make_weights(arch)
+    b = synth.make_poses("c4", 1, pose0=5)
+    cen = oracle.pose_center(b.xyz[b.is_lig.astype(bool)])[None]
+    grids = oracle.splat_batch(b, cen, 64)
+    want = np.stack([oracle.cnn3d_forward(g, w, arch)[0] for g in grids])
+    return arch, w, grids, want
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_tiled_frequency_domain_layers_at_32cube(tiled_case, prec):
+    import torch
+    from paper_2104_04547_amd import Scorer, cfabi
+    arch, w, grids, want = tiled_case
+    s = Scorer(arch, w, prec)
+    try:
+        names = cfabi.cf_conv_variant_names()
+        v = list(s.variants(64))
+        assert names[v[1]] == "fft32", [names[i] for i in v]   # the 7^3 layer's default
+        v[1:] = [names.index("fft32")] * 3
+        s.set_variants(64, v)
+        _say(f"cf_cnn3d_fwd {prec} tiled frequency-domain layers, G=64, variants {[names[i] for i in v]}")
+        x = torch.from_numpy(grids.astype(np.float32)).cuda()
+        if prec == "bf16":
+            x = x.to(torch.bfloat16)
+        got = s.cnn3d(x, 64).cpu().numpy()
+        s.check()
+        scale = np.abs(want).max()
+        tol = 1e-4 if prec == "fp32" else BF16_LATENT_TOL
+        np.testing.assert_allclose(got, want, rtol=tol, atol=tol * scale)
+    finally:
+        s.close()
