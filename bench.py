@@ -236,6 +236,35 @@ def paper_leg(db, n_poses, steps):
     return res
 
 
+def backward_leg(db, batch, arch, w, G, n_poses, steps):
+    """Backward pass for fine-tuning (cf_backward, plain form): gradients of the squared
+    error (s - y)^2 / 2 against synthetic labels y = 6 pK for every parameter, over the
+    first n_poses poses of the workload."""
+    import numpy as np
+    import torch
+    from paper_2104_04547_amd import Scorer, cfabi
+    sub = cfabi.DeviceBatch.from_pose_batch(batch.select(list(range(n_poses))))
+    s = Scorer(arch, w, "fp32")
+    try:
+        scores = s.score(sub, G)
+        dscore = (scores - 6.0).contiguous()                    # d/ds of (s - y)^2 / 2 with y = 6
+        g, _ = s.backward(sub, G, dscore)                        # warm-up (allocates scratch)
+        s.check()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g, sc = s.backward(sub, G, dscore)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        s.check()
+        gn = float(torch.linalg.vector_norm(g).item())
+    finally:
+        s.close()
+    return dict(poses=n_poses, grid=G, steps=steps, ms_per_call=round(dt * 1e3, 3),
+                poses_per_s=round(n_poses / dt, 2), grad_norm=gn,
+                what="scores + gradients of every parameter (3D-CNN, SG-CNN, fusion head), float32")
+
+
 def serve_leg(arch, w, res, seconds, stream_poses=0):
     """Open-loop Poisson serving: requests of U{1..256} poses (200-1500 atoms),
     grid 48^3 or 64^3 per request, continuous batching on 4 slots with hipGraph
@@ -315,6 +344,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--backward-poses", type=int, default=64)
+    ap.add_argument("--backward-steps", type=int, default=2)
     ap.add_argument("--paper-steps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 10 device copies of MIB MiB (calibrates HBM byte counters) and exit")
@@ -409,6 +441,12 @@ def main():
     if not a.no_paper:
         paper = paper_leg(db, a.poses, a.paper_steps)
 
+    backward = None
+    if not a.no_backward:
+        backward = backward_leg(db, batch, arch, w, G, a.backward_poses, a.backward_steps)
+        log(f"backward (fp32): {backward['poses_per_s']:.1f} poses/s, {backward['ms_per_call']:.1f} ms per "
+            f"{backward['poses']}-pose call")
+
     batching = None
     if not a.no_batching:
         batching = batching_leg(arch, w, a.batch_poses, a.batch_steps)
@@ -473,6 +511,8 @@ def main():
         line["paper_model"] = paper
     if batching is not None:
         line["batching"] = batching
+    if backward is not None:
+        line["backward"] = backward
     if serving is not None:
         line["serving"] = serving
     if a.json_out:
