@@ -106,6 +106,7 @@ struct cf_ctx {
   std::vector<DevBuf> act;  // t_1 .. t_L
   std::vector<DevBuf> dact; // backward: gradients of t_1 .. t_L
   DevBuf bw_sg, bw_cnn, bw_part, bw_head;  // backward scratch
+  DevBuf splatwork;                        // per-atom normalisers and per-tile atom lists
   DevBuf convwork;          // scratch of the frequency-domain conv (spectra)
   std::map<int, std::vector<int>> variants;  // per G
 };
@@ -214,6 +215,7 @@ int64_t scratch_after(const cf_ctx *c, int G, int64_t n, int64_t atoms) {
   grow(c->cnn_lat, n * c->lc * 4);
   grow(c->sg_lat, n * c->sgw * 4);
   if (atoms > 0) {
+    grow(c->splatwork, cf::splat_work_bytes((int)n, atoms, G));
     grow(c->deg, 2 * atoms * 4);
     grow(c->pose_tot, 4 * n * 8);
     grow(c->cov_row, (atoms + 1) * 4);
@@ -836,7 +838,7 @@ void free_ctx(cf_ctx *c) {
     if (b.p) (void)hipFree(b.p);
   for (auto &b : c->dact)
     if (b.p) (void)hipFree(b.p);
-  DevBuf *bw[] = {&c->bw_sg, &c->bw_cnn, &c->bw_part, &c->bw_head};
+  DevBuf *bw[] = {&c->bw_sg, &c->bw_cnn, &c->bw_part, &c->bw_head, &c->splatwork};
   for (DevBuf *b : bw)
     if (b->p) (void)hipFree(b->p);
   if (c->convwork.p) (void)hipFree(c->convwork.p);
@@ -946,8 +948,9 @@ int cf_voxelize(cf_ctx *c, const cf_pose_batch *b, int G, void *grid_out, void *
     CF_HIP(cf::launch_centers(b->atom_off, b->n_atoms, b->xyz, b->is_lig, 0, b->n_poses, (int32_t *)c->centers.p, c->status, s));
     cen = (const int32_t *)c->centers.p;
   }
+  if ((rc = ensure(c, c->splatwork, (size_t)cf::splat_work_bytes(b->n_poses, b->n_atoms, G)))) return rc;
   CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, 0, b->n_poses, G, grid_out, c->bf16 ? 1 : 0, 0,
-                          c->status, s));
+                          c->splatwork.p, b->n_atoms, c->status, s));
   return CF_OK;
 }
 
@@ -1027,6 +1030,7 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
   if ((rc = ensure(c, c->centers, (size_t)chunk * 3 * sizeof(int32_t)))) return rc;
   if ((rc = ensure(c, c->cnn_lat, (size_t)chunk * c->lc * sizeof(float)))) return rc;
   if ((rc = ensure(c, c->sg_lat, (size_t)chunk * c->sgw * sizeof(float)))) return rc;
+  if ((rc = ensure(c, c->splatwork, (size_t)cf::splat_work_bytes(chunk, acap, G)))) return rc;
   const int H = c->sgw;
   // The graph / SG-CNN branch of each chunk runs on the context's side stream,
   // forked once the chunk's first conv layer is enqueued (ev_fork, recorded on
@@ -1049,7 +1053,7 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
     }
     hipEvent_t e = tbegin(c, s);
     CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, p0, np, G, c->grid.p, c->bf16 ? 4 : 2,
-                            grid_cpad(c), c->status, s));
+                            grid_cpad(c), c->splatwork.p, acap, c->status, s));
     tend(c, s, e, "splat", 0.0, atoms * (12.0 + 4.0 * CF_NCH) + (double)np * G * G * G * CF_NCH * elem_size(c));
     if ((rc = run_cnn(c, G, np, (float *)c->cnn_lat.p, s, c->ev_fork))) return rc;
     CF_HIP(hipStreamWaitEvent(s2, c->ev_fork, 0));
@@ -1120,6 +1124,7 @@ int cf_backward(cf_ctx *c, const cf_pose_batch *b, int G, const float *dscore, f
   if ((rc = ensure(c, c->centers, (size_t)chunk * 3 * sizeof(int32_t)))) return rc;
   if ((rc = ensure(c, c->cnn_lat, (size_t)chunk * c->lc * sizeof(float)))) return rc;
   if ((rc = ensure(c, c->sg_lat, (size_t)chunk * c->sgw * sizeof(float)))) return rc;
+  if ((rc = ensure(c, c->splatwork, (size_t)cf::splat_work_bytes(chunk, acap, G)))) return rc;
   // layer sizes
   std::vector<int> dims{G};
   for (auto &Lr : c->conv) dims.push_back(conv_out_dim(dims.back(), Lr.k, Lr.stride));
@@ -1165,7 +1170,7 @@ int cf_backward(cf_ctx *c, const cf_pose_batch *b, int G, const float *dscore, f
     if (!b->center)
       CF_HIP(cf::launch_centers(b->atom_off, b->n_atoms, b->xyz, b->is_lig, p0, np, (int32_t *)c->centers.p, c->status, s));
     CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, p0, np, G, c->grid.p, 2, grid_cpad(c),
-                            c->status, s));
+                            c->splatwork.p, acap, c->status, s));
     if ((rc = run_cnn(c, G, np, (float *)c->cnn_lat.p, s, nullptr, true))) return rc;
     CF_HIP(cf::launch_graph(b->atom_off, b->n_atoms, b->xyz, p0, np, d.r_cov_u, d.r_nc_u, (int32_t *)c->cov_row.p,
                             (int32_t *)c->cov_col.p, acap * 16, (int32_t *)c->nc_row.p, (int32_t *)c->nc_col.p,

@@ -93,9 +93,12 @@ hipError_t launch_centers(const int32_t *atom_off, int n_atoms, const int32_t *x
                           int p0, int n_poses, int32_t *center_out, int64_t *status, hipStream_t s);
 // out_mode: 0 = float [19], 1 = bf16 [19], 2 = float padded [cpad], 3 = bf16 padded [cpad],
 // 4 = bf16 4-channel chunk-major [P][cpad / 4][G^3][4]
+// work: splat_work_bytes(n_poses, atoms_cap, G) bytes of scratch (per-atom normalisers
+// and the per-tile atom lists), atoms_cap >= the atoms of poses p0 .. p0 + n_poses - 1
 hipError_t launch_splat(const int32_t *atom_off, int n_atoms, const int32_t *xyz, const float *feat,
                         const int32_t *centers, int p0, int n_poses, int G, void *grid, int out_mode,
-                        int cpad, int64_t *status, hipStream_t s);
+                        int cpad, void *work, int64_t atoms_cap, int64_t *status, hipStream_t s);
+int64_t splat_work_bytes(int n_poses, int64_t atoms, int G);
 // chunk4_vpp > 0: bf16 4-channel chunk-major output with that many voxels per pose
 hipError_t launch_grid_repack(const void *src, int src_bf16, int n_vox, void *dst, int dst_bf16,
                               int cpad, hipStream_t s, int64_t chunk4_vpp = 0);
