@@ -49,57 +49,113 @@ __device__ inline void sg_embed(const SgWeights &W, const float *__restrict__ fe
 
 // Neighbour sums of atoms [blk, blk+nblk) into A (row stride ld) and their current
 // states into Hc; rows past the pose are zero.  Each thread owns four consecutive
-// features of a row (one 16-byte load per neighbour row segment), H / 4 threads
-// share a row, and the neighbour loop keeps several rows in flight; every
-// feature's sum runs over the row's neighbours in CSR order.
-template <int H>
+// features of a row (one 16-byte load per neighbour row segment) and H / 4 threads
+// share a row.  The block's CSR rows are consecutive, so their columns form one
+// contiguous range: it is staged in LDS (idx, up to icap entries; columns beyond
+// that are read from memory) with coalesced loads, and every thread then walks NU
+// of the block's rows at once (nblk <= NU * kThreads / (H / 4)), kSlots neighbours
+// per row per step, so that up to 4 NU row loads are in flight with no index load
+// in front of them.  Every feature's sum runs over the row's neighbours in CSR order.
+template <int H, int NU>
 __device__ inline void sg_aggregate(const float *__restrict__ cur, const int32_t *__restrict__ rowp,
                                     const int32_t *__restrict__ colp, int64_t cap, int csr_global, int a0, int base,
-                                    int64_t lb, int n, int blk, int nblk, int ld, float *A, float *Hc,
-                                    int64_t *status) {
+                                    int64_t lb, int n, int blk, int nblk, int ld, float *A, float *Hc, int32_t *idx,
+                                    int icap, int64_t *status) {
   constexpr int TPR = H / 4;              // threads per row
   constexpr int RPI = kThreads / TPR;     // rows per pass
+  constexpr int kSlots = 4;               // neighbours per row per step
   static_assert(H % 4 == 0 && kThreads % TPR == 0, "row split");
   const int tr = threadIdx.x / TPR, c4 = (threadIdx.x % TPR) * 4;
-  for (int a = tr; a < nblk; a += RPI) {
-    const int i = blk + a;
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f), hc = s;
-    if (i < n) {
-      const int64_t ri = csr_global ? (int64_t)a0 + i : lb + i;
-      int64_t e0 = rowp[ri], e1 = rowp[ri + 1];
-      if (e1 > cap) e1 = cap;
-      if (e0 < 0) {
-        dev_fail(status, kDevBadGraph);
-        e0 = e1;
-      }
-      // whole batches of kGather neighbours with a branch-free body (slots past the
-      // row and columns outside the pose read the atom's own row and add nothing; a
-      // bad column is reported once after the loop), so that every batch's index and
-      // row loads are in flight together and no neighbour waits alone in a remainder
-      bool anybad = false;
-      for (int64_t q0 = e0; q0 < e1; q0 += kGather) {
-        int64_t jj[kGather];
+  const int nrow = min(nblk, n - blk);  // rows of the pose in this block (>= 1)
+  const int64_t rb = csr_global ? (int64_t)a0 + blk : lb + blk;
+  // this thread's rows and their edge ranges (empty for rows past the block)
+  int64_t e0[NU], e1[NU];
+  int64_t E0 = rowp[rb], E1 = rowp[rb + nrow];
 #pragma unroll
-        for (int u = 0; u < kGather; ++u) jj[u] = colp[q0 + u < e1 ? q0 + u : e1 - 1];
-#pragma unroll
-        for (int u = 0; u < kGather; ++u) {
-          const int64_t j = csr_global ? jj[u] - base : jj[u];
-          const bool live = q0 + u < e1;
-          const bool bad = j < lb || j >= lb + n;
-          anybad |= live && bad;
-          const bool use = live && !bad;
-          const float4 v = *reinterpret_cast<const float4 *>(cur + (use ? j : lb + i) * H + c4);
-          s.x += use ? v.x : 0.0f;
-          s.y += use ? v.y : 0.0f;
-          s.z += use ? v.z : 0.0f;
-          s.w += use ? v.w : 0.0f;
-        }
-      }
-      if (anybad) dev_fail(status, kDevBadGraph);
-      hc = *reinterpret_cast<const float4 *>(cur + (lb + i) * H + c4);
+  for (int u = 0; u < NU; ++u) {
+    const int a = tr + RPI * u;
+    e0[u] = e1[u] = 0;
+    if (a < nrow) {
+      e0[u] = rowp[rb + a];
+      e1[u] = rowp[rb + a + 1];
     }
-    *reinterpret_cast<float4 *>(A + a * ld + c4) = s;
-    *reinterpret_cast<float4 *>(Hc + a * ld + c4) = hc;
+  }
+  E1 = E1 < cap ? E1 : cap;
+  const int64_t nst = E0 < 0 || E1 <= E0 ? 0 : (E1 - E0 < icap ? E1 - E0 : icap);
+  // staged in batches of kStage loads per thread, all in flight together
+  constexpr int kStage = 4;
+  for (int64_t e0 = 0; e0 < nst; e0 += kStage * kThreads) {
+    int32_t cv[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int64_t e = e0 + u * kThreads + threadIdx.x;
+      cv[u] = e < nst ? colp[E0 + e] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int64_t e = e0 + u * kThreads + threadIdx.x;
+      if (e < nst) idx[e] = cv[u];
+    }
+  }
+  bool anybad = false;
+  int64_t len = 0;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    if (e1[u] > cap) e1[u] = cap;
+    if (e0[u] < 0) {
+      anybad = true;
+      e0[u] = e1[u];
+    }
+    len = e1[u] - e0[u] > len ? e1[u] - e0[u] : len;
+  }
+  __syncthreads();
+  float4 s[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) s[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+  // whole steps with a branch-free body: slots past a row's end and columns outside
+  // the pose read the row's own state (the pose's first row for rows past the
+  // block) and add nothing; a bad column is reported once after the loop
+  for (int64_t k = 0; k < len; k += kSlots) {
+    float4 v[NU][kSlots];
+    bool use[NU][kSlots];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int a = tr + RPI * u;
+      const int64_t self = lb + (a < nrow ? blk + a : 0);
+#pragma unroll
+      for (int w = 0; w < kSlots; ++w) {
+        const int64_t q = e0[u] + k + w;
+        const bool live = q < e1[u];
+        const int64_t qs = q - E0;
+        int64_t c = 0;
+        if (live) c = (qs >= 0 && qs < nst) ? (int64_t)idx[qs] : (int64_t)colp[q];
+        const int64_t j = csr_global ? c - base : c;
+        const bool bad = j < lb || j >= lb + n;
+        anybad |= live && bad;
+        use[u][w] = live && !bad;
+        v[u][w] = *reinterpret_cast<const float4 *>(cur + (use[u][w] ? j : self) * H + c4);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+#pragma unroll
+      for (int w = 0; w < kSlots; ++w) {
+        s[u].x += use[u][w] ? v[u][w].x : 0.0f;
+        s[u].y += use[u][w] ? v[u][w].y : 0.0f;
+        s[u].z += use[u][w] ? v[u][w].z : 0.0f;
+        s[u].w += use[u][w] ? v[u][w].w : 0.0f;
+      }
+  }
+  if (anybad) dev_fail(status, kDevBadGraph);
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int a = tr + RPI * u;
+    if (a < nblk) {
+      const float4 hc = a < nrow ? *reinterpret_cast<const float4 *>(cur + (lb + blk + a) * H + c4)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+      *reinterpret_cast<float4 *>(A + a * ld + c4) = s[u];
+      *reinterpret_cast<float4 *>(Hc + a * ld + c4) = hc;
+    }
   }
 }
 
@@ -149,7 +205,7 @@ struct SgShared {
 };
 
 template <int H>
-__global__ __launch_bounds__(kThreads) void k_sgcnn_f32(SgWeights W, const int32_t *__restrict__ atom_off,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H >= 32 ? 3 : 2))) void k_sgcnn_f32(SgWeights W, const int32_t *__restrict__ atom_off,
                                                         int n_atoms, const float *__restrict__ feat,
                                                         const uint8_t *__restrict__ is_lig, int p0,
                                                         const int32_t *__restrict__ cov_row,
@@ -197,7 +253,8 @@ __global__ __launch_bounds__(kThreads) void k_sgcnn_f32(SgWeights W, const int32
     const float *bih = W.b_ih[stage], *bhh = W.b_hh[stage];
     __syncthreads();
     for (int blk = 0; blk < n; blk += kBlk) {
-      sg_aggregate<H>(cur, rowp, colp, cap, csr_global, a0, base, lb, n, blk, kBlk, H, S.A, S.Hc, status);
+      sg_aggregate<H, (kBlk + 4 * kThreads / H - 1) / (4 * kThreads / H)>(cur, rowp, colp, cap, csr_global, a0, base, lb, n, blk, kBlk, H, S.A, S.Hc,
+                      reinterpret_cast<int32_t *>(S.M), kBlk * H, status);
       __syncthreads();
       // messages m = W_t a
       {
@@ -327,14 +384,16 @@ __device__ inline f32x16v mm_row(const float *arow, const bf16_t *bhi, const bf1
   return acc;
 }
 
-// K rounds of one stage at width H (rounds r0 .. r0+K-1 of the weight lists, GRU
-// of stage `stage`); states ping-pong between cur and nxt (row stride H).
+// One round of one stage at width H for the atoms [blk, blk + BLK) of a pose:
+// neighbour sums of the current states (cur), the round's message product, the
+// stage's GRU, the new states of those atoms written to nxt (row stride H).
 template <int H, bool F32>
-__device__ void sg_rounds(const SgWeights &W, int stage, int r0, int K, const int32_t *__restrict__ rowp,
-                          const int32_t *__restrict__ colp, int64_t cap, int csr_global, int a0, int base,
-                          int64_t lb, int n, float *&cur, float *&nxt, float *lds, int64_t *status) {
+__device__ void sg_block(const SgWeights &W, int stage, int r, const int32_t *__restrict__ rowp,
+                         const int32_t *__restrict__ colp, int64_t cap, int csr_global, int a0, int base, int64_t lb,
+                         int n, int blk, const float *cur, float *nxt, float *lds, int64_t *status) {
   using T = SgTile<H>;
   constexpr int LD = T::LD, BLK = T::BLK;
+  static_assert(BLK % (4 * kThreads / H) == 0, "whole rows per thread in the neighbour sums");
   float *A = lds, *M = lds + BLK * LD, *Hc = lds + 2 * BLK * LD;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -344,65 +403,77 @@ __device__ void sg_rounds(const SgWeights &W, int stage, int r0, int K, const in
   const float *bih = W.b_ih[stage], *bhh = W.b_hh[stage];
   const float bir = bih[ocol], biz = bih[H + ocol], bin = bih[2 * H + ocol];
   const float bhr = bhh[ocol], bhz = bhh[H + ocol], bhn = bhh[2 * H + ocol];
-  for (int r = r0; r < r0 + K; ++r) {
-    for (int blk = 0; blk < n; blk += BLK) {
-      sg_aggregate<H>(cur, rowp, colp, cap, csr_global, a0, base, lb, n, blk, BLK, LD, A, Hc, status);
-      __syncthreads();
-      // messages: M[atoms, ocol] = sum_k A[atoms, k] W_t[ocol, k]
-      {
-        f32x16v acc = {};
-        acc = mm_row<H, F32>(&A[(mb * 32 + lrow) * LD], W.msg_hi[r], W.msg_lo[r], W.msgT[r], H, ocol, khalf, acc);
+    sg_aggregate<H, BLK / (4 * kThreads / H)>(cur, rowp, colp, cap, csr_global, a0, base, lb, n, blk, BLK, LD, A, Hc,
+                  reinterpret_cast<int32_t *>(M), BLK * LD, status);
+    __syncthreads();
+    // messages: M[atoms, ocol] = sum_k A[atoms, k] W_t[ocol, k]
+    {
+      f32x16v acc = {};
+      acc = mm_row<H, F32>(&A[(mb * 32 + lrow) * LD], W.msg_hi[r], W.msg_lo[r], W.msgT[r], H, ocol, khalf, acc);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const int row = mb * 32 + 8 * (j >> 2) + 4 * khalf + (j & 3);
-          M[row * LD + ocol] = acc[j];
-        }
+      for (int j = 0; j < 16; ++j) {
+        const int row = mb * 32 + 8 * (j >> 2) + 4 * khalf + (j & 3);
+        M[row * LD + ocol] = acc[j];
       }
-      __syncthreads();
-      // GRU gates for this wave's tile, all six products from the same operands
-      {
-        f32x16v gir = {}, giz = {}, gin = {}, ghr = {}, ghz = {}, ghn = {};
-        const float *mrow = &M[(mb * 32 + lrow) * LD], *hrow = &Hc[(mb * 32 + lrow) * LD];
-        if constexpr (F32) {
-          const float *wi = W.w_ihT[stage], *wh = W.w_hhT[stage];
-          gir = mm_row<H, true>(mrow, nullptr, nullptr, wi, 3 * H, ocol, khalf, gir);
-          giz = mm_row<H, true>(mrow, nullptr, nullptr, wi, 3 * H, H + ocol, khalf, giz);
-          gin = mm_row<H, true>(mrow, nullptr, nullptr, wi, 3 * H, 2 * H + ocol, khalf, gin);
-          ghr = mm_row<H, true>(hrow, nullptr, nullptr, wh, 3 * H, ocol, khalf, ghr);
-          ghz = mm_row<H, true>(hrow, nullptr, nullptr, wh, 3 * H, H + ocol, khalf, ghz);
-          ghn = mm_row<H, true>(hrow, nullptr, nullptr, wh, 3 * H, 2 * H + ocol, khalf, ghn);
-        } else {
-          const bf16_t *ih = W.ih_hi[stage], *il = W.ih_lo[stage], *hh = W.hh_hi[stage], *hl = W.hh_lo[stage];
-          constexpr int kUnroll = H <= 64 ? H / 16 : 2;  // wider: bounded unroll keeps it in registers
-#pragma unroll kUnroll
-          for (int ks = 0; ks < H / 16; ++ks) {
-            bf16x8 mhi, mlo, hhi, hlo;
-            split8(mrow + ks * 16 + khalf * 8, mhi, mlo);
-            split8(hrow + ks * 16 + khalf * 8, hhi, hlo);
-            const int64_t w0 = ((int64_t)ks * 3 * H + ocol) * 16 + khalf * 8;
-            const int64_t gs = (int64_t)H * 16;  // next gate's rows
-            gir = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0), *reinterpret_cast<const bf16x8 *>(il + w0), gir);
-            giz = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0 + gs), *reinterpret_cast<const bf16x8 *>(il + w0 + gs), giz);
-            gin = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0 + 2 * gs), *reinterpret_cast<const bf16x8 *>(il + w0 + 2 * gs), gin);
-            ghr = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0), *reinterpret_cast<const bf16x8 *>(hl + w0), ghr);
-            ghz = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0 + gs), *reinterpret_cast<const bf16x8 *>(hl + w0 + gs), ghz);
-            ghn = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0 + 2 * gs), *reinterpret_cast<const bf16x8 *>(hl + w0 + 2 * gs), ghn);
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const int row = mb * 32 + 8 * (j >> 2) + 4 * khalf + (j & 3);
-          const int i = blk + row;
-          if (i < n) {
-            const float rr = sigm(gir[j] + bir + ghr[j] + bhr);
-            const float zz = sigm(giz[j] + biz + ghz[j] + bhz);
-            const float nn = tanhf(gin[j] + bin + rr * (ghn[j] + bhn));
-            nxt[(lb + i) * H + ocol] = (1.0f - zz) * nn + zz * Hc[row * LD + ocol];
-          }
-        }
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    // GRU gates for this wave's tile: the reset and update gates accumulate their
+    // input and hidden products in one accumulator each; the candidate keeps them
+    // apart (the reset gate scales only the hidden part)
+    {
+      f32x16v gr = {}, gz = {}, gin = {}, ghn = {};
+      const float *mrow = &M[(mb * 32 + lrow) * LD], *hrow = &Hc[(mb * 32 + lrow) * LD];
+      if constexpr (F32) {
+        const float *wi = W.w_ihT[stage], *wh = W.w_hhT[stage];
+        gr = mm_row<H, true>(mrow, nullptr, nullptr, wi, 3 * H, ocol, khalf, gr);
+        gr = mm_row<H, true>(hrow, nullptr, nullptr, wh, 3 * H, ocol, khalf, gr);
+        gz = mm_row<H, true>(mrow, nullptr, nullptr, wi, 3 * H, H + ocol, khalf, gz);
+        gz = mm_row<H, true>(hrow, nullptr, nullptr, wh, 3 * H, H + ocol, khalf, gz);
+        gin = mm_row<H, true>(mrow, nullptr, nullptr, wi, 3 * H, 2 * H + ocol, khalf, gin);
+        ghn = mm_row<H, true>(hrow, nullptr, nullptr, wh, 3 * H, 2 * H + ocol, khalf, ghn);
+      } else {
+        const bf16_t *ih = W.ih_hi[stage], *il = W.ih_lo[stage], *hh = W.hh_hi[stage], *hl = W.hh_lo[stage];
+        constexpr int kUnroll = H <= 64 ? H / 16 : 2;  // wider: bounded unroll keeps it in registers
+#pragma unroll kUnroll
+        for (int ks = 0; ks < H / 16; ++ks) {
+          bf16x8 mhi, mlo, hhi, hlo;
+          split8(mrow + ks * 16 + khalf * 8, mhi, mlo);
+          split8(hrow + ks * 16 + khalf * 8, hhi, hlo);
+          const int64_t w0 = ((int64_t)ks * 3 * H + ocol) * 16 + khalf * 8;
+          const int64_t gs = (int64_t)H * 16;  // next gate's rows
+          gr = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0), *reinterpret_cast<const bf16x8 *>(il + w0), gr);
+          gr = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0), *reinterpret_cast<const bf16x8 *>(hl + w0), gr);
+          gz = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0 + gs), *reinterpret_cast<const bf16x8 *>(il + w0 + gs), gz);
+          gz = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0 + gs), *reinterpret_cast<const bf16x8 *>(hl + w0 + gs), gz);
+          gin = mfma3(mhi, mlo, *reinterpret_cast<const bf16x8 *>(ih + w0 + 2 * gs), *reinterpret_cast<const bf16x8 *>(il + w0 + 2 * gs), gin);
+          ghn = mfma3(hhi, hlo, *reinterpret_cast<const bf16x8 *>(hh + w0 + 2 * gs), *reinterpret_cast<const bf16x8 *>(hl + w0 + 2 * gs), ghn);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int row = mb * 32 + 8 * (j >> 2) + 4 * khalf + (j & 3);
+        const int i = blk + row;
+        if (i < n) {
+          const float rr = sigm(gr[j] + (bir + bhr));
+          const float zz = sigm(gz[j] + (biz + bhz));
+          const float nn = tanhf(gin[j] + bin + rr * (ghn[j] + bhn));
+          nxt[(lb + i) * H + ocol] = (1.0f - zz) * nn + zz * Hc[row * LD + ocol];
+        }
+      }
+    }
+    __syncthreads();
+}
+
+// K rounds of one stage at width H (rounds r0 .. r0+K-1 of the weight lists, GRU
+// of stage `stage`) over all the pose's atom blocks; states ping-pong between cur
+// and nxt (row stride H).
+template <int H, bool F32>
+__device__ void sg_rounds(const SgWeights &W, int stage, int r0, int K, const int32_t *__restrict__ rowp,
+                          const int32_t *__restrict__ colp, int64_t cap, int csr_global, int a0, int base,
+                          int64_t lb, int n, float *&cur, float *&nxt, float *lds, int64_t *status) {
+  for (int r = r0; r < r0 + K; ++r) {
+    for (int blk = 0; blk < n; blk += SgTile<H>::BLK)
+      sg_block<H, F32>(W, stage, r, rowp, colp, cap, csr_global, a0, base, lb, n, blk, cur, nxt, lds, status);
     __threadfence();
     __syncthreads();
     float *tmp = cur;
