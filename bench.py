@@ -50,9 +50,30 @@ def load_scores(cfg, G, tag=""):
     return None if gd is None else np.array([p["score"] for p in gd["poses"]], np.float64)
 
 
+def provenance(batch, arch, w, seed_poses=0):
+    """What the run read: SHA-256 of the pose arrays and of the model blob, the
+    seeds, the library file and the host, so that a line can be matched to its inputs."""
+    import hashlib
+    import platform
+    from paper_2104_04547_amd import cfabi
+    h = hashlib.sha256()
+    for arr in (batch.atom_off, batch.xyz, batch.feat, batch.is_lig):
+        h.update(memoryview(arr).cast("B"))
+    lib = cfabi.LIB_PATH
+    return {"inputs_sha256": h.hexdigest(),
+            "weights_sha256": hashlib.sha256(cfabi.pack_model(arch, w)).hexdigest(),
+            "library_sha256": hashlib.sha256(open(lib, "rb").read()).hexdigest() if os.path.exists(lib) else None,
+            "seed_poses": seed_poses, "seed_weights": 1, "host": platform.node(), "host_cpus": os.cpu_count(),
+            "time_utc": time.strftime("%Y-%m-%dT%H:%M:%SZ", time.gmtime())}
+
+
+ROCTX = False  # --roctx: stage ranges for a tracer around every scoring call
+
+
 def time_steps(scorer, db, G, steps, warmup, out, timing=False):
     import torch
     from paper_2104_04547_amd import cfabi
+    cfabi.cf_timing_enable(scorer.ctx, False, roctx=ROCTX)
     for _ in range(warmup):
         scorer.score(db, G, out)
     torch.cuda.synchronize()
@@ -61,7 +82,7 @@ def time_steps(scorer, db, G, steps, warmup, out, timing=False):
         raise RuntimeError(f"device status {rc}: {cfabi.cf_last_error()}")
     if timing:
         cfabi.cf_timing_read(scorer.ctx)          # drop warm-up entries
-        cfabi.cf_timing_enable(scorer.ctx, True)
+        cfabi.cf_timing_enable(scorer.ctx, True, roctx=ROCTX)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -71,7 +92,7 @@ def time_steps(scorer, db, G, steps, warmup, out, timing=False):
     stats = None
     if timing:
         stats = cfabi.cf_timing_read(scorer.ctx)
-        cfabi.cf_timing_enable(scorer.ctx, False)
+        cfabi.cf_timing_enable(scorer.ctx, False, roctx=ROCTX)
     rc = scorer.status()[0]
     if rc != 0:
         raise RuntimeError(f"device status {rc}: {cfabi.cf_last_error()}")
@@ -351,7 +372,13 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 10 device copies of MIB MiB (calibrates HBM byte counters) and exit")
     ap.add_argument("--json-out", default="")
+    ap.add_argument("--roctx", action="store_true",
+                    help="roctx ranges around each chunk's stages (for rocprofv3 --marker-trace)")
+    ap.add_argument("--run-log", default="", metavar="PATH",
+                    help="append the result line, with its provenance, to this JSONL file")
     a = ap.parse_args()
+    global ROCTX
+    ROCTX = a.roctx
 
     if a.gpus != 1:
         print(f"bench.py measures one GPU: this build scores poses on a single MI355X and has no "
@@ -515,8 +542,12 @@ def main():
         line["backward"] = backward
     if serving is not None:
         line["serving"] = serving
+    line["provenance"] = provenance(batch, arch, w)
     if a.json_out:
         json.dump(line, open(a.json_out, "w"), indent=1)
+    if a.run_log:
+        with open(a.run_log, "a") as fh:
+            fh.write(json.dumps(line) + "\n")
     print(json.dumps(line))
 
 

@@ -252,6 +252,13 @@ typedef struct {
   double flop;
   double bytes;
 } cf_kernel_stat;
+/* enable: a bit set of CF_TIMING_EVENTS (the event pairs above) and CF_TIMING_ROCTX
+ * (roctx ranges "cf.splat", "cf.cnn3d", "cf.graph_sgcnn", "cf.head" around what
+ * cf_score_poses enqueues for each chunk, for a tracer such as rocprofv3
+ * --marker-trace; the roctx library is opened at run time and, when it is absent,
+ * the ranges are skipped).  0 turns both off. */
+#define CF_TIMING_EVENTS 1
+#define CF_TIMING_ROCTX 2
 int cf_timing_enable(cf_ctx *ctx, int enable);
 int cf_timing_read(cf_ctx *ctx, cf_kernel_stat *out, int32_t max_entries, int32_t *n_out);
 

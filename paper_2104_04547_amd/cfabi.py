@@ -304,8 +304,12 @@ def cf_top_k_noalloc(values_ptr: int, n: int, k: int, idx_ptr: int, val_ptr, str
     _check(load().cf_top_k_noalloc(values_ptr, n, k, idx_ptr, val_ptr, stream))
 
 
-def cf_timing_enable(ctx, enable: bool = True):
-    _check(load().cf_timing_enable(ctx, int(enable)))
+CF_TIMING_EVENTS, CF_TIMING_ROCTX = 1, 2
+
+
+def cf_timing_enable(ctx, enable: bool = True, roctx: bool = False):
+    """Per-launch event timing and / or roctx stage ranges (see cf.h)."""
+    _check(load().cf_timing_enable(ctx, (CF_TIMING_EVENTS if enable else 0) | (CF_TIMING_ROCTX if roctx else 0)))
 
 
 def cf_timing_read(ctx):

@@ -1,5 +1,6 @@
 // C ABI of the pose scorer: context, weight preparation, scratch management and
 // the scoring entry points declared in include/cf.h.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -94,6 +95,7 @@ struct cf_ctx {
     double ms = 0, flop = 0, bytes = 0;
   };
   bool timing = false;
+  bool roctx = false;  // stage ranges for a tracer (cf_timing_enable, CF_TIMING_ROCTX)
   std::vector<Pending> pending;
   std::map<std::string, Stat> stats;
 
@@ -141,6 +143,45 @@ int ensure(cf_ctx *c, DevBuf &b, size_t bytes) {
 }
 
 int conv_out_dim(int D, int k, int s) { return (D + 2 * ((k - 1) / 2) - k) / s + 1; }
+
+// roctx ranges around the stages a scoring call enqueues (CF_TIMING_ROCTX), so that
+// a tracer (rocprofv3 --marker-trace) groups the kernels by stage.  The tracer's
+// library is opened at run time on first use: no link-time dependency, and a
+// process without it gets no ranges.
+struct RoctxApi {
+  int (*push)(const char *) = nullptr;
+  int (*pop)() = nullptr;
+  RoctxApi() {
+    // the profiler SDK's roctx (what rocprofv3 records), else the older roctracer one
+    const char *names[] = {"librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so", "libroctx64.so.4",
+                           "libroctx64.so"};
+    void *h = nullptr;
+    for (const char *n : names)
+      if (!h) h = dlopen(n, RTLD_NOW | RTLD_LOCAL);
+    if (!h) return;
+    push = reinterpret_cast<int (*)(const char *)>(dlsym(h, "roctxRangePushA"));
+    pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (!push || !pop) push = nullptr, pop = nullptr;
+  }
+};
+const RoctxApi &roctx_api() {
+  static const RoctxApi api;  // initialised once, thread-safe
+  return api;
+}
+class Range {
+ public:
+  Range(const cf_ctx *c, const char *name) : on_(c->roctx && roctx_api().push) {
+    if (on_) roctx_api().push(name);
+  }
+  ~Range() {
+    if (on_) roctx_api().pop();
+  }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+
+ private:
+  bool on_;
+};
 
 // Event pair around one launch on its own stream (only when timing is enabled).
 hipEvent_t tbegin(cf_ctx *c, hipStream_t s) {
@@ -1052,10 +1093,18 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
       cen = (const int32_t *)c->centers.p;
     }
     hipEvent_t e = tbegin(c, s);
-    CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, p0, np, G, c->grid.p, c->bf16 ? 4 : 2,
-                            grid_cpad(c), c->splatwork.p, acap, c->status, s));
+    {
+      Range r(c, "cf.splat");
+      CF_HIP(cf::launch_splat(b->atom_off, b->n_atoms, b->xyz, b->feat, cen, p0, np, G, c->grid.p, c->bf16 ? 4 : 2,
+                              grid_cpad(c), c->splatwork.p, acap, c->status, s));
+    }
     tend(c, s, e, "splat", 0.0, atoms * (12.0 + 4.0 * CF_NCH) + (double)np * G * G * G * CF_NCH * elem_size(c));
-    if ((rc = run_cnn(c, G, np, (float *)c->cnn_lat.p, s, c->ev_fork))) return rc;
+    {
+      Range r(c, "cf.cnn3d");
+      if ((rc = run_cnn(c, G, np, (float *)c->cnn_lat.p, s, c->ev_fork))) return rc;
+    }
+    {
+    Range rg(c, "cf.graph_sgcnn");
     CF_HIP(hipStreamWaitEvent(s2, c->ev_fork, 0));
     hipEvent_t eg = tbegin(c, s2);
     CF_HIP(cf::launch_graph(b->atom_off, b->n_atoms, b->xyz, p0, np, c->desc.r_cov_u, c->desc.r_nc_u, (int32_t *)c->cov_row.p,
@@ -1080,7 +1129,9 @@ int cf_score_poses(cf_ctx *c, const cf_pose_batch *b, int G, float *scores, void
                             acap * 96, 0, (float *)c->hbuf.p, acap, (float *)c->sg_lat.p, c->status, s2));
     tend(c, s2, eg, "sgcnn", atoms * c->sg_flop_atom, atoms * 4.0 * CF_NCH);
     CF_HIP(hipEventRecord(c->ev_sg, s2));
+    }
     CF_HIP(hipStreamWaitEvent(s, c->ev_sg, 0));
+    Range rh(c, "cf.head");
     e = tbegin(c, s);
     CF_HIP(cf::launch_head((float *)c->cnn_lat.p, c->lc, (float *)c->sg_lat.p, H, c->head_prm, c->head, np,
                            scores + p0, s));
@@ -1355,7 +1406,8 @@ int cf_stream_status(cf_ctx *c, void *stream, int64_t *need_cov, int64_t *need_n
 
 int cf_timing_enable(cf_ctx *c, int enable) {
   if (!c) return fail(CF_ERR_INVALID_ARG, "ctx is NULL");
-  c->timing = enable != 0;
+  c->timing = (enable & CF_TIMING_EVENTS) != 0;
+  c->roctx = (enable & CF_TIMING_ROCTX) != 0;
   return CF_OK;
 }
 

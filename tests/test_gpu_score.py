@@ -228,3 +228,21 @@ def test_score_device_reports_bad_features(scorers):
     rc, _, _ = s.status()
     assert rc == cfabi.CF_ERR_INVALID_ARG
     assert s.status()[0] == 0                # the status word was cleared
+
+
+def test_score_with_roctx_ranges_and_timing_unchanged(scorers):
+    # stage ranges for a tracer and per-launch event timing only observe: the
+    # scores are bitwise those of a plain call
+    from paper_2104_04547_amd import cfabi
+    _say("cf_score_poses bf16 c2 G=48 poses=8 with CF_TIMING_ROCTX | CF_TIMING_EVENTS")
+    s = scorers[("full", "bf16")]
+    b = synth.make_poses("c2", 8)
+    plain = _score(s, b, 48)
+    cfabi.cf_timing_enable(s.ctx, True, roctx=True)
+    try:
+        traced = _score(s, b, 48)
+        stats = cfabi.cf_timing_read(s.ctx)
+    finally:
+        cfabi.cf_timing_enable(s.ctx, False)
+    assert np.array_equal(plain, traced)
+    assert "splat" in stats and stats["splat"]["launches"] >= 1
