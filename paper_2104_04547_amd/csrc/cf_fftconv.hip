@@ -76,10 +76,10 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
 }
 
 // One complex value of channel c from a spectrum row [col][re | im][8]: fp32
-// directly; bf16 by lane pairs (c, c ^ 1) that read two channels at once (even
-// lanes the re pair, odd lanes the im pair) and swap halves, so both lanes of a
-// pair must be active.
-template <bool F32>
+// directly; bf16 by lane pairs (c, c ^ 1), LX lanes apart, that read two channels
+// at once (even channels the re pair, odd channels the im pair) and swap halves,
+// so both lanes of a pair must be active.
+template <bool F32, int LX = 1>
 __device__ inline void spec_get(const void *Y, int col, int c, float &r, float &i) {
   if constexpr (F32) {
     const float *Yf = reinterpret_cast<const float *>(Y);
@@ -91,14 +91,14 @@ __device__ inline void spec_get(const void *Y, int col, int c, float &r, float &
   const bool odd = c & 1;
   const uint32_t two = Yw[col * 8 + (odd ? 4 : 0) + (c >> 1)];
   const float lo = __uint_as_float(two << 16), hi = __uint_as_float(two & 0xffff0000u);
-  const float other = __shfl_xor(odd ? lo : hi, 1);
+  const float other = __shfl_xor(odd ? lo : hi, LX);
   r = odd ? other : lo;
   i = odd ? hi : other;
 }
 
 // The inverse of spec_get: fp32 directly; bf16 lane pairs swap halves so that
 // each lane stores two channels as one 32-bit word, rounded to bf16.
-template <bool F32>
+template <bool F32, int LX = 1>
 __device__ inline void spec_put(void *Ov, int col, int c, float r, float i) {
   if constexpr (F32) {
     float *Of = reinterpret_cast<float *>(Ov);
@@ -108,7 +108,7 @@ __device__ inline void spec_put(void *Ov, int col, int c, float r, float i) {
   }
   uint32_t *O = reinterpret_cast<uint32_t *>(Ov);
   const bool odd = c & 1;
-  const float other = __shfl_xor(odd ? r : i, 1);
+  const float other = __shfl_xor(odd ? r : i, LX);
   O[col * 8 + (odd ? 4 : 0) + (c >> 1)] = pack_bf16x2(odd ? other : r, odd ? i : other);
 }
 
@@ -650,6 +650,226 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int col = e / kQ, h = e % kQ;
     *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * (16 / kEsz)) =
         *reinterpret_cast<const uint4 *>(O + col * 16 + h * (16 / kEsz));
+  }
+}
+
+// ---------------------------------------------------------------- lane-pair transforms
+//
+// The fused transform with every 32-point FFT shared by two adjacent lanes
+// (fft32_pair_dit / fft32_pair_dif): the column phases then run on all 256
+// threads (128 (column, channel) pairs) and the row phase on 8 D threads, each
+// lane holding 16 points instead of 32, so that all four waves work in every phase
+// and the register file holds half the transform state.  Lane h = tid & 1 of a
+// pair, partner tid ^ 1 (a quad permutation, so the exchange is a DPP move); the
+// channel pair (c, c ^ 1) of a bf16 spectrum access is two lanes apart.
+
+__device__ inline float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // lanes 1,0,3,2
+}
+
+// inverse columns, decimation in time: lane h takes ky = 2n + h (columns 1 .. 15
+// from the spectrum; the packed DC / Nyquist column from Zp)
+template <bool F32>
+__device__ inline void col_inv_load2(const void *Y, int kxp, int c, int h, float (&re)[16], float (&im)[16]) {
+#pragma unroll
+  for (int n = 0; n < 16; ++n) spec_get<F32, 2>(Y, (2 * n + h) * kNX + kxp, c, re[n], im[n]);
+}
+__device__ inline void col_inv_load_dc2(const float2 *Zp, int c, int h, float (&re)[16], float (&im)[16]) {
+#pragma unroll
+  for (int n = 0; n < 16; ++n) {
+    const float2 v = Zp[(2 * n + h) * 8 + c];
+    re[n] = v.x;
+    im[n] = v.y;
+  }
+}
+// after fft32_pair_dit<true>: lane h holds y = 16 h + k; rows y < D of T
+__device__ inline void col_inv_store2(float2 *T, int kxp, int c, int h, int D, const float (&re)[16],
+                                      const float (&im)[16]) {
+  const int DP = D + 1;
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (16 * h + k < D) T[(kxp * DP + 16 * h + k) * 8 + c] = make_float2(re[k], im[k]);
+}
+// rows, inverse: lane h takes Z[2n + h] of the complex sequence A + i B of the two
+// channels' Hermitian halves (Z[0], Z[16] from the packed column)
+__device__ inline void row_inv_load2(const float2 *T, int y, int c0, int h, int D, float (&re)[16], float (&im)[16]) {
+  const int DP = D + 1;
+#pragma unroll
+  for (int n = 0; n < 16; ++n) {
+    const int k = 2 * n + h;
+    if (k == 0 || k == 16) {
+      const float4 dc = *reinterpret_cast<const float4 *>(T + y * 8 + c0);  // A0, A16, B0, B16
+      re[n] = k ? dc.y : dc.x;
+      im[n] = k ? dc.w : dc.z;
+    } else if (k < 16) {
+      const float4 ab = *reinterpret_cast<const float4 *>(T + (k * DP + y) * 8 + c0);
+      re[n] = ab.x - ab.w;
+      im[n] = ab.y + ab.z;
+    } else {
+      const float4 ab = *reinterpret_cast<const float4 *>(T + ((32 - k) * DP + y) * 8 + c0);
+      re[n] = ab.x + ab.w;
+      im[n] = ab.z - ab.y;
+    }
+  }
+}
+// rows, forward, after fft32_pair_dif<false> (lane h holds X[2m + h]): the row
+// spectra of the two channels at the frequencies of this lane's parity
+__device__ inline void row_fwd_store2(float2 *T, int y, int c0, int h, int D, const float (&re)[16],
+                                      const float (&im)[16]) {
+  const int DP = D + 1;
+  if (!h) *reinterpret_cast<float4 *>(T + y * 8 + c0) = make_float4(re[0], re[8], im[0], im[8]);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int k = 2 * m + h;  // 1 .. 15 (k = 0 is the packed column)
+    if (k == 0) continue;
+    const int j = 16 - m - h;  // index of X[32 - k] in this lane
+    *reinterpret_cast<float4 *>(T + (k * DP + y) * 8 + c0) =
+        make_float4(0.5f * (re[m] + re[j]), 0.5f * (im[m] - im[j]), 0.5f * (im[m] + im[j]), -0.5f * (re[m] - re[j]));
+  }
+}
+// forward columns, decimation in frequency: lane h takes y = 16 h + n (zero past D)
+__device__ inline void col_fwd_load2(const float2 *T, int kxp, int c, int h, int D, float (&re)[16], float (&im)[16]) {
+  const int DP = D + 1;
+#pragma unroll
+  for (int n = 0; n < 16; ++n) {
+    const int y = 16 * h + n;
+    const float2 v = y < D ? T[(kxp * DP + y) * 8 + c] : make_float2(0.0f, 0.0f);
+    re[n] = v.x;
+    im[n] = v.y;
+  }
+}
+// after fft32_pair_dif<false>: lane h holds ky = 2m + h of column kxp (spectrum), or
+// of the packed column (Zp)
+template <bool F32>
+__device__ inline void col_fwd_store2(void *O, float2 *Zp, int kxp, int c, int h, const float (&re)[16],
+                                      const float (&im)[16]) {
+  if (kxp) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) spec_put<F32, 2>(O, (2 * m + h) * kNX + kxp, c, re[m], im[m]);
+  } else {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) Zp[(2 * m + h) * 8 + c] = make_float2(re[m], im[m]);
+  }
+}
+
+// k_fft_mid with lane-pair transforms (same grid, LDS and results up to rounding)
+template <int DT, bool F32>
+__global__ __launch_bounds__(256) void k_fft_mid2(const void *__restrict__ ys_v, const float *__restrict__ bias,
+                                                  const void *__restrict__ res_v, void *__restrict__ out_v,
+                                                  void *__restrict__ xs_v, int np, int D_rt, int nch, int cout_store,
+                                                  int lds_spec) {
+  using act_t = typename std::conditional<F32, float, bf16_t>::type;
+  constexpr int kEsz = sizeof(act_t), kQ = kEsz;
+  const act_t *ys = reinterpret_cast<const act_t *>(ys_v);
+  const act_t *res = reinterpret_cast<const act_t *>(res_v);
+  act_t *out = reinterpret_cast<act_t *>(out_v);
+  act_t *xs = reinterpret_cast<act_t *>(xs_v);
+  const int D = DT ? DT : D_rt;
+  int chunk, z, p;
+  xcd_order(z, p, chunk);
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  act_t *Y = reinterpret_cast<act_t *>(dyn_lds);
+  float2 *T = reinterpret_cast<float2 *>(dyn_lds);
+  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D, F32));
+  act_t *R = reinterpret_cast<act_t *>(dyn_lds + lds_spec);
+  const int tid = threadIdx.x, h = tid & 1, q = tid >> 1;
+  const int64_t rowb = (int64_t)nch * 16;
+  const int64_t base = (((int64_t)p * D + z) * D * D) * cout_store + chunk * 8;
+  for (int e = tid; e < kCols * kQ; e += 256) {
+    const int col = e / kQ, hh = e % kQ;
+    *reinterpret_cast<uint4 *>(Y + col * 16 + hh * (16 / kEsz)) = *reinterpret_cast<const uint4 *>(
+        ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + hh * (16 / kEsz));
+  }
+  if (res)
+    for (int v = tid; v < D * D; v += 256)
+#pragma unroll
+      for (int qq = 0; qq < kEsz / 2; ++qq)
+        reinterpret_cast<uint4 *>(R + v * 8)[qq] = reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store)[qq];
+  __syncthreads();
+  const int kxp = q >> 3, c = q & 7;  // column pair of the column phases
+  // inverse columns along ky
+  {
+    float re[16], im[16];
+    dc_nyquist_pack<F32>(Y, Zp, tid);
+    if (kxp) col_inv_load2<F32>(Y, kxp, c, h, re, im);
+    __syncthreads();
+    if (!kxp) col_inv_load_dc2(Zp, c, h, re, im);
+    fft32_pair_dit<true>(re, im, h, pair_swap);
+    col_inv_store2(T, kxp, c, h, D, re, im);
+  }
+  __syncthreads();
+  // rows along x: inverse of two channels, epilogue (bf16 rounding in the bf16
+  // form), then their forward transform (the next layer's input rows)
+  {
+    const bool roww = tid < 8 * D;
+    const int y = q >> 2, c0 = (q & 3) * 2;
+    float re[16], im[16];
+    if (roww) {
+      row_inv_load2(T, y, c0, h, D, re, im);
+      fft32_pair_dit<true>(re, im, h, pair_swap);
+      constexpr float kScale = 1.0f / (kN * kN);
+      const float b0 = bias[chunk * 8 + c0], b1 = bias[chunk * 8 + c0 + 1];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int x = 16 * h + j;
+        if (x < D) {
+          float v0 = re[j] * kScale + b0, v1 = im[j] * kScale + b1;
+          if constexpr (F32) {
+            if (res) {
+              const float2 two = *reinterpret_cast<const float2 *>(R + (y * D + x) * 8 + c0);
+              v0 += two.x;
+              v1 += two.y;
+            }
+            v0 = v0 > 0.0f ? v0 : 0.0f;
+            v1 = v1 > 0.0f ? v1 : 0.0f;
+            if (out) *reinterpret_cast<float2 *>(R + (y * D + x) * 8 + c0) = make_float2(v0, v1);
+            re[j] = v0;
+            im[j] = v1;
+          } else {
+            if (res) {
+              const uint32_t two = *reinterpret_cast<const uint32_t *>(R + (y * D + x) * 8 + c0);
+              v0 += __uint_as_float(two << 16);
+              v1 += __uint_as_float(two & 0xffff0000u);
+            }
+            const bf16_t h0 = (bf16_t)(v0 > 0.0f ? v0 : 0.0f), h1 = (bf16_t)(v1 > 0.0f ? v1 : 0.0f);
+            if (out)
+              *reinterpret_cast<uint32_t *>(R + (y * D + x) * 8 + c0) =
+                  (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+            re[j] = (float)h0;
+            im[j] = (float)h1;
+          }
+        } else {
+          re[j] = 0.0f;
+          im[j] = 0.0f;
+        }
+      }
+      fft32_pair_dif<false>(re, im, h, pair_swap);
+      // no barrier between reading and rewriting T: each lane reads the row spectra
+      // at the frequencies of its own parity (the mirror 32 - k has the same parity)
+      // and writes back exactly those slots; the partner's values came by DPP
+      row_fwd_store2(T, y, c0, h, D, re, im);
+    }
+  }
+  __syncthreads();
+  if (out)
+    for (int v = tid; v < D * D; v += 256)
+#pragma unroll
+      for (int qq = 0; qq < kEsz / 2; ++qq)
+        reinterpret_cast<uint4 *>(out + base + (int64_t)v * cout_store)[qq] = reinterpret_cast<const uint4 *>(R + v * 8)[qq];
+  // forward columns along y
+  float re[16], im[16];
+  col_fwd_load2(T, kxp, c, h, D, re, im);
+  fft32_pair_dif<false>(re, im, h, pair_swap);
+  __syncthreads();
+  act_t *O = reinterpret_cast<act_t *>(T);
+  col_fwd_store2<F32>(O, Zp, kxp, c, h, re, im);
+  __syncthreads();
+  dc_nyquist_split<F32>(Zp, O, tid);
+  __syncthreads();
+  for (int e = tid; e < kCols * kQ; e += 256) {
+    const int col = e / kQ, hh = e % kQ;
+    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + hh * (16 / kEsz)) =
+        *reinterpret_cast<const uint4 *>(O + col * 16 + hh * (16 / kEsz));
   }
 }
 
@@ -1258,11 +1478,15 @@ hipError_t launch_fft_mid(const ConvLayer &L, const ConvLayer &Ln, const void *r
 #define CF_MID(DT, F)                                                                                   \
   hipLaunchKernelGGL((k_fft_mid<DT, F>), dim3(D, np, nch), dim3(256), lds, s, ys, L.bias, res, out, xs, np, D, nch, \
                      L.cout_store, (int)spec)
+#define CF_MID2(DT, F)                                                                                  \
+  hipLaunchKernelGGL((k_fft_mid2<DT, F>), dim3(D, np, nch), dim3(256), lds, s, ys, L.bias, res, out, xs, np, D, nch, \
+                     L.cout_store, (int)spec)
   if (f32) {
-    if (D == 24) CF_MID(24, true); else if (D == 16) CF_MID(16, true); else if (D == 12) CF_MID(12, true); else CF_MID(0, true);
+    if (D == 24) CF_MID2(24, true); else if (D == 16) CF_MID2(16, true); else if (D == 12) CF_MID2(12, true); else CF_MID(0, true);
   } else {
-    if (D == 24) CF_MID(24, false); else if (D == 16) CF_MID(16, false); else if (D == 12) CF_MID(12, false); else CF_MID(0, false);
+    if (D == 24) CF_MID2(24, false); else if (D == 16) CF_MID2(16, false); else if (D == 12) CF_MID2(12, false); else CF_MID(0, false);
   }
+#undef CF_MID2
 #undef CF_MID
   return hipGetLastError();
 }
