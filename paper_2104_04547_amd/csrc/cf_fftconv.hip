@@ -21,6 +21,9 @@
 //   k_fft_zconv  one (column, block of poses): the z-correlation on MFMAs
 //   k_fft_inv2d  one (pose, z, 8-channel chunk) plane: inverse FFT, bias, residual,
 //                ReLU, bf16 store in the activations' channels-last layout
+// and, between two such layers, k_fft_mid: one layer's inverse and the next one's
+// forward transform of the same plane.  Overlap-save tiles of 32^3 activations
+// (64^3 grids) have their own forward / inverse (k_fft_fwd2d_t, k_fft_inv2d_t).
 //
 // Spectrum layout (bf16): [col][pose][z][chunk][re | im][8 channels] -- 64 bytes
 // per 8 channels, so a (column, pose block) of the z-correlation is one
@@ -41,11 +44,14 @@ constexpr int kPanelRows = 288;                                // LDS rows of on
 
 // ---------------------------------------------------------------- plane transforms
 
-// Thread roles in the plane kernels (256 threads): the column transforms along
-// ky / y run on threads 0 .. 127 (waves 0 and 1), one (kxp, channel) each with
-// kxp = tid >> 3; the row transforms along x run on threads 128 .. 128 + 4 D - 1
-// (waves 2 and 3), two channels of one y each.  The phases alternate, so two
-// workgroups on one CU keep all four SIMDs busy.
+// Thread roles in the plane kernels (256 threads).  k_fft_fwd2d, k_fft_inv2d and
+// k_fft_mid share each 32-point FFT between two adjacent lanes (see the lane-pair
+// section below): the column transforms along ky / y run on all 256 threads, a
+// lane pair per (kxp, channel), and the row transforms along x on threads
+// 0 .. 8 D - 1, a pair per (y, two channels).  The tiled kernels keep one transform
+// per lane: columns on threads 0 .. 127 (waves 0 and 1), one (kxp, channel) each
+// with kxp = tid >> 3, rows on threads 128 .. 128 + 4 W - 1 (waves 2 and 3); their
+// phases alternate, so two workgroups on one CU keep all four SIMDs busy.
 //
 // Columns: kxp 1 .. 15 is the complex column kx = kxp; kxp 0 carries the DC and
 // Nyquist columns (kx 0 and 16) together.  Along y both are real sequences (the
@@ -135,41 +141,9 @@ __device__ inline void dc_nyquist_split(const float2 *Zp, void *O, int tid) {
   spec_put<F32>(O, ky * kNX + kNX - 1, c, 0.5f * (a.y + b.y), -0.5f * (a.x - b.x));
 }
 
-// inverse columns, step 1 (before the barrier that frees the spectrum): columns 1 .. 15
-template <bool F32>
-__device__ inline void col_inv_load(const void *Y, int kxp, int c, float (&re)[32], float (&im)[32]) {
-#pragma unroll
-  for (int ky = 0; ky < 32; ++ky) spec_get<F32>(Y, ky * kNX + kxp, c, re[ky], im[ky]);
-}
 
-// inverse columns, step 2 (after it): the packed column from Zp
-__device__ inline void col_inv_load_dc(const float2 *Zp, int c, float (&re)[32], float (&im)[32]) {
-#pragma unroll
-  for (int ky = 0; ky < 32; ++ky) {
-    const float2 v = Zp[ky * 8 + c];
-    re[ky] = v.x;
-    im[ky] = v.y;
-  }
-}
 
-// inverse columns, after fft32<true>: rows y < D of T = [kx][y (pitch D + 1)][8] complex
-__device__ inline void col_inv_store(float2 *T, int kxp, int c, int D, const float (&re)[32], const float (&im)[32]) {
-  const int DP = D + 1;
-#pragma unroll
-  for (int y = 0; y < kDMax; ++y)
-    if (y < D) T[(kxp * DP + y) * 8 + c] = make_float2(re[y], im[y]);
-}
 
-// forward columns: column kxp of T into registers, zero-padded to 32
-__device__ inline void col_fwd_load(const float2 *T, int kxp, int c, int D, float (&re)[32], float (&im)[32]) {
-  const int DP = D + 1;
-#pragma unroll
-  for (int y = 0; y < 32; ++y) {
-    const float2 v = y < D ? T[(kxp * DP + y) * 8 + c] : make_float2(0.0f, 0.0f);
-    re[y] = v.x;
-    im[y] = v.y;
-  }
-}
 
 // forward columns, after fft32<false>: the spectrum column into O = [col][re | im][8]
 // (bf16 or fp32), or the packed column into Zp
@@ -199,112 +173,9 @@ __device__ inline void row_fwd_store(float2 *T, int y, int c0, int D, const floa
   }
 }
 
-// rows, inverse: the Hermitian halves of two channels into one complex sequence
-// A + i B; DC and Nyquist (real) come from the packed column
-__device__ inline void row_inv_load(const float2 *T, int y, int c0, int D, float (&re)[32], float (&im)[32]) {
-  const int DP = D + 1;
-  const float4 dc = *reinterpret_cast<const float4 *>(T + y * 8 + c0);  // A0, A16, B0, B16
-  re[0] = dc.x;
-  im[0] = dc.z;
-  re[16] = dc.y;
-  im[16] = dc.w;
-#pragma unroll
-  for (int k = 1; k < kNX - 1; ++k) {
-    const float4 ab = *reinterpret_cast<const float4 *>(T + (k * DP + y) * 8 + c0);
-    re[k] = ab.x - ab.w;
-    im[k] = ab.y + ab.z;
-    re[32 - k] = ab.x + ab.w;
-    im[32 - k] = ab.z - ab.y;
-  }
-}
 
 // ---------------------------------------------------------------- forward
 
-// LDS layouts are padded so that the lanes of one access hit distinct banks:
-// the input plane is held transposed, [x][y (pitch D + 1)][8 channels], so the
-// lanes (y, channel pair) of one x read one contiguous run; the half spectrum of
-// the rows is [kx][y (pitch D + 1)][8] complex.
-// One workgroup per (z, pose, chunk), grid (D, np, nch) in XCD order: the chunks
-// of one plane run under one L2, where their pieces of each spectrum row (and of
-// each input voxel) meet.  in: [P][D][D][D][cin_pad] of bf16 (F32 = false) or
-// float; spectrum rows of the same type.
-template <int DT, bool F32>
-__global__ __launch_bounds__(256) void k_fft_fwd2d(const void *__restrict__ in_v, void *__restrict__ xs_v, int np,
-                                                   int D_rt, int cin_pad, int nch) {
-  using act_t = typename std::conditional<F32, float, bf16_t>::type;
-  constexpr int kEsz = sizeof(act_t), kQ = 2 * kEsz / 2;  // 16-byte pieces per spectrum column of 8 channels
-  const act_t *in = reinterpret_cast<const act_t *>(in_v);
-  act_t *xs = reinterpret_cast<act_t *>(xs_v);
-  const int D = DT ? DT : D_rt;
-  int chunk, z, p;
-  xcd_order(z, p, chunk);
-  // one dynamic LDS block (fft_lds_bytes): the plane, then (after its rows are in
-  // registers) the row spectra, then the output staging
-  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
-  act_t *plane = reinterpret_cast<act_t *>(dyn_lds);    // [x][y][8]
-  float2 *T = reinterpret_cast<float2 *>(dyn_lds);      // [kx][y][8]
-  const int tid = threadIdx.x, DP = D + 1;
-  const act_t *src = in + (((int64_t)p * D + z) * D * D) * cin_pad + chunk * 8;
-  for (int v = tid; v < D * D; v += 256) {
-    const int y = v / D, x = v - y * D;
-#pragma unroll
-    for (int q = 0; q < kEsz / 2; ++q)
-      reinterpret_cast<uint4 *>(plane + (x * DP + y) * 8)[q] =
-          reinterpret_cast<const uint4 *>(src + (int64_t)v * cin_pad)[q];
-  }
-  __syncthreads();
-  // rows along x, two channels per complex transform
-  {
-    const int r = tid - kColThreads;
-    const bool roww = r >= 0 && r < D * 4;
-    const int y = r >> 2, c0 = (r & 3) * 2;
-    float re[32], im[32];
-#pragma unroll
-    for (int x = 0; x < 32; ++x) {
-      if (roww && x < D) {
-        if constexpr (F32) {
-          const float2 two = *reinterpret_cast<const float2 *>(plane + (x * DP + y) * 8 + c0);
-          re[x] = two.x;
-          im[x] = two.y;
-        } else {
-          const uint32_t two = *reinterpret_cast<const uint32_t *>(plane + (x * DP + y) * 8 + c0);
-          re[x] = __uint_as_float(two << 16);
-          im[x] = __uint_as_float(two & 0xffff0000u);
-        }
-      } else {
-        re[x] = 0.0f;
-        im[x] = 0.0f;
-      }
-    }
-    __syncthreads();  // the plane is in registers; its LDS becomes the row spectra
-    if (roww) {
-      fft32<false>(re, im);
-      row_fwd_store(T, y, c0, D, re, im);
-    }
-  }
-  __syncthreads();
-  // columns along y
-  float re[32], im[32];
-  const bool colw = tid < kColThreads;
-  const int kxp = tid >> 3, c = tid & 7;
-  if (colw) {
-    col_fwd_load(T, kxp, c, D, re, im);
-    fft32<false>(re, im);
-  }
-  __syncthreads();
-  act_t *O = reinterpret_cast<act_t *>(T);  // [col][re | im][8]
-  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D, F32));
-  if (colw) col_fwd_store<F32>(O, Zp, kxp, c, re, im);
-  __syncthreads();
-  dc_nyquist_split<F32>(Zp, O, tid);
-  __syncthreads();
-  const int64_t rowb = (int64_t)nch * 16;  // elements per (col, pose, z) row
-  for (int e = tid; e < kCols * kQ; e += 256) {
-    const int col = e / kQ, h = e % kQ;
-    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * (16 / kEsz)) =
-        *reinterpret_cast<const uint4 *>(O + col * 16 + h * (16 / kEsz));
-  }
-}
 
 // Overlap-save forward transform for grids of edge 2 TS beyond the 32-point
 // transforms' reach (D + k - 1 > 32): each plane is 2 x 2 tiles of TS x TS outputs.
@@ -402,13 +273,14 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d_t(const void *__restrict__ in
 
 // ---------------------------------------------------------------- inverse
 
-// One workgroup per (z, pose, output chunk), grid (D, np, nco) in XCD order.
-// out, res: [P][D][D][D][cout_store] of bf16 (F32 = false) or float.
-// NTL > 1 (overlap-save tiles): the plane of edge NTL * D is NTL x NTL tiles of
+// Inverse transform with one FFT per lane, used for overlap-save tiles (the untiled
+// inverse is k_fft_inv2d).  One workgroup per (z, pose, output chunk), grid (D, np,
+// nco) in XCD order.  out, res: [P][D][D][D][cout_store] of bf16 (F32 = false) or
+// float.  NTL > 1 (overlap-save tiles): the plane of edge NTL * D is NTL x NTL tiles of
 // D x D outputs, each with its own spectrum; grid (NTL * D, np * NTL^2, nco), np
 // counting (pose, tile) planes.
 template <int DT, bool F32, int NTL = 1>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_inv2d(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_inv2d_t(
     const void *__restrict__ ys_v, const float *__restrict__ bias, const void *__restrict__ res_v,
     void *__restrict__ out_v, int np, int D_rt, int nco, int cout_store) {
   using act_t = typename std::conditional<F32, float, bf16_t>::type;
@@ -520,148 +392,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
-// ---------------------------------------------------------------- fused inverse + forward
-
-// Between two frequency-domain layers: the inverse of layer i (bias, residual,
-// ReLU, bf16 rounding exactly as k_fft_inv2d stores it) feeds the forward
-// transform of layer i + 1 in registers, so the activation makes no round trip
-// through memory; it is stored only when a later layer reads it (out != null).
-// One workgroup per (z, pose, chunk); the chunking of layer i's output is the
-// chunking of layer i + 1's input.  LDS: the spectrum / column transforms
-// (fft_lds_bytes) and, with a residual or a stored output, the activation plane
-// [y][x][8] bf16.
-template <int DT, bool F32>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_mid(
-    const void *__restrict__ ys_v, const float *__restrict__ bias, const void *__restrict__ res_v,
-    void *__restrict__ out_v, void *__restrict__ xs_v, int np, int D_rt, int nch, int cout_store, int lds_spec) {
-  using act_t = typename std::conditional<F32, float, bf16_t>::type;
-  constexpr int kEsz = sizeof(act_t), kQ = kEsz;  // 16-byte pieces per spectrum column of 8 channels
-  const act_t *ys = reinterpret_cast<const act_t *>(ys_v);
-  const act_t *res = reinterpret_cast<const act_t *>(res_v);
-  act_t *out = reinterpret_cast<act_t *>(out_v);
-  act_t *xs = reinterpret_cast<act_t *>(xs_v);
-  const int D = DT ? DT : D_rt;
-  int chunk, z, p;
-  xcd_order(z, p, chunk);
-  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
-  act_t *Y = reinterpret_cast<act_t *>(dyn_lds);                  // [col][re | im][8]
-  float2 *T = reinterpret_cast<float2 *>(dyn_lds);                 // [kx][y][8]
-  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D, F32));  // [32][8] packed DC / Nyquist column
-  act_t *R = reinterpret_cast<act_t *>(dyn_lds + lds_spec);        // [y][x][8]: residual in, activation out
-  const int tid = threadIdx.x;
-  const int64_t rowb = (int64_t)nch * 16;
-  const int64_t base = (((int64_t)p * D + z) * D * D) * cout_store + chunk * 8;
-  for (int e = tid; e < kCols * kQ; e += 256) {
-    const int col = e / kQ, h = e % kQ;
-    *reinterpret_cast<uint4 *>(Y + col * 16 + h * (16 / kEsz)) = *reinterpret_cast<const uint4 *>(
-        ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * (16 / kEsz));
-  }
-  if (res)
-    for (int v = tid; v < D * D; v += 256)
-#pragma unroll
-      for (int q = 0; q < kEsz / 2; ++q)
-        reinterpret_cast<uint4 *>(R + v * 8)[q] = reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store)[q];
-  __syncthreads();
-  const bool colw = tid < kColThreads;
-  const int kxp = tid >> 3, c = tid & 7;
-  // inverse columns along ky (as k_fft_inv2d)
-  {
-    float re[32], im[32];
-    dc_nyquist_pack<F32>(Y, Zp, tid);
-    if (colw && kxp) col_inv_load<F32>(Y, kxp, c, re, im);
-    __syncthreads();
-    if (colw) {
-      if (!kxp) col_inv_load_dc(Zp, c, re, im);
-      fft32<true>(re, im);
-      col_inv_store(T, kxp, c, D, re, im);
-    }
-  }
-  __syncthreads();
-  // rows along x: inverse of two channels, epilogue (bf16 rounding in the bf16
-  // form), then their forward transform (the next layer's input rows)
-  {
-    const int r = tid - kColThreads;
-    const bool roww = r >= 0 && r < D * 4;
-    const int y = r >> 2, c0 = (r & 3) * 2;
-    float re[32], im[32];
-    // no barrier between reading and rewriting T here: a row thread reads and then
-    // overwrites only its own (y, channel pair) slots, and the column threads wait
-    if (roww) {
-      row_inv_load(T, y, c0, D, re, im);
-      fft32<true>(re, im);
-      constexpr float kScale = 1.0f / (kN * kN);
-      const float b0 = bias[chunk * 8 + c0], b1 = bias[chunk * 8 + c0 + 1];
-#pragma unroll
-      for (int x = 0; x < 32; ++x) {
-        if (x < D) {
-          float v0 = re[x] * kScale + b0, v1 = im[x] * kScale + b1;
-          if constexpr (F32) {
-            if (res) {
-              const float2 two = *reinterpret_cast<const float2 *>(R + (y * D + x) * 8 + c0);
-              v0 += two.x;
-              v1 += two.y;
-            }
-            v0 = v0 > 0.0f ? v0 : 0.0f;
-            v1 = v1 > 0.0f ? v1 : 0.0f;
-            if (out) *reinterpret_cast<float2 *>(R + (y * D + x) * 8 + c0) = make_float2(v0, v1);
-            re[x] = v0;
-            im[x] = v1;
-          } else {
-            if (res) {
-              const uint32_t two = *reinterpret_cast<const uint32_t *>(R + (y * D + x) * 8 + c0);
-              v0 += __uint_as_float(two << 16);
-              v1 += __uint_as_float(two & 0xffff0000u);
-            }
-            const bf16_t h0 = (bf16_t)(v0 > 0.0f ? v0 : 0.0f), h1 = (bf16_t)(v1 > 0.0f ? v1 : 0.0f);
-            if (out)
-              *reinterpret_cast<uint32_t *>(R + (y * D + x) * 8 + c0) =
-                  (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
-            re[x] = (float)h0;
-            im[x] = (float)h1;
-          }
-        } else {
-          re[x] = 0.0f;
-          im[x] = 0.0f;
-        }
-      }
-      fft32<false>(re, im);
-      row_fwd_store(T, y, c0, D, re, im);
-    }
-  }
-  __syncthreads();
-  if (out)
-    for (int v = tid; v < D * D; v += 256)
-#pragma unroll
-      for (int q = 0; q < kEsz / 2; ++q)
-        reinterpret_cast<uint4 *>(out + base + (int64_t)v * cout_store)[q] = reinterpret_cast<const uint4 *>(R + v * 8)[q];
-  // forward columns along y (as k_fft_fwd2d)
-  float re[32], im[32];
-  if (colw) {
-    col_fwd_load(T, kxp, c, D, re, im);
-    fft32<false>(re, im);
-  }
-  __syncthreads();
-  act_t *O = reinterpret_cast<act_t *>(T);
-  if (colw) col_fwd_store<F32>(O, Zp, kxp, c, re, im);
-  __syncthreads();
-  dc_nyquist_split<F32>(Zp, O, tid);
-  __syncthreads();
-  for (int e = tid; e < kCols * kQ; e += 256) {
-    const int col = e / kQ, h = e % kQ;
-    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + h * (16 / kEsz)) =
-        *reinterpret_cast<const uint4 *>(O + col * 16 + h * (16 / kEsz));
-  }
-}
-
 // ---------------------------------------------------------------- lane-pair transforms
 //
-// The fused transform with every 32-point FFT shared by two adjacent lanes
-// (fft32_pair_dit / fft32_pair_dif): the column phases then run on all 256
-// threads (128 (column, channel) pairs) and the row phase on 8 D threads, each
-// lane holding 16 points instead of 32, so that all four waves work in every phase
-// and the register file holds half the transform state.  Lane h = tid & 1 of a
-// pair, partner tid ^ 1 (a quad permutation, so the exchange is a DPP move); the
-// channel pair (c, c ^ 1) of a bf16 spectrum access is two lanes apart.
+// Every 32-point FFT of the untiled plane kernels is shared by two adjacent lanes
+// (fft32_pair_dit / fft32_pair_dif): the column phases run on all 256 threads
+// (128 (column, channel) pairs) and the row phase on 8 D threads, each lane
+// holding 16 points instead of 32, so that all four waves work in every phase and
+// the register file holds half the transform state (at 24^3: 118 VGPRs for the
+// fused transform against 153 with one transform per lane, four waves per SIMD
+// instead of three).  Lane h = tid & 1 of a pair, partner tid ^ 1 (a quad
+// permutation, so the exchange is a DPP move); the channel pair (c, c ^ 1) of a
+// bf16 spectrum access is then two lanes apart.
 
 __device__ inline float pair_swap(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // lanes 1,0,3,2
@@ -752,9 +493,16 @@ __device__ inline void col_fwd_store2(void *O, float2 *Zp, int kxp, int c, int h
   }
 }
 
-// k_fft_mid with lane-pair transforms (same grid, LDS and results up to rounding)
+// Between two frequency-domain layers: the inverse of layer i (bias, residual,
+// ReLU, bf16 rounding exactly as k_fft_inv2d stores it) feeds the forward
+// transform of layer i + 1 in registers, so the activation makes no round trip
+// through memory; it is stored only when a later layer reads it (out != null).
+// One workgroup per (z, pose, chunk), grid (D, np, nch) in XCD order; the chunking
+// of layer i's output is the chunking of layer i + 1's input.  LDS: the spectrum /
+// row spectra (fft_lds_bytes) and, with a residual or a stored output, the
+// activation plane [y][x][8].
 template <int DT, bool F32>
-__global__ __launch_bounds__(256) void k_fft_mid2(const void *__restrict__ ys_v, const float *__restrict__ bias,
+__global__ __launch_bounds__(256) void k_fft_mid(const void *__restrict__ ys_v, const float *__restrict__ bias,
                                                   const void *__restrict__ res_v, void *__restrict__ out_v,
                                                   void *__restrict__ xs_v, int np, int D_rt, int nch, int cout_store,
                                                   int lds_spec) {
@@ -873,6 +621,178 @@ __global__ __launch_bounds__(256) void k_fft_mid2(const void *__restrict__ ys_v,
   }
 }
 
+// Forward transform of one (z, pose, chunk) plane, grid (D, np, nch) in XCD order:
+// the chunks of one plane run under one L2, where their pieces of each spectrum row
+// (and of each input voxel) meet.  in: [P][D][D][D][cin_pad] of bf16 (F32 = false)
+// or float; spectrum rows of the same type.  LDS layouts are padded so that the
+// lanes of one access hit distinct banks: the input plane is held transposed,
+// [x][y (pitch D + 1)][8 channels], and the half spectrum of the rows is
+// [kx][y (pitch D + 1)][8] complex, aliasing the plane once it is in registers.
+template <int DT, bool F32>
+__global__ __launch_bounds__(256) void k_fft_fwd2d(const void *__restrict__ in_v, void *__restrict__ xs_v, int np,
+                                                    int D_rt, int cin_pad, int nch) {
+  using act_t = typename std::conditional<F32, float, bf16_t>::type;
+  constexpr int kEsz = sizeof(act_t), kQ = kEsz;
+  const act_t *in = reinterpret_cast<const act_t *>(in_v);
+  act_t *xs = reinterpret_cast<act_t *>(xs_v);
+  const int D = DT ? DT : D_rt;
+  int chunk, z, p;
+  xcd_order(z, p, chunk);
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  act_t *plane = reinterpret_cast<act_t *>(dyn_lds);  // [x][y][8]
+  float2 *T = reinterpret_cast<float2 *>(dyn_lds);    // [kx][y][8]
+  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D, F32));
+  const int tid = threadIdx.x, h = tid & 1, q = tid >> 1, DP = D + 1;
+  const act_t *src = in + (((int64_t)p * D + z) * D * D) * cin_pad + chunk * 8;
+  for (int v = tid; v < D * D; v += 256) {
+    const int y = v / D, x = v - y * D;
+#pragma unroll
+    for (int qq = 0; qq < kEsz / 2; ++qq)
+      reinterpret_cast<uint4 *>(plane + (x * DP + y) * 8)[qq] =
+          reinterpret_cast<const uint4 *>(src + (int64_t)v * cin_pad)[qq];
+  }
+  __syncthreads();
+  // rows along x, two channels per complex transform: lane h takes x = 16 h + n
+  {
+    const bool roww = tid < 8 * D;
+    const int y = q >> 2, c0 = (q & 3) * 2;
+    float re[16], im[16];
+#pragma unroll
+    for (int n = 0; n < 16; ++n) {
+      const int x = 16 * h + n;
+      if (roww && x < D) {
+        if constexpr (F32) {
+          const float2 two = *reinterpret_cast<const float2 *>(plane + (x * DP + y) * 8 + c0);
+          re[n] = two.x;
+          im[n] = two.y;
+        } else {
+          const uint32_t two = *reinterpret_cast<const uint32_t *>(plane + (x * DP + y) * 8 + c0);
+          re[n] = __uint_as_float(two << 16);
+          im[n] = __uint_as_float(two & 0xffff0000u);
+        }
+      } else {
+        re[n] = 0.0f;
+        im[n] = 0.0f;
+      }
+    }
+    __syncthreads();  // the plane is in registers; its LDS becomes the row spectra
+    if (roww) {
+      fft32_pair_dif<false>(re, im, h, pair_swap);
+      row_fwd_store2(T, y, c0, h, D, re, im);
+    }
+  }
+  __syncthreads();
+  // columns along y
+  const int kxp = q >> 3, c = q & 7;
+  float re[16], im[16];
+  col_fwd_load2(T, kxp, c, h, D, re, im);
+  fft32_pair_dif<false>(re, im, h, pair_swap);
+  __syncthreads();
+  act_t *O = reinterpret_cast<act_t *>(T);  // [col][re | im][8]
+  col_fwd_store2<F32>(O, Zp, kxp, c, h, re, im);
+  __syncthreads();
+  dc_nyquist_split<F32>(Zp, O, tid);
+  __syncthreads();
+  const int64_t rowb = (int64_t)nch * 16;
+  for (int e = tid; e < kCols * kQ; e += 256) {
+    const int col = e / kQ, hh = e % kQ;
+    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + hh * (16 / kEsz)) =
+        *reinterpret_cast<const uint4 *>(O + col * 16 + hh * (16 / kEsz));
+  }
+}
+
+// Inverse transform of one (z, pose, output chunk) plane, grid (D, np, nco) in XCD
+// order: bias, residual, ReLU and the store in the activations' channels-last
+// layout [P][D][D][D][cout_store].  The spectrum's DC and Nyquist columns travel
+// packed, as in the fused transform.
+template <int DT, bool F32>
+__global__ __launch_bounds__(256) void k_fft_inv2d(const void *__restrict__ ys_v, const float *__restrict__ bias,
+                                                    const void *__restrict__ res_v, void *__restrict__ out_v, int np,
+                                                    int D_rt, int nco, int cout_store) {
+  using act_t = typename std::conditional<F32, float, bf16_t>::type;
+  constexpr int kEsz = sizeof(act_t), kQ = kEsz;
+  const act_t *ys = reinterpret_cast<const act_t *>(ys_v);
+  const act_t *res = reinterpret_cast<const act_t *>(res_v);
+  act_t *out = reinterpret_cast<act_t *>(out_v);
+  const int D = DT ? DT : D_rt;
+  int chunk, z, p;
+  xcd_order(z, p, chunk);
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  act_t *Y = reinterpret_cast<act_t *>(dyn_lds);
+  float2 *T = reinterpret_cast<float2 *>(dyn_lds);
+  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(D, F32));
+  const int tid = threadIdx.x, h = tid & 1, q = tid >> 1, DP = D + 1;
+  const int64_t rowb = (int64_t)nco * 16;
+  for (int e = tid; e < kCols * kQ; e += 256) {
+    const int col = e / kQ, hh = e % kQ;
+    *reinterpret_cast<uint4 *>(Y + col * 16 + hh * (16 / kEsz)) = *reinterpret_cast<const uint4 *>(
+        ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + hh * (16 / kEsz));
+  }
+  __syncthreads();
+  const int kxp = q >> 3, c = q & 7;
+  {
+    float re[16], im[16];
+    dc_nyquist_pack<F32>(Y, Zp, tid);
+    if (kxp) col_inv_load2<F32>(Y, kxp, c, h, re, im);
+    __syncthreads();
+    if (!kxp) col_inv_load_dc2(Zp, c, h, re, im);
+    fft32_pair_dit<true>(re, im, h, pair_swap);
+    col_inv_store2(T, kxp, c, h, D, re, im);
+  }
+  __syncthreads();
+  const bool roww = tid < 8 * D;
+  const int y = q >> 2, c0 = (q & 3) * 2;
+  float re[16], im[16];
+  if (roww) {
+    row_inv_load2(T, y, c0, h, D, re, im);
+    fft32_pair_dit<true>(re, im, h, pair_swap);
+  }
+  __syncthreads();  // the row spectra are read; T becomes the output plane
+  float *O = reinterpret_cast<float *>(T);  // [x][y (pitch D + 1)][8] conv result + bias
+  if (roww) {
+    constexpr float kScale = 1.0f / (kN * kN);
+    const float b0 = bias[chunk * 8 + c0], b1 = bias[chunk * 8 + c0 + 1];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int x = 16 * h + j;
+      if (x < D) *reinterpret_cast<float2 *>(O + (x * DP + y) * 8 + c0) = make_float2(re[j] * kScale + b0, im[j] * kScale + b1);
+    }
+  }
+  __syncthreads();
+  const int64_t base = (((int64_t)p * D + z) * D * D) * cout_store + chunk * 8;
+  for (int v0 = tid; v0 < D * D; v0 += 256) {
+    const int yy = v0 / D, xx = v0 - yy * D;
+    float f[8];
+    const float4 f0 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8);
+    const float4 f1 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8 + 4);
+    f[0] = f0.x; f[1] = f0.y; f[2] = f0.z; f[3] = f0.w; f[4] = f1.x; f[5] = f1.y; f[6] = f1.z; f[7] = f1.w;
+    if constexpr (F32) {
+      if (res) {
+        const float4 r0 = *reinterpret_cast<const float4 *>(res + base + (int64_t)v0 * cout_store);
+        const float4 r1 = *reinterpret_cast<const float4 *>(res + base + (int64_t)v0 * cout_store + 4);
+        f[0] += r0.x; f[1] += r0.y; f[2] += r0.z; f[3] += r0.w; f[4] += r1.x; f[5] += r1.y; f[6] += r1.z; f[7] += r1.w;
+      }
+#pragma unroll
+      for (int qq = 0; qq < 8; ++qq) f[qq] = f[qq] > 0.0f ? f[qq] : 0.0f;
+      float4 *dst = reinterpret_cast<float4 *>(out + base + (int64_t)v0 * cout_store);
+      dst[0] = make_float4(f[0], f[1], f[2], f[3]);
+      dst[1] = make_float4(f[4], f[5], f[6], f[7]);
+    } else {
+      if (res) {
+        const uint4 r = *reinterpret_cast<const uint4 *>(res + base + (int64_t)v0 * cout_store);
+        const bf16_t *rb = reinterpret_cast<const bf16_t *>(&r);
+#pragma unroll
+        for (int qq = 0; qq < 8; ++qq) f[qq] += (float)rb[qq];
+      }
+      uint4 o;
+      bf16_t *ob = reinterpret_cast<bf16_t *>(&o);
+#pragma unroll
+      for (int qq = 0; qq < 8; ++qq) ob[qq] = (bf16_t)(f[qq] > 0.0f ? f[qq] : 0.0f);
+      *reinterpret_cast<uint4 *>(out + base + (int64_t)v0 * cout_store) = o;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- z-correlation
 
 // One (column, block of ppb poses): rows r = (pose pl, z), pl = r / D; the panel in
@@ -976,36 +896,39 @@ __global__ __launch_bounds__(NT == 128 ? 256 : 128) __attribute__((amdgpu_waves_
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) a[0][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb]);
   int nchunk = 0, ndz = 1;  // step s + 1
-  for (int s0 = 0; s0 < steps; s0 += kPF) {
-#pragma unroll
-    for (int ph = 0; ph < kPF; ++ph) {
-      const int s = s0 + ph;
-      if (s < steps) {
-        if (ndz == KS) {
-          ndz = 0;
-          ++nchunk;
-        }
-        const int noff = s + 1 < steps ? ndz * pitch + nchunk * 32 : 0;
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-          a[(ph + 1) & 1][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + noff);
-        ++ndz;
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[ph & 1][mb]),
-                                                                   __builtin_bit_cast(bf16x8, bq[ph][nb]),
-                                                                   acc[mb][nb], 0, 0, 0);
-        const int sn = s + kPF;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                     wrs, wbase + nb * 1024, min(sn, steps - 1) * step_bytes, 0));
-      }
+  auto step = [&](const int s, const int ph) {
+    if (ndz == KS) {
+      ndz = 0;
+      ++nchunk;
     }
+    const int noff = s + 1 < steps ? ndz * pitch + nchunk * 32 : 0;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) a[(ph + 1) & 1][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + noff);
+    ++ndz;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[ph & 1][mb]),
+                                                               __builtin_bit_cast(bf16x8, bq[ph][nb]), acc[mb][nb], 0,
+                                                               0, 0);
+    const int sn = s + kPF;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                 wrs, wbase + nb * 1024, min(sn, steps - 1) * step_bytes, 0));
+  };
+  // whole groups of kPF steps with no test inside (a test per step makes the
+  // compiler's wait analysis drain every outstanding weight load), then the rest
+  const int full = steps / kPF * kPF;
+  for (int s0 = 0; s0 < full; s0 += kPF) {
+#pragma unroll
+    for (int ph = 0; ph < kPF; ++ph) step(s0 + ph, ph);
   }
+#pragma unroll
+  for (int ph = 0; ph < kPF; ++ph)
+    if (full + ph < steps) step(full + ph, ph);
 
   // epilogue through LDS: rows of NT bf16 in the spectrum layout, then contiguous stores
   __syncthreads();
@@ -1128,36 +1051,41 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) a[0][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb]);
     int nchunk = 0, ndz = 1;  // step s + 1 within the half
-    for (int s0 = 0; s0 < hsteps; s0 += kPF) {
-#pragma unroll
-      for (int ph = 0; ph < kPF; ++ph) {
-        const int s = s0 + ph;
-        if (s < hsteps) {
-          if (ndz == KS) {
-            ndz = 0;
-            ++nchunk;
-          }
-          const int noff = s + 1 < hsteps ? ndz * PH + nchunk * 32 : 0;
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-            a[(ph + 1) & 1][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + noff);
-          ++ndz;
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[ph & 1][mb]),
-                                                                     __builtin_bit_cast(bf16x8, bq[ph][nb]),
-                                                                     acc[mb][nb], 0, 0, 0);
-          const int sn = s + kPF;
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                       wrs, wbase + nb * 1024, (sbase + min(sn, hsteps - 1)) * step_bytes, 0));
-        }
+    // one K step: the row fragments of step s + 1 are read while the MFMAs of step s
+    // issue, and the weight fragments of step s + kPF replace those just used
+    auto step = [&](const int s, const int ph) {
+      if (ndz == KS) {
+        ndz = 0;
+        ++nchunk;
       }
+      const int noff = s + 1 < hsteps ? ndz * PH + nchunk * 32 : 0;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) a[(ph + 1) & 1][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + noff);
+      ++ndz;
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[ph & 1][mb]),
+                                                                 __builtin_bit_cast(bf16x8, bq[ph][nb]), acc[mb][nb],
+                                                                 0, 0, 0);
+      const int sn = s + kPF;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                   wrs, wbase + nb * 1024, (sbase + min(sn, hsteps - 1)) * step_bytes, 0));
+    };
+    // whole groups of kPF steps with no test inside (a test per step makes the
+    // compiler's wait analysis drain every outstanding weight load), then the rest
+    const int full = hsteps / kPF * kPF;
+    for (int s0 = 0; s0 < full; s0 += kPF) {
+#pragma unroll
+      for (int ph = 0; ph < kPF; ++ph) step(s0 + ph, ph);
     }
+#pragma unroll
+    for (int ph = 0; ph < kPF; ++ph)
+      if (full + ph < hsteps) step(full + ph, ph);
   }
 
   // epilogue through LDS: rows of NT bf16 in the spectrum layout, then contiguous stores
@@ -1475,19 +1403,15 @@ hipError_t launch_fft_mid(const ConvLayer &L, const ConvLayer &Ln, const void *r
   char *xs = reinterpret_cast<char *>(work);
   char *ys = xs + fft_spec_in_elems(D, np) * esz_of(L);
   const size_t spec = fft_lds_bytes(D, f32), lds = spec + ((res || out) ? (size_t)D * D * 8 * esz_of(L) : 0);
-#define CF_MID(DT, F)                                                                                   \
+#define CF_MID2(DT, F)                                                                                  \
   hipLaunchKernelGGL((k_fft_mid<DT, F>), dim3(D, np, nch), dim3(256), lds, s, ys, L.bias, res, out, xs, np, D, nch, \
                      L.cout_store, (int)spec)
-#define CF_MID2(DT, F)                                                                                  \
-  hipLaunchKernelGGL((k_fft_mid2<DT, F>), dim3(D, np, nch), dim3(256), lds, s, ys, L.bias, res, out, xs, np, D, nch, \
-                     L.cout_store, (int)spec)
   if (f32) {
-    if (D == 24) CF_MID2(24, true); else if (D == 16) CF_MID2(16, true); else if (D == 12) CF_MID2(12, true); else CF_MID(0, true);
+    if (D == 24) CF_MID2(24, true); else if (D == 16) CF_MID2(16, true); else if (D == 12) CF_MID2(12, true); else CF_MID2(0, true);
   } else {
-    if (D == 24) CF_MID2(24, false); else if (D == 16) CF_MID2(16, false); else if (D == 12) CF_MID2(12, false); else CF_MID(0, false);
+    if (D == 24) CF_MID2(24, false); else if (D == 16) CF_MID2(16, false); else if (D == 12) CF_MID2(12, false); else CF_MID2(0, false);
   }
 #undef CF_MID2
-#undef CF_MID
   return hipGetLastError();
 }
 
@@ -1568,10 +1492,10 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
   }
   if ((stage < 0 || stage == 2) && tiled) {
     if (f32)
-      hipLaunchKernelGGL((k_fft_inv2d<kTileTS, true, 2>), dim3(D, np, nco), dim3(256), fft_lds_bytes(kTileTS, true), s,
+      hipLaunchKernelGGL((k_fft_inv2d_t<kTileTS, true, 2>), dim3(D, np, nco), dim3(256), fft_lds_bytes(kTileTS, true), s,
                          ys, L.bias, res, out, np, kTileTS, nco, L.cout_store);
     else
-      hipLaunchKernelGGL((k_fft_inv2d<kTileTS, false, 2>), dim3(D, np, nco), dim3(256), fft_lds_bytes(kTileTS, false),
+      hipLaunchKernelGGL((k_fft_inv2d_t<kTileTS, false, 2>), dim3(D, np, nco), dim3(256), fft_lds_bytes(kTileTS, false),
                          s, ys, L.bias, res, out, np, kTileTS, nco, L.cout_store);
   } else if (stage < 0 || stage == 2) {
 #define CF_INV(DT, F)                                                                                      \
