@@ -477,39 +477,42 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv8Cf
       for (int mb = 0; mb < C::MB; ++mb) ar[0][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + t0);
     }
     int dz = 0, dy = 0, dx = 2;  // first tap of pair 1
-    for (int p0 = 0; p0 < C::PAIRS; p0 += kPF) {
+    auto pair = [&](const int p, const int ph) {
+      // the last pair re-reads offset 0 of its rows (inside the halo) instead
+      const int tn = (p + 1 < C::PAIRS) ? pair_toff(p + 1, dz, dy, dx) : 0;
 #pragma unroll
-      for (int ph = 0; ph < kPF; ++ph) {
-        const int p = p0 + ph;
-        if (p < C::PAIRS) {
-          // the last pair re-reads offset 0 of its rows (inside the halo) instead
-          const int tn = (p + 1 < C::PAIRS) ? pair_toff(p + 1, dz, dy, dx) : 0;
-#pragma unroll
-          for (int mb = 0; mb < C::MB; ++mb)
-            ar[(ph + 1) & 1][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + tn);
-          __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this pair's MFMAs
-          dx += 2;
-          if (dx >= KS) {
-            dx -= KS;
-            if (++dy == KS) {
-              dy = 0;
-              ++dz;
-            }
-          }
-#pragma unroll
-          for (int mb = 0; mb < C::MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < C::NB; ++nb)
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ar[ph & 1][mb]),
-                                                                     __builtin_bit_cast(bf16x8, bq[ph][nb]),
-                                                                     acc[mb][nb], 0, 0, 0);
-#pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb)
-            bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], soff, 0));
-          soff += pair_bytes;
+      for (int mb = 0; mb < C::MB; ++mb) ar[(ph + 1) & 1][mb] = *reinterpret_cast<const uint4 *>(lds + rowoff[mb] + tn);
+      __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this pair's MFMAs
+      dx += 2;
+      if (dx >= KS) {
+        dx -= KS;
+        if (++dy == KS) {
+          dy = 0;
+          ++dz;
         }
       }
+#pragma unroll
+      for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ar[ph & 1][mb]),
+                                                                 __builtin_bit_cast(bf16x8, bq[ph][nb]), acc[mb][nb],
+                                                                 0, 0, 0);
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb)
+        bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], soff, 0));
+      soff += pair_bytes;
+    };
+    // whole groups of kPF pairs with no test inside (so that the compiler's wait
+    // analysis keeps every weight load of the ring in flight), then the rest
+    constexpr int kFull = C::PAIRS / kPF * kPF;
+    for (int p0 = 0; p0 < kFull; p0 += kPF) {
+#pragma unroll
+      for (int ph = 0; ph < kPF; ++ph) pair(p0 + ph, ph);
     }
+#pragma unroll
+    for (int ph = 0; ph < kPF; ++ph)
+      if (kFull + ph < C::PAIRS) pair(kFull + ph, ph);
   }
 
   // ---- epilogue through LDS, MBG row blocks per wave at a time ----
@@ -695,34 +698,38 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv4Cf
         ar[0][mb] = make_uint4(lo.x, lo.y, hi.x, hi.y);
       }
     }
-    for (int q0 = 0; q0 < C::QUADS; q0 += kPF) {
+    auto quad = [&](const int q, const int ph) {
+      const int qn = q + 1 < C::QUADS ? q + 1 : q;
+      const int t0 = tab[4 * qn + 2 * khalf], t1 = tab[4 * qn + 2 * khalf + 1];
 #pragma unroll
-      for (int ph = 0; ph < kPF; ++ph) {
-        const int q = q0 + ph;
-        if (q < C::QUADS) {
-          const int qn = q + 1 < C::QUADS ? q + 1 : q;
-          const int t0 = tab[4 * qn + 2 * khalf], t1 = tab[4 * qn + 2 * khalf + 1];
-#pragma unroll
-          for (int mb = 0; mb < C::MB; ++mb) {
-            const uint2 lo = *reinterpret_cast<const uint2 *>(halo + rowoff[mb] + t0);
-            const uint2 hi = *reinterpret_cast<const uint2 *>(halo + rowoff[mb] + t1);
-            ar[(ph + 1) & 1][mb] = make_uint4(lo.x, lo.y, hi.x, hi.y);
-          }
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int mb = 0; mb < C::MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < C::NB; ++nb)
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ar[ph & 1][mb]),
-                                                                     __builtin_bit_cast(bf16x8, bq[ph][nb]),
-                                                                     acc[mb][nb], 0, 0, 0);
-#pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb)
-            bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], soff, 0));
-          soff += quad_bytes;
-        }
+      for (int mb = 0; mb < C::MB; ++mb) {
+        const uint2 lo = *reinterpret_cast<const uint2 *>(halo + rowoff[mb] + t0);
+        const uint2 hi = *reinterpret_cast<const uint2 *>(halo + rowoff[mb] + t1);
+        ar[(ph + 1) & 1][mb] = make_uint4(lo.x, lo.y, hi.x, hi.y);
       }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ar[ph & 1][mb]),
+                                                                 __builtin_bit_cast(bf16x8, bq[ph][nb]), acc[mb][nb],
+                                                                 0, 0, 0);
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb)
+        bq[ph][nb] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wrs, vb[nb], soff, 0));
+      soff += quad_bytes;
+    };
+    // whole groups of kPF quads with no test inside (so that the compiler's wait
+    // analysis keeps every weight load of the ring in flight), then the rest
+    constexpr int kFull = C::QUADS / kPF * kPF;
+    for (int q0 = 0; q0 < kFull; q0 += kPF) {
+#pragma unroll
+      for (int ph = 0; ph < kPF; ++ph) quad(q0 + ph, ph);
     }
+#pragma unroll
+    for (int ph = 0; ph < kPF; ++ph)
+      if (kFull + ph < C::QUADS) quad(kFull + ph, ph);
   }
 
   // ---- epilogue through LDS (as k_conv8) ----
