@@ -14,8 +14,8 @@
 //     per atom, one candidate voxel per lane, as an exact integer reduction.
 //   * k_splat: the tile's accumulators sit in LDS as 2^20 fixed-point int32, so
 //     the atomics are exact and the result does not depend on the order in which
-//     waves add contributions.  The waves take the tile's list 64 atoms at a time
-//     (one atom per lane) and sweep them one after another: an atom's candidate
+//     waves add contributions.  The list is dealt to the four waves in turn (one
+//     atom per lane) and each wave sweeps its atoms one after another: an atom's candidate
 //     voxels form at most a 4 x 4 x 4 box, one per lane, and the adds are
 //     wavefront-wide LDS atomics.  The finished tile is streamed to HBM once.
 // Results are bitwise independent of launch shape, list order and atom
@@ -219,14 +219,15 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
                                                const int32_t *__restrict__ bin_atoms,
                                                int64_t *__restrict__ status) {
   // bin_atoms and Zs are indexed by atom - base, base = the launch's first atom
-  extern __shared__ int acc[];  // [kTA][kTB][G][19]
+  extern __shared__ __attribute__((aligned(16))) int acc[];  // [kTA][kTB][G][19]
   __shared__ int budget;        // range budget used by the atoms reaching this tile
   const int pl = blockIdx.y;    // pose within this launch
   const int p = p0 + pl;
   const int ntb = G / kTB, ntiles = (G / kTA) * ntb;
   const int i0 = (blockIdx.x / ntb) * kTA, j0 = (blockIdx.x % ntb) * kTB;
-  const int nacc = kTA * kTB * G * CF_NCH;
-  for (int e = threadIdx.x; e < nacc; e += blockDim.x) acc[e] = 0;
+  const int nacc = kTA * kTB * G * CF_NCH;  // a multiple of 4 (kTA * kTB is)
+  static_assert((kTA * kTB) % 4 == 0, "accumulators cleared 16 bytes at a time");
+  for (int e = threadIdx.x; e < nacc / 4; e += blockDim.x) reinterpret_cast<int4 *>(acc)[e] = make_int4(0, 0, 0, 0);
   if (threadIdx.x == 0) budget = 0;
   int a0, a1;
   if (!pose_range(atom_off, p, n_atoms, a0, a1) && blockIdx.x == 0 && threadIdx.x == 0)
@@ -236,8 +237,10 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
   const int l0 = bin_off[(int64_t)pl * (ntiles + 1) + blockIdx.x], l1 = bin_off[(int64_t)pl * (ntiles + 1) + blockIdx.x + 1];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q0 = l0 + wave * 64; q0 < l1; q0 += 256) {
-    const int q = q0 + lane;
+  // the tile's list is dealt to the waves in turn (entry q0 + 4 k to lane k of wave
+  // q0 - l0), so that a list of a few dozen atoms keeps all four waves sweeping
+  for (int q0 = l0 + wave; q0 < l1; q0 += 256) {
+    const int q = q0 + 4 * lane;
     bool ov = false;
     AtomBox bx{};
     double Za = 1.0;
