@@ -23,7 +23,8 @@
 //                ReLU, bf16 store in the activations' channels-last layout
 // and, between two such layers, k_fft_mid: one layer's inverse and the next one's
 // forward transform of the same plane.  Overlap-save tiles of 32^3 activations
-// (64^3 grids) have their own forward / inverse (k_fft_fwd2d_t, k_fft_inv2d_t).
+// (64^3 grids) have their own forward (k_fft_fwd2d_t, which reads the tile's window);
+// k_fft_inv2d takes them as tiles of its plane.
 //
 // Spectrum layout (bf16): [col][pose][z][chunk][re | im][8 channels] -- 64 bytes
 // per 8 channels, so a (column, pose block) of the z-correlation is one
@@ -44,14 +45,11 @@ constexpr int kPanelRows = 288;                                // LDS rows of on
 
 // ---------------------------------------------------------------- plane transforms
 
-// Thread roles in the plane kernels (256 threads).  k_fft_fwd2d, k_fft_inv2d and
-// k_fft_mid share each 32-point FFT between two adjacent lanes (see the lane-pair
-// section below): the column transforms along ky / y run on all 256 threads, a
-// lane pair per (kxp, channel), and the row transforms along x on threads
-// 0 .. 8 D - 1, a pair per (y, two channels).  The tiled kernels keep one transform
-// per lane: columns on threads 0 .. 127 (waves 0 and 1), one (kxp, channel) each
-// with kxp = tid >> 3, rows on threads 128 .. 128 + 4 W - 1 (waves 2 and 3); their
-// phases alternate, so two workgroups on one CU keep all four SIMDs busy.
+// Thread roles in the plane kernels (256 threads): each 32-point FFT is shared by
+// two adjacent lanes (see the lane-pair section below); the column transforms along
+// ky / y run on all 256 threads, a lane pair per (kxp, channel), and the row
+// transforms along x on threads 0 .. 8 D - 1 (8 W for a tile's window), a pair per
+// (y, two channels).
 //
 // Columns: kxp 1 .. 15 is the complex column kx = kxp; kxp 0 carries the DC and
 // Nyquist columns (kx 0 and 16) together.  Along y both are real sequences (the
@@ -67,8 +65,6 @@ constexpr int kPanelRows = 288;                                // LDS rows of on
 // The plane kernels take the grid edge as a template argument DT (0: D_rt at run
 // time): with D a constant, the bounds tests inside the unrolled transforms fold
 // away instead of turning into register-copy blocks.
-constexpr int kColThreads = 128;
-
 // LDS of the plane kernels: the plane region (the larger of the row spectra
 // [17][D + 1][8] complex and the spectrum of a plane, bf16 or fp32), then Zp
 // [32][8] complex
@@ -145,256 +141,12 @@ __device__ inline void dc_nyquist_split(const float2 *Zp, void *O, int tid) {
 
 
 
-// forward columns, after fft32<false>: the spectrum column into O = [col][re | im][8]
-// (bf16 or fp32), or the packed column into Zp
-template <bool F32>
-__device__ inline void col_fwd_store(void *O, float2 *Zp, int kxp, int c, const float (&re)[32],
-                                     const float (&im)[32]) {
-  if (kxp) {
-#pragma unroll
-    for (int ky = 0; ky < 32; ++ky) spec_put<F32>(O, ky * kNX + kxp, c, re[ky], im[ky]);
-  } else {
-#pragma unroll
-    for (int ky = 0; ky < 32; ++ky) Zp[ky * 8 + c] = make_float2(re[ky], im[ky]);
-  }
-}
-
-// rows, forward: the row spectra of two real channels from one complex transform
-// z = a + i b: A[k] = (Z[k] + conj Z[-k]) / 2, B[k] = (Z[k] - conj Z[-k]) / 2i for
-// k = 1 .. 15; at k = 0 the packed column (A0 + i A16, B0 + i B16), all four real
-__device__ inline void row_fwd_store(float2 *T, int y, int c0, int D, const float (&re)[32], const float (&im)[32]) {
-  const int DP = D + 1;
-  *reinterpret_cast<float4 *>(T + y * 8 + c0) = make_float4(re[0], re[16], im[0], im[16]);
-#pragma unroll
-  for (int k = 1; k < kNX - 1; ++k) {
-    const int m = 32 - k;
-    *reinterpret_cast<float4 *>(T + (k * DP + y) * 8 + c0) = make_float4(
-        0.5f * (re[k] + re[m]), 0.5f * (im[k] - im[m]), 0.5f * (im[k] + im[m]), -0.5f * (re[k] - re[m]));
-  }
-}
 
 
-// ---------------------------------------------------------------- forward
-
-
-// Overlap-save forward transform for grids of edge 2 TS beyond the 32-point
-// transforms' reach (D + k - 1 > 32): each plane is 2 x 2 tiles of TS x TS outputs.
-// A tile's input window spans TS + 2P positions per axis, from its origin - P:
-// window position w holds array position (w - P) mod 32 (the left halo wraps to
-// 32 - P .. 31), so the circular correlation of the 32-point DFTs gives the tile's
-// outputs at array positions 0 .. TS - 1 exactly (TS + 2P <= 32).  One workgroup
-// per (z, pose and tile, chunk), grid (2 TS, 4 np, nch); spectrum rows are indexed
-// by (pose, tile) planes, so the z-correlation runs on them unchanged.
-template <int KS, bool F32, int TS>
-__global__ __launch_bounds__(256) void k_fft_fwd2d_t(const void *__restrict__ in_v, void *__restrict__ xs_v, int np,
-                                                     int cin_pad, int nch) {
-  using act_t = typename std::conditional<F32, float, bf16_t>::type;
-  constexpr int kEsz = sizeof(act_t), kQ = kEsz;
-  constexpr int P = (KS - 1) / 2, W = TS + 2 * P, WP = W + 1, Dz = 2 * TS;
-  static_assert(W <= 32 && TS + P < 32 - P + 1, "window exceeds the 32-point transform");
-  const act_t *in = reinterpret_cast<const act_t *>(in_v);
-  act_t *xs = reinterpret_cast<act_t *>(xs_v);
-  int chunk, z, pv;
-  xcd_order(z, pv, chunk);
-  const int p = pv >> 2, y0 = ((pv >> 1) & 1) * TS - P, x0 = (pv & 1) * TS - P;
-  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
-  act_t *plane = reinterpret_cast<act_t *>(dyn_lds);    // [wx][wy (pitch WP)][8]
-  float2 *T = reinterpret_cast<float2 *>(dyn_lds);      // [kx][wy (pitch WP)][8]
-  const int tid = threadIdx.x;
-  const act_t *src = in + (((int64_t)p * Dz + z) * Dz * Dz) * cin_pad + chunk * 8;
-  for (int v = tid; v < W * W; v += 256) {
-    const int wy = v / W, wx = v - wy * W;
-    const int y = y0 + wy, x = x0 + wx;
-    const bool inside = y >= 0 && y < Dz && x >= 0 && x < Dz;
-#pragma unroll
-    for (int q = 0; q < kEsz / 2; ++q)
-      reinterpret_cast<uint4 *>(plane + (wx * WP + wy) * 8)[q] =
-          inside ? reinterpret_cast<const uint4 *>(src + ((int64_t)y * Dz + x) * cin_pad)[q] : make_uint4(0, 0, 0, 0);
-  }
-  __syncthreads();
-  // rows along x (window rows wy), array position a <- window column w(a)
-  {
-    const int r = tid - kColThreads;
-    const bool roww = r >= 0 && r < W * 4;
-    const int wy = r >> 2, c0 = (r & 3) * 2;
-    float re[32], im[32];
-#pragma unroll
-    for (int a = 0; a < 32; ++a) {
-      const int w = a < TS + P ? a + P : (a >= 32 - P ? a - 32 + P : -1);
-      re[a] = 0.0f;
-      im[a] = 0.0f;
-      if (roww && w >= 0) {
-        if constexpr (F32) {
-          const float2 two = *reinterpret_cast<const float2 *>(plane + (w * WP + wy) * 8 + c0);
-          re[a] = two.x;
-          im[a] = two.y;
-        } else {
-          const uint32_t two = *reinterpret_cast<const uint32_t *>(plane + (w * WP + wy) * 8 + c0);
-          re[a] = __uint_as_float(two << 16);
-          im[a] = __uint_as_float(two & 0xffff0000u);
-        }
-      }
-    }
-    __syncthreads();  // the plane is in registers; its LDS becomes the row spectra
-    if (roww) {
-      fft32<false>(re, im);
-      row_fwd_store(T, wy, c0, W, re, im);
-    }
-  }
-  __syncthreads();
-  // columns along y: array position a <- window row w(a)
-  float re[32], im[32];
-  const bool colw = tid < kColThreads;
-  const int kxp = tid >> 3, c = tid & 7;
-  if (colw) {
-#pragma unroll
-    for (int a = 0; a < 32; ++a) {
-      const int w = a < TS + P ? a + P : (a >= 32 - P ? a - 32 + P : -1);
-      const float2 v = w >= 0 ? T[(kxp * WP + w) * 8 + c] : make_float2(0.0f, 0.0f);
-      re[a] = v.x;
-      im[a] = v.y;
-    }
-    fft32<false>(re, im);
-  }
-  __syncthreads();
-  act_t *O = reinterpret_cast<act_t *>(T);  // [col][re | im][8]
-  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(W, F32));
-  if (colw) col_fwd_store<F32>(O, Zp, kxp, c, re, im);
-  __syncthreads();
-  dc_nyquist_split<F32>(Zp, O, tid);
-  __syncthreads();
-  const int64_t rowb = (int64_t)nch * 16;
-  for (int e = tid; e < kCols * kQ; e += 256) {
-    const int col = e / kQ, h = e % kQ;
-    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + pv) * Dz + z) * rowb + chunk * 16 + h * (16 / kEsz)) =
-        *reinterpret_cast<const uint4 *>(O + col * 16 + h * (16 / kEsz));
-  }
-}
-
-// ---------------------------------------------------------------- inverse
-
-// Inverse transform with one FFT per lane, used for overlap-save tiles (the untiled
-// inverse is k_fft_inv2d).  One workgroup per (z, pose, output chunk), grid (D, np,
-// nco) in XCD order.  out, res: [P][D][D][D][cout_store] of bf16 (F32 = false) or
-// float.  NTL > 1 (overlap-save tiles): the plane of edge NTL * D is NTL x NTL tiles of
-// D x D outputs, each with its own spectrum; grid (NTL * D, np * NTL^2, nco), np
-// counting (pose, tile) planes.
-template <int DT, bool F32, int NTL = 1>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_inv2d_t(
-    const void *__restrict__ ys_v, const float *__restrict__ bias, const void *__restrict__ res_v,
-    void *__restrict__ out_v, int np, int D_rt, int nco, int cout_store) {
-  using act_t = typename std::conditional<F32, float, bf16_t>::type;
-  constexpr int kEsz = sizeof(act_t), kQ = kEsz;  // 16-byte pieces per spectrum column of 8 channels
-  const act_t *ys = reinterpret_cast<const act_t *>(ys_v);
-  const act_t *res = reinterpret_cast<const act_t *>(res_v);
-  act_t *out = reinterpret_cast<act_t *>(out_v);
-  const int D = DT ? DT : D_rt;  // in-plane extent of one tile
-  const int Dz = D * NTL;        // grid edge
-  int chunk, z, pv;
-  xcd_order(z, pv, chunk);
-  const int p = pv / (NTL * NTL), y0 = (pv % (NTL * NTL)) / NTL * D, x0 = (pv % NTL) * D;
-  // one dynamic LDS block (fft_lds_bytes): the spectrum, then (after its columns
-  // are in registers) the column transforms, then the output plane
-  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
-  act_t *Y = reinterpret_cast<act_t *>(dyn_lds);    // [col][re | im][8]
-  float2 *T = reinterpret_cast<float2 *>(dyn_lds);  // [kx][y][8]; later [x][y][8] floats
-  const int tid = threadIdx.x, DP = D + 1;
-  const int64_t rowb = (int64_t)nco * 16;
-  for (int e = tid; e < kCols * kQ; e += 256) {
-    const int col = e / kQ, h = e % kQ;
-    *reinterpret_cast<uint4 *>(Y + col * 16 + h * (16 / kEsz)) = *reinterpret_cast<const uint4 *>(
-        ys + (((int64_t)col * np + pv) * Dz + z) * rowb + chunk * 16 + h * (16 / kEsz));
-  }
-  __syncthreads();
-  // columns along ky
-  {
-    const bool colw = tid < kNX * 8;
-    const int kx = tid >> 3, c = tid & 7;
-    float re[32], im[32];
-    if (colw) {
-#pragma unroll
-      for (int ky = 0; ky < 32; ++ky) spec_get<F32>(Y, ky * kNX + kx, c, re[ky], im[ky]);
-    }
-    __syncthreads();  // the spectrum is in registers; its LDS becomes the transforms
-    if (colw) {
-      fft32<true>(re, im);
-#pragma unroll
-      for (int y = 0; y < kDMax; ++y)
-        if (y < D) T[(kx * DP + y) * 8 + c] = make_float2(re[y], im[y]);
-    }
-  }
-  __syncthreads();
-  // rows along x: the Hermitian halves of two channels in one complex transform
-  float re[32], im[32];
-  const bool roww = tid < D * 4;
-  const int y = tid >> 2, c0 = (tid & 3) * 2;
-  if (roww) {
-#pragma unroll
-    for (int k = 0; k < kNX; ++k) {
-      const float4 ab = *reinterpret_cast<const float4 *>(T + (k * DP + y) * 8 + c0);
-      float2 a = make_float2(ab.x, ab.y), b = make_float2(ab.z, ab.w);
-      if (k == 0 || k == kNX - 1) {  // DC and Nyquist of a real signal are real
-        a.y = 0.0f;
-        b.y = 0.0f;
-      }
-      re[k] = a.x - b.y;
-      im[k] = a.y + b.x;
-      if (k > 0 && k < kNX - 1) {
-        re[32 - k] = a.x + b.y;
-        im[32 - k] = b.x - a.y;
-      }
-    }
-    fft32<true>(re, im);
-  }
-  __syncthreads();
-  float *O = reinterpret_cast<float *>(T);  // [x][y (pitch D + 1)][8] conv result + bias
-  if (roww) {
-    constexpr float kScale = 1.0f / (kN * kN);
-    const float b0 = bias[chunk * 8 + c0], b1 = bias[chunk * 8 + c0 + 1];
-#pragma unroll
-    for (int x = 0; x < kDMax; ++x)
-      if (x < D)
-        *reinterpret_cast<float2 *>(O + (x * DP + y) * 8 + c0) = make_float2(re[x] * kScale + b0, im[x] * kScale + b1);
-  }
-  __syncthreads();
-  const int64_t base = (((int64_t)p * Dz + z) * Dz * Dz) * cout_store + chunk * 8;
-  for (int v0 = tid; v0 < D * D; v0 += 256) {
-    const int yy = v0 / D, xx = v0 - yy * D;
-    const int64_t v = (int64_t)(y0 + yy) * Dz + x0 + xx;
-    float f[8];
-    const float4 f0 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8);
-    const float4 f1 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8 + 4);
-    f[0] = f0.x; f[1] = f0.y; f[2] = f0.z; f[3] = f0.w; f[4] = f1.x; f[5] = f1.y; f[6] = f1.z; f[7] = f1.w;
-    if constexpr (F32) {
-      if (res) {
-        const float4 r0 = *reinterpret_cast<const float4 *>(res + base + (int64_t)v * cout_store);
-        const float4 r1 = *reinterpret_cast<const float4 *>(res + base + (int64_t)v * cout_store + 4);
-        f[0] += r0.x; f[1] += r0.y; f[2] += r0.z; f[3] += r0.w; f[4] += r1.x; f[5] += r1.y; f[6] += r1.z; f[7] += r1.w;
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) f[q] = f[q] > 0.0f ? f[q] : 0.0f;
-      float4 *dst = reinterpret_cast<float4 *>(out + base + (int64_t)v * cout_store);
-      dst[0] = make_float4(f[0], f[1], f[2], f[3]);
-      dst[1] = make_float4(f[4], f[5], f[6], f[7]);
-    } else {
-      if (res) {
-        const uint4 r = *reinterpret_cast<const uint4 *>(res + base + (int64_t)v * cout_store);
-        const bf16_t *rb = reinterpret_cast<const bf16_t *>(&r);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) f[q] += (float)rb[q];
-      }
-      uint4 o;
-      bf16_t *ob = reinterpret_cast<bf16_t *>(&o);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) ob[q] = (bf16_t)(f[q] > 0.0f ? f[q] : 0.0f);
-      *reinterpret_cast<uint4 *>(out + base + (int64_t)v * cout_store) = o;
-    }
-  }
-}
 
 // ---------------------------------------------------------------- lane-pair transforms
 //
-// Every 32-point FFT of the untiled plane kernels is shared by two adjacent lanes
+// Every 32-point FFT of the plane kernels is shared by two adjacent lanes
 // (fft32_pair_dit / fft32_pair_dif): the column phases run on all 256 threads
 // (128 (column, channel) pairs) and the row phase on 8 D threads, each lane
 // holding 16 points instead of 32, so that all four waves work in every phase and
@@ -492,6 +244,104 @@ __device__ inline void col_fwd_store2(void *O, float2 *Zp, int kxp, int c, int h
     for (int m = 0; m < 16; ++m) Zp[(2 * m + h) * 8 + c] = make_float2(re[m], im[m]);
   }
 }
+
+// ---------------------------------------------------------------- forward
+
+
+// Overlap-save forward transform for grids of edge 2 TS beyond the 32-point
+// transforms' reach (D + k - 1 > 32): each plane is 2 x 2 tiles of TS x TS outputs.
+// A tile's input window spans TS + 2P positions per axis, from its origin - P:
+// window position w holds array position (w - P) mod 32 (the left halo wraps to
+// 32 - P .. 31), so the circular correlation of the 32-point DFTs gives the tile's
+// outputs at array positions 0 .. TS - 1 exactly (TS + 2P <= 32).  One workgroup
+// per (z, pose and tile, chunk), grid (2 TS, 4 np, nch); spectrum rows are indexed
+// by (pose, tile) planes, so the z-correlation runs on them unchanged.
+template <int KS, bool F32, int TS>
+__global__ __launch_bounds__(256) void k_fft_fwd2d_t(const void *__restrict__ in_v, void *__restrict__ xs_v, int np,
+                                                     int cin_pad, int nch) {
+  using act_t = typename std::conditional<F32, float, bf16_t>::type;
+  constexpr int kEsz = sizeof(act_t), kQ = kEsz;
+  constexpr int P = (KS - 1) / 2, W = TS + 2 * P, WP = W + 1, Dz = 2 * TS;
+  static_assert(W <= 32 && TS + P < 32 - P + 1, "window exceeds the 32-point transform");
+  const act_t *in = reinterpret_cast<const act_t *>(in_v);
+  act_t *xs = reinterpret_cast<act_t *>(xs_v);
+  int chunk, z, pv;
+  xcd_order(z, pv, chunk);
+  const int p = pv >> 2, y0 = ((pv >> 1) & 1) * TS - P, x0 = (pv & 1) * TS - P;
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  act_t *plane = reinterpret_cast<act_t *>(dyn_lds);    // [wx][wy (pitch WP)][8]
+  float2 *T = reinterpret_cast<float2 *>(dyn_lds);      // [kx][wy (pitch WP)][8]
+  const int tid = threadIdx.x;
+  const act_t *src = in + (((int64_t)p * Dz + z) * Dz * Dz) * cin_pad + chunk * 8;
+  for (int v = tid; v < W * W; v += 256) {
+    const int wy = v / W, wx = v - wy * W;
+    const int y = y0 + wy, x = x0 + wx;
+    const bool inside = y >= 0 && y < Dz && x >= 0 && x < Dz;
+#pragma unroll
+    for (int q = 0; q < kEsz / 2; ++q)
+      reinterpret_cast<uint4 *>(plane + (wx * WP + wy) * 8)[q] =
+          inside ? reinterpret_cast<const uint4 *>(src + ((int64_t)y * Dz + x) * cin_pad)[q] : make_uint4(0, 0, 0, 0);
+  }
+  __syncthreads();
+  // rows along x (window rows wy) on 8 W threads, a lane pair per (wy, two channels),
+  // lane h taking array positions a = 16 h + n <- window column w(a)
+  const int h = tid & 1, q = tid >> 1;
+  {
+    const bool roww = tid < 8 * W;
+    const int wy = q >> 2, c0 = (q & 3) * 2;
+    float re[16], im[16];
+#pragma unroll
+    for (int n = 0; n < 16; ++n) {
+      const int a = 16 * h + n;
+      const int w = a < TS + P ? a + P : (a >= 32 - P ? a - 32 + P : -1);
+      re[n] = 0.0f;
+      im[n] = 0.0f;
+      if (roww && w >= 0) {
+        if constexpr (F32) {
+          const float2 two = *reinterpret_cast<const float2 *>(plane + (w * WP + wy) * 8 + c0);
+          re[n] = two.x;
+          im[n] = two.y;
+        } else {
+          const uint32_t two = *reinterpret_cast<const uint32_t *>(plane + (w * WP + wy) * 8 + c0);
+          re[n] = __uint_as_float(two << 16);
+          im[n] = __uint_as_float(two & 0xffff0000u);
+        }
+      }
+    }
+    __syncthreads();  // the plane is in registers; its LDS becomes the row spectra
+    if (roww) {
+      fft32_pair_dif<false>(re, im, h, pair_swap);
+      row_fwd_store2(T, wy, c0, h, W, re, im);
+    }
+  }
+  __syncthreads();
+  // columns along y on all 256 threads: array position a <- window row w(a)
+  const int kxp = q >> 3, c = q & 7;
+  float re[16], im[16];
+#pragma unroll
+  for (int n = 0; n < 16; ++n) {
+    const int a = 16 * h + n;
+    const int w = a < TS + P ? a + P : (a >= 32 - P ? a - 32 + P : -1);
+    const float2 v = w >= 0 ? T[(kxp * WP + w) * 8 + c] : make_float2(0.0f, 0.0f);
+    re[n] = v.x;
+    im[n] = v.y;
+  }
+  fft32_pair_dif<false>(re, im, h, pair_swap);
+  __syncthreads();
+  act_t *O = reinterpret_cast<act_t *>(T);  // [col][re | im][8]
+  float2 *Zp = reinterpret_cast<float2 *>(dyn_lds + plane_lds_bytes(W, F32));
+  col_fwd_store2<F32>(O, Zp, kxp, c, h, re, im);
+  __syncthreads();
+  dc_nyquist_split<F32>(Zp, O, tid);
+  __syncthreads();
+  const int64_t rowb = (int64_t)nch * 16;
+  for (int e = tid; e < kCols * kQ; e += 256) {
+    const int col = e / kQ, hh = e % kQ;
+    *reinterpret_cast<uint4 *>(xs + (((int64_t)col * np + pv) * Dz + z) * rowb + chunk * 16 + hh * (16 / kEsz)) =
+        *reinterpret_cast<const uint4 *>(O + col * 16 + hh * (16 / kEsz));
+  }
+}
+
 
 // Between two frequency-domain layers: the inverse of layer i (bias, residual,
 // ReLU, bf16 rounding exactly as k_fft_inv2d stores it) feeds the forward
@@ -704,8 +554,10 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d(const void *__restrict__ in_v
 // Inverse transform of one (z, pose, output chunk) plane, grid (D, np, nco) in XCD
 // order: bias, residual, ReLU and the store in the activations' channels-last
 // layout [P][D][D][D][cout_store].  The spectrum's DC and Nyquist columns travel
-// packed, as in the fused transform.
-template <int DT, bool F32>
+// packed, as in the fused transform.  NTL > 1 (overlap-save tiles): the plane of
+// edge NTL * D is NTL x NTL tiles of D x D outputs, each with its own spectrum;
+// grid (NTL * D, np * NTL^2, nco), np counting (pose, tile) planes.
+template <int DT, bool F32, int NTL = 1>
 __global__ __launch_bounds__(256) void k_fft_inv2d(const void *__restrict__ ys_v, const float *__restrict__ bias,
                                                     const void *__restrict__ res_v, void *__restrict__ out_v, int np,
                                                     int D_rt, int nco, int cout_store) {
@@ -714,9 +566,11 @@ __global__ __launch_bounds__(256) void k_fft_inv2d(const void *__restrict__ ys_v
   const act_t *ys = reinterpret_cast<const act_t *>(ys_v);
   const act_t *res = reinterpret_cast<const act_t *>(res_v);
   act_t *out = reinterpret_cast<act_t *>(out_v);
-  const int D = DT ? DT : D_rt;
-  int chunk, z, p;
-  xcd_order(z, p, chunk);
+  const int D = DT ? DT : D_rt;  // in-plane extent of one tile
+  const int Dz = D * NTL;        // grid edge
+  int chunk, z, pv;
+  xcd_order(z, pv, chunk);
+  const int p = pv / (NTL * NTL), y0 = (pv % (NTL * NTL)) / NTL * D, x0 = (pv % NTL) * D;
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
   act_t *Y = reinterpret_cast<act_t *>(dyn_lds);
   float2 *T = reinterpret_cast<float2 *>(dyn_lds);
@@ -726,7 +580,7 @@ __global__ __launch_bounds__(256) void k_fft_inv2d(const void *__restrict__ ys_v
   for (int e = tid; e < kCols * kQ; e += 256) {
     const int col = e / kQ, hh = e % kQ;
     *reinterpret_cast<uint4 *>(Y + col * 16 + hh * (16 / kEsz)) = *reinterpret_cast<const uint4 *>(
-        ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + hh * (16 / kEsz));
+        ys + (((int64_t)col * np + pv) * Dz + z) * rowb + chunk * 16 + hh * (16 / kEsz));
   }
   __syncthreads();
   const int kxp = q >> 3, c = q & 7;
@@ -759,27 +613,28 @@ __global__ __launch_bounds__(256) void k_fft_inv2d(const void *__restrict__ ys_v
     }
   }
   __syncthreads();
-  const int64_t base = (((int64_t)p * D + z) * D * D) * cout_store + chunk * 8;
+  const int64_t base = (((int64_t)p * Dz + z) * Dz * Dz) * cout_store + chunk * 8;
   for (int v0 = tid; v0 < D * D; v0 += 256) {
     const int yy = v0 / D, xx = v0 - yy * D;
+    const int64_t v = (int64_t)(y0 + yy) * Dz + x0 + xx;
     float f[8];
     const float4 f0 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8);
     const float4 f1 = *reinterpret_cast<const float4 *>(O + (xx * DP + yy) * 8 + 4);
     f[0] = f0.x; f[1] = f0.y; f[2] = f0.z; f[3] = f0.w; f[4] = f1.x; f[5] = f1.y; f[6] = f1.z; f[7] = f1.w;
     if constexpr (F32) {
       if (res) {
-        const float4 r0 = *reinterpret_cast<const float4 *>(res + base + (int64_t)v0 * cout_store);
-        const float4 r1 = *reinterpret_cast<const float4 *>(res + base + (int64_t)v0 * cout_store + 4);
+        const float4 r0 = *reinterpret_cast<const float4 *>(res + base + v * cout_store);
+        const float4 r1 = *reinterpret_cast<const float4 *>(res + base + v * cout_store + 4);
         f[0] += r0.x; f[1] += r0.y; f[2] += r0.z; f[3] += r0.w; f[4] += r1.x; f[5] += r1.y; f[6] += r1.z; f[7] += r1.w;
       }
 #pragma unroll
       for (int qq = 0; qq < 8; ++qq) f[qq] = f[qq] > 0.0f ? f[qq] : 0.0f;
-      float4 *dst = reinterpret_cast<float4 *>(out + base + (int64_t)v0 * cout_store);
+      float4 *dst = reinterpret_cast<float4 *>(out + base + v * cout_store);
       dst[0] = make_float4(f[0], f[1], f[2], f[3]);
       dst[1] = make_float4(f[4], f[5], f[6], f[7]);
     } else {
       if (res) {
-        const uint4 r = *reinterpret_cast<const uint4 *>(res + base + (int64_t)v0 * cout_store);
+        const uint4 r = *reinterpret_cast<const uint4 *>(res + base + v * cout_store);
         const bf16_t *rb = reinterpret_cast<const bf16_t *>(&r);
 #pragma unroll
         for (int qq = 0; qq < 8; ++qq) f[qq] += (float)rb[qq];
@@ -788,7 +643,7 @@ __global__ __launch_bounds__(256) void k_fft_inv2d(const void *__restrict__ ys_v
       bf16_t *ob = reinterpret_cast<bf16_t *>(&o);
 #pragma unroll
       for (int qq = 0; qq < 8; ++qq) ob[qq] = (bf16_t)(f[qq] > 0.0f ? f[qq] : 0.0f);
-      *reinterpret_cast<uint4 *>(out + base + (int64_t)v0 * cout_store) = o;
+      *reinterpret_cast<uint4 *>(out + base + v * cout_store) = o;
     }
   }
 }
@@ -1492,10 +1347,10 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
   }
   if ((stage < 0 || stage == 2) && tiled) {
     if (f32)
-      hipLaunchKernelGGL((k_fft_inv2d_t<kTileTS, true, 2>), dim3(D, np, nco), dim3(256), fft_lds_bytes(kTileTS, true), s,
+      hipLaunchKernelGGL((k_fft_inv2d<kTileTS, true, 2>), dim3(D, np, nco), dim3(256), fft_lds_bytes(kTileTS, true), s,
                          ys, L.bias, res, out, np, kTileTS, nco, L.cout_store);
     else
-      hipLaunchKernelGGL((k_fft_inv2d_t<kTileTS, false, 2>), dim3(D, np, nco), dim3(256), fft_lds_bytes(kTileTS, false),
+      hipLaunchKernelGGL((k_fft_inv2d<kTileTS, false, 2>), dim3(D, np, nco), dim3(256), fft_lds_bytes(kTileTS, false),
                          s, ys, L.bias, res, out, np, kTileTS, nco, L.cout_store);
   } else if (stage < 0 || stage == 2) {
 #define CF_INV(DT, F)                                                                                      \
