@@ -24,27 +24,37 @@ __global__ __launch_bounds__(256) void k_pool_dense(const T *__restrict__ act, i
                                                     int n_dense, const float *__restrict__ dw2,
                                                     const float *__restrict__ db2, int n_dense2,
                                                     float *__restrict__ latent) {
-  __shared__ float part[4][256];
+  // 16-byte loads: each thread owns KV consecutive channels (a channel group g) of
+  // the voxels v = vr, vr + NV, ... (NV = 256 / groups); the per-thread sums run
+  // over v in ascending order and the NV partial sums of a channel are added in
+  // order of vr, so the mean does not depend on scheduling
+  constexpr int KV = 16 / sizeof(T);
+  __shared__ float part[256 * KV];
   __shared__ float mean[256];
   __shared__ float hid[256];
   const int pose = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const T *a = act + (int64_t)pose * vox * cstride;
-  float s[4] = {0.f, 0.f, 0.f, 0.f};  // channels lane, lane+64, lane+128, lane+192
-  for (int v = wave; v < vox; v += 4) {
-    const T *row = a + (int64_t)v * cstride;
+  const int groups = cstride / KV, NV = 256 / groups;  // threads past NV * groups sit out
+  const int g = threadIdx.x % groups, vr = threadIdx.x / groups;
+  float s[KV];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ch = lane + 64 * q;
-      if (ch < c) s[q] += (float)row[ch];
-    }
+  for (int q = 0; q < KV; ++q) s[q] = 0.0f;
+  for (int v = vr < NV ? vr : vox; v < vox; v += NV) {
+    const uint4 raw = *reinterpret_cast<const uint4 *>(a + (int64_t)v * cstride + g * KV);
+    const T *x = reinterpret_cast<const T *>(&raw);
+#pragma unroll
+    for (int q = 0; q < KV; ++q) s[q] += (float)x[q];
   }
+  if (vr < NV)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) part[wave][lane + 64 * q] = s[q];
+    for (int q = 0; q < KV; ++q) part[vr * cstride + g * KV + q] = s[q];
   __syncthreads();
   const float inv = 1.0f / (float)vox;
-  for (int ch = threadIdx.x; ch < c; ch += 256)
-    mean[ch] = ((part[0][ch] + part[1][ch]) + (part[2][ch] + part[3][ch])) * inv;
+  for (int ch = threadIdx.x; ch < c; ch += 256) {
+    float m = 0.0f;
+    for (int r = 0; r < NV; ++r) m += part[r * cstride + ch];
+    mean[ch] = m * inv;
+  }
   __syncthreads();
   if (n_dense == 0) {
     for (int ch = threadIdx.x; ch < c; ch += 256) latent[(int64_t)pose * c + ch] = mean[ch];
@@ -110,6 +120,8 @@ hipError_t launch_pool_dense(const void *act, int bf16, int n_poses, int vox, in
                              const float *dense2_b, int n_dense2, float *latent, hipStream_t s) {
   if (n_poses <= 0) return hipSuccess;
   if (c > 256 || n_dense > 256 || n_dense2 > 256 || (n_dense2 && !n_dense)) return hipErrorInvalidValue;
+  // channel groups of 16 bytes must tile the row, at most one per thread
+  if (c > cstride || cstride % (bf16 ? 8 : 4) || cstride / (bf16 ? 8 : 4) > 256) return hipErrorInvalidValue;
   if (bf16)
     hipLaunchKernelGGL(k_pool_dense<bf16_t>, dim3(n_poses), dim3(256), 0, s, reinterpret_cast<const bf16_t *>(act),
                        vox, cstride, c, dense_w, dense_b, n_dense, dense2_w, dense2_b, n_dense2, latent);
