@@ -466,11 +466,11 @@ std::vector<T> pack_conv(const std::vector<float> &W, int cout, int cin, int k, 
 }
 
 // bf16 weights for the tap-pair kernel: [pair][chunk8][c_out (pad 32)][16], element
-// 8 h + c = W[n][8 chunk + c][tap 2 pair + h]; four zero pairs of padding (the
-// kernel prefetches weights up to four pairs ahead).
+// 8 h + c = W[n][8 chunk + c][tap 2 pair + h]; kConvPadSteps zero pairs of padding
+// (the kernel prefetches weights up to that many pairs ahead).
 std::vector<bf16_t> pack_conv8(const std::vector<float> &W, int cout, int cin, int k, int cout_pad32) {
   const int taps = k * k * k, pairs = (taps + 1) / 2, nch = (cin + 7) / 8;
-  std::vector<bf16_t> out((size_t)(pairs + 4) * nch * cout_pad32 * 16, (bf16_t)0.0f);
+  std::vector<bf16_t> out((size_t)(pairs + cf::kConvPadSteps) * nch * cout_pad32 * 16, (bf16_t)0.0f);
   for (int p = 0; p < pairs; ++p)
     for (int ch = 0; ch < nch; ++ch)
       for (int n = 0; n < cout; ++n)
@@ -483,11 +483,11 @@ std::vector<bf16_t> pack_conv8(const std::vector<float> &W, int cout, int cin, i
 }
 
 // tap-quad packing: [quad][4-channel chunk][c_out (pad 32)][16], element e of a
-// row = tap 4 quad + e / 4, channel 4 chunk + e % 4; four zero quads past the end
-// for the weight prefetch
+// row = tap 4 quad + e / 4, channel 4 chunk + e % 4; kConvPadSteps zero quads past
+// the end for the weight prefetch
 std::vector<bf16_t> pack_conv4(const std::vector<float> &W, int cout, int cin, int k, int cout_pad32) {
   const int taps = k * k * k, quads = (taps + 3) / 4, nch = (cin + 3) / 4;
-  std::vector<bf16_t> out((size_t)(quads + 4) * nch * cout_pad32 * 16, (bf16_t)0.0f);
+  std::vector<bf16_t> out((size_t)(quads + cf::kConvPadSteps) * nch * cout_pad32 * 16, (bf16_t)0.0f);
   for (int q = 0; q < quads; ++q)
     for (int ch = 0; ch < nch; ++ch)
       for (int n = 0; n < cout; ++n)

@@ -346,12 +346,14 @@ __global__ __launch_bounds__(256) void k_fft_fwd2d_t(const void *__restrict__ in
 // Between two frequency-domain layers: the inverse of layer i (bias, residual,
 // ReLU, bf16 rounding exactly as k_fft_inv2d stores it) feeds the forward
 // transform of layer i + 1 in registers, so the activation makes no round trip
-// through memory; it is stored only when a later layer reads it (out != null).
+// through memory; it is stored only when a later layer reads it (OUT).
 // One workgroup per (z, pose, chunk), grid (D, np, nch) in XCD order; the chunking
 // of layer i's output is the chunking of layer i + 1's input.  LDS: the spectrum /
 // row spectra (fft_lds_bytes) and, with a residual or a stored output, the
-// activation plane [y][x][8].
-template <int DT, bool F32>
+// activation plane [y][x][8].  The residual (RES) and the stored output (OUT) are
+// template arguments: as run-time tests they put a branch and a wait on each
+// value's residual read inside the epilogue of the row transforms.
+template <int DT, bool F32, bool RES, bool OUT>
 __global__ __launch_bounds__(256) void k_fft_mid(const void *__restrict__ ys_v, const float *__restrict__ bias,
                                                   const void *__restrict__ res_v, void *__restrict__ out_v,
                                                   void *__restrict__ xs_v, int np, int D_rt, int nch, int cout_store,
@@ -378,7 +380,7 @@ __global__ __launch_bounds__(256) void k_fft_mid(const void *__restrict__ ys_v, 
     *reinterpret_cast<uint4 *>(Y + col * 16 + hh * (16 / kEsz)) = *reinterpret_cast<const uint4 *>(
         ys + (((int64_t)col * np + p) * D + z) * rowb + chunk * 16 + hh * (16 / kEsz));
   }
-  if (res)
+  if constexpr (RES)
     for (int v = tid; v < D * D; v += 256)
 #pragma unroll
       for (int qq = 0; qq < kEsz / 2; ++qq)
@@ -413,24 +415,24 @@ __global__ __launch_bounds__(256) void k_fft_mid(const void *__restrict__ ys_v, 
         if (x < D) {
           float v0 = re[j] * kScale + b0, v1 = im[j] * kScale + b1;
           if constexpr (F32) {
-            if (res) {
+            if constexpr (RES) {
               const float2 two = *reinterpret_cast<const float2 *>(R + (y * D + x) * 8 + c0);
               v0 += two.x;
               v1 += two.y;
             }
             v0 = v0 > 0.0f ? v0 : 0.0f;
             v1 = v1 > 0.0f ? v1 : 0.0f;
-            if (out) *reinterpret_cast<float2 *>(R + (y * D + x) * 8 + c0) = make_float2(v0, v1);
+            if constexpr (OUT) *reinterpret_cast<float2 *>(R + (y * D + x) * 8 + c0) = make_float2(v0, v1);
             re[j] = v0;
             im[j] = v1;
           } else {
-            if (res) {
+            if constexpr (RES) {
               const uint32_t two = *reinterpret_cast<const uint32_t *>(R + (y * D + x) * 8 + c0);
               v0 += __uint_as_float(two << 16);
               v1 += __uint_as_float(two & 0xffff0000u);
             }
             const bf16_t h0 = (bf16_t)(v0 > 0.0f ? v0 : 0.0f), h1 = (bf16_t)(v1 > 0.0f ? v1 : 0.0f);
-            if (out)
+            if constexpr (OUT)
               *reinterpret_cast<uint32_t *>(R + (y * D + x) * 8 + c0) =
                   (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
             re[j] = (float)h0;
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(256) void k_fft_mid(const void *__restrict__ ys_v, 
     }
   }
   __syncthreads();
-  if (out)
+  if constexpr (OUT)
     for (int v = tid; v < D * D; v += 256)
 #pragma unroll
       for (int qq = 0; qq < kEsz / 2; ++qq)
@@ -1258,15 +1260,23 @@ hipError_t launch_fft_mid(const ConvLayer &L, const ConvLayer &Ln, const void *r
   char *xs = reinterpret_cast<char *>(work);
   char *ys = xs + fft_spec_in_elems(D, np) * esz_of(L);
   const size_t spec = fft_lds_bytes(D, f32), lds = spec + ((res || out) ? (size_t)D * D * 8 * esz_of(L) : 0);
-#define CF_MID2(DT, F)                                                                                  \
-  hipLaunchKernelGGL((k_fft_mid<DT, F>), dim3(D, np, nch), dim3(256), lds, s, ys, L.bias, res, out, xs, np, D, nch, \
-                     L.cout_store, (int)spec)
+#define CF_MID3(DT, F, R, O)                                                                                  \
+  hipLaunchKernelGGL((k_fft_mid<DT, F, R, O>), dim3(D, np, nch), dim3(256), lds, s, ys, L.bias, res, out, xs, np, D, \
+                     nch, L.cout_store, (int)spec)
+#define CF_MID2(DT, F)                                 \
+  do {                                                 \
+    if (res && out) CF_MID3(DT, F, true, true);        \
+    else if (res) CF_MID3(DT, F, true, false);         \
+    else if (out) CF_MID3(DT, F, false, true);         \
+    else CF_MID3(DT, F, false, false);                 \
+  } while (0)
   if (f32) {
     if (D == 24) CF_MID2(24, true); else if (D == 16) CF_MID2(16, true); else if (D == 12) CF_MID2(12, true); else CF_MID2(0, true);
   } else {
     if (D == 24) CF_MID2(24, false); else if (D == 16) CF_MID2(16, false); else if (D == 12) CF_MID2(12, false); else CF_MID2(0, false);
   }
 #undef CF_MID2
+#undef CF_MID3
   return hipGetLastError();
 }
 

@@ -69,6 +69,10 @@ __device__ inline void xcd_order(int &x, int &y, int &z) {
   y = l / (gz * gx);
 }
 
+// Zero K steps past the end of the packed tap-pair / tap-quad weights: the conv
+// kernels prefetch weight fragments up to this many steps ahead.
+constexpr int kConvPadSteps = 6;
+
 // ---- per-layer conv launch description (host side) ----
 struct ConvLayer {
   int cin, cout, k, stride, res_src;
