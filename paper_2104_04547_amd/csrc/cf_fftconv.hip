@@ -816,21 +816,27 @@ __global__ __launch_bounds__(NT == 128 ? 256 : 128) __attribute__((amdgpu_waves_
   }
 }
 
-// The same z-correlation for 128 real columns with 96-row blocks and the K walk in
-// two halves of at most four channel chunks: the panel holds one half at a time
-// (rows of 128 bytes + 16), so a workgroup needs 26 KB of LDS (the epilogue
-// staging) and six fit per CU; their panel loads hide behind each other's MFMAs.
-// Two waves, each 96 rows x 64 columns.  Tile rows r = (pl, z), z fastest.
-constexpr int kRowsZH = 96, kPanelRowsH = 144;
+// The same z-correlation for 128 real columns with RG row groups of 96 rows and
+// the K walk in two halves of at most four channel chunks: the panel holds one
+// half at a time (rows of 128 bytes + 16).  Each row group is two waves of 96 rows
+// x 64 columns; the row groups read the same weight fragments at the same step, so
+// the second read is served next to the CU and the L2 weight stream per row
+// shrinks by RG.  RG = 2 (192 rows, 8 poses at 24^3): 52 KB of LDS (the epilogue
+// staging), three workgroups per CU whose panel loads hide behind each other's
+// MFMAs; 3 % faster than RG = 1 (six two-wave workgroups), while RG = 3 (two per
+// CU) is 35 % slower: fewer workgroups leave the panel loads exposed.
+// Tile rows r = (pl, z), z fastest.
+constexpr int kRowsZH = 96, kPanelRowsH = 144, kZhRG = 2;
 
-template <int KS>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_zconv_h(
+template <int KS, int RG>
+__global__ __launch_bounds__(128 * RG) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_zconv_h(
     const bf16_t *__restrict__ xs, const bf16_t *__restrict__ gp, bf16_t *__restrict__ ys, int np, int D, int nch,
     int ppb, int gbytes) {
-  constexpr int P = (KS - 1) / 2, NT = 128, NB = 2, MB = 3, NBT = 4, NTH = 128;
+  constexpr int P = (KS - 1) / 2, NT = 128, NB = 2, MB = 3, NBT = 4, NTH = 128 * RG;
   constexpr int PH = 4 * 32 + 16;                // panel row pitch (bytes)
   constexpr int HALF = NT / 2, orow = HALF * 4, opitch = orow + 16;
-  constexpr int kLds = kRowsZH * opitch > kPanelRowsH * PH ? kRowsZH * opitch : kPanelRowsH * PH;
+  constexpr int kRows = kRowsZH * RG, kPanel = kPanelRowsH * RG;
+  constexpr int kLds = kRows * opitch > kPanel * PH ? kRows * opitch : kPanel * PH;
   __shared__ __attribute__((aligned(16))) char lds[kLds];
   int pblk, col, zero;
   xcd_order(pblk, col, zero);
@@ -839,12 +845,12 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int nvalid = min(ppb, np - p0);
   const int rowh = nch * 16;  // bf16 elements per spectrum row
   const int zrows = D + KS - 1;
-  const int tid = threadIdx.x, lane = tid & 63, wave_n = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave_n = (tid >> 6) & 1, wave_m = tid >> 7;
   const int khalf = lane >> 5, lrow = lane & 31;
   int rowoff[MB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
-    const int r = mb * 32 + lrow;
+    const int r = wave_m * kRowsZH + mb * 32 + lrow;
     const int pl = r / D, zl = r % D;
     rowoff[mb] = (pl < ppb ? (pl * zrows + zl) * PH : 0) + khalf * 16;
   }
@@ -875,7 +881,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int nh = min(4, nch - h0);  // chunks in this half
     if (h0) __syncthreads();           // the previous half's panel is read
     {
-      constexpr int kIt = (kPanelRowsH * 8 + NTH - 1) / NTH;  // uint4 per thread, 8 per row
+      constexpr int kIt = (kPanel * 8 + NTH - 1) / NTH;  // uint4 per thread, 8 per row
       uint4 pv[kIt];
       const int q8 = nh * 2, total = ppb * zrows * q8;
 #pragma unroll
@@ -952,7 +958,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int row = mb * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
+      const int row = wave_m * kRowsZH + mb * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int n = (wave_n * NB + nb) * 32 + lrow;
@@ -1323,19 +1329,19 @@ hipError_t launch_fft_conv(const ConvLayer &L, const void *in, const void *res, 
       if (L.k == 7) CF_ZF(7, 1); else if (L.k == 5) CF_ZF(5, 1); else CF_ZF(3, 1);
     }
 #undef CF_ZF
-  } else if ((stage < 0 || stage == 1) && L.cout == 64 && (kRowsZH / D) * (D + L.k - 1) <= kPanelRowsH) {
-    const int ppb = kRowsZH / D;
+  } else if ((stage < 0 || stage == 1) && L.cout == 64 && (kZhRG * kRowsZH / D) * (D + L.k - 1) <= kZhRG * kPanelRowsH) {
+    const int ppb = kZhRG * kRowsZH / D;
     const dim3 zg((np + ppb - 1) / ppb, kCols, 1);
     const bf16_t *gp = reinterpret_cast<const bf16_t *>(L.gspec);
     const bf16_t *xb = reinterpret_cast<const bf16_t *>(xs);
     bf16_t *yb = reinterpret_cast<bf16_t *>(ys);
     const int gb = (int)L.gspec_bytes;
     if (L.k == 7)
-      hipLaunchKernelGGL((k_fft_zconv_h<7>), zg, dim3(128), 0, s, xb, gp, yb, np, D, nch, ppb, gb);
+      hipLaunchKernelGGL((k_fft_zconv_h<7, kZhRG>), zg, dim3(128 * kZhRG), 0, s, xb, gp, yb, np, D, nch, ppb, gb);
     else if (L.k == 5)
-      hipLaunchKernelGGL((k_fft_zconv_h<5>), zg, dim3(128), 0, s, xb, gp, yb, np, D, nch, ppb, gb);
+      hipLaunchKernelGGL((k_fft_zconv_h<5, kZhRG>), zg, dim3(128 * kZhRG), 0, s, xb, gp, yb, np, D, nch, ppb, gb);
     else
-      hipLaunchKernelGGL((k_fft_zconv_h<3>), zg, dim3(128), 0, s, xb, gp, yb, np, D, nch, ppb, gb);
+      hipLaunchKernelGGL((k_fft_zconv_h<3, kZhRG>), zg, dim3(128 * kZhRG), 0, s, xb, gp, yb, np, D, nch, ppb, gb);
   } else if (stage < 0 || stage == 1) {
     const int ppb = kRowsZ / D;
     const dim3 zg((np + ppb - 1) / ppb, kCols, 1);
