@@ -288,15 +288,19 @@ __global__ __launch_bounds__(256) void k_splat(const int32_t *__restrict__ atom_
       const bool tile = in && v0 >= i0 && v0 < i0 + kTA && v1 >= j0 && v1 < j0 + kTB && v2 >= 0 && v2 < G;
       if (tile) {
         int *dst = acc + (((v0 - i0) * kTB + (v1 - j0)) * G + v2) * CF_NCH;
-        // a feature out of range adds nothing and is reported once, so that no branch
-        // separates the channels' adds
+        // a feature out of range adds nothing and is reported once.  A zero feature
+        // (most channels of an atom: one-hot element and flags) adds nothing either;
+        // the feature is the same on every lane, so skipping its add is a uniform
+        // branch and the sums are unchanged
         bool badf = false;
 #pragma unroll
         for (int ch = 0; ch < CF_NCH; ++ch) {
           const float fv = __int_as_float(rdlane(__float_as_int(fr[ch]), b));
-          const bool okf = fabsf(fv) <= kFeatMax;
-          badf |= !okf;
-          atomicAdd(dst + ch, okf ? (int)rintf(fv * f * kSplatScale) : 0);
+          if (fv != 0.0f) {
+            const bool okf = fabsf(fv) <= kFeatMax;
+            badf |= !okf;
+            atomicAdd(dst + ch, okf ? (int)rintf(fv * f * kSplatScale) : 0);
+          }
         }
         if (badf) dev_fail(status, kDevBadFeature);
       }
