@@ -430,6 +430,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv8Cf
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(wpk), (short)0, wbytes, 0x00020000);
   for (int chunk = 0; chunk < nchunks; ++chunk) {
     if (chunk) __syncthreads();
+    // the chunk's first channel of the workgroup's first pose (uniform); voxel
+    // offsets from it fit 32 bits (PP * D^3 * cin_pad elements), which keeps the
+    // per-voxel address arithmetic out of 64-bit multiplies
+    const bf16_t *cin0 = in + pose_in * cin_pad + chunk * 8;
 #pragma unroll
     for (int it0 = 0; it0 < HITER; it0 += HB) {
       uint4 hv[HB];
@@ -443,8 +447,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv8Cf
           const int gz = oz + hz, gy = oy + hy, gx = ox + hx;
           if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gx < (unsigned)D &&
               (PP == 1 || pose0 + pp < n_poses))
-            hv[it - it0] = *reinterpret_cast<const uint4 *>(
-                in + ((pose_in + (((int64_t)pp * D + gz) * D + gy) * D + gx) * cin_pad + chunk * 8));
+            hv[it - it0] = *reinterpret_cast<const uint4 *>(cin0 + (((pp * D + gz) * D + gy) * D + gx) * cin_pad);
         }
       }
 #pragma unroll
@@ -651,6 +654,12 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv4Cf
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t *>(wpk), (short)0, wbytes, 0x00020000);
   for (int chunk = 0; chunk < nchunks; ++chunk) {
     __syncthreads();  // the table is written / the previous chunk's halo is read
+    // the chunk's channels of this pose (uniform) and the elements per voxel: voxel
+    // offsets from there fit 32 bits, which keeps the per-voxel address arithmetic
+    // out of 64-bit multiplies
+    const bf16_t *cin0 = chunk_major ? in + ((int64_t)pose * nchunks + chunk) * D * D * D * 4
+                                     : in + pose_in * cin_pad + chunk * 4;
+    const int vstride = chunk_major ? 4 : cin_pad;
     // batches of HB loads in flight; the batch loop is not unrolled, so the halo
     // addressing is recomputed per chunk rather than hoisted and held in registers
 #pragma unroll 1
@@ -664,10 +673,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(Conv4Cf
           const int hx = v % C::HX, hy = (v / C::HX) % C::HY, hz = v / (C::HX * C::HY);
           const int gz = oz + hz, gy = oy + hy, gx = ox + hx;
           if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)D && (unsigned)gx < (unsigned)D)
-            hv[i] = *reinterpret_cast<const uint2 *>(
-                chunk_major
-                    ? in + ((((int64_t)pose * nchunks + chunk) * D + gz) * D + gy) * D * 4 + (int64_t)gx * 4
-                    : in + ((pose_in + ((int64_t)gz * D + gy) * D + gx) * cin_pad + chunk * 4));
+            hv[i] = *reinterpret_cast<const uint2 *>(cin0 + ((gz * D + gy) * D + gx) * vstride);
         }
       }
 #pragma unroll
