@@ -381,7 +381,7 @@ def main():
     ROCTX = a.roctx
 
     if a.gpus != 1:
-        print(f"bench.py measures one GPU: this build scores poses on a single MI355X and has no "
+        print(f"bench.py measures one GPU: the library scores poses on a single MI355X and has no "
               f"multi-GPU path (asked for --gpus {a.gpus}).", file=sys.stderr)
         sys.exit(2)
 

@@ -51,7 +51,7 @@ typedef enum {
   CF_ERR_CAPACITY = -2,    /* a caller-provided CSR is too small; see cf_stream_status */
   CF_ERR_OOM = -3,         /* device allocation failed or would exceed the HBM budget */
   CF_ERR_HIP = -4,         /* a HIP runtime call failed */
-  CF_ERR_UNSUPPORTED = -5, /* valid request outside what this build implements */
+  CF_ERR_UNSUPPORTED = -5, /* valid request outside what the library implements */
   CF_ERR_CANCELLED = -6    /* serving request cancelled before it was scheduled */
 } cf_status;
 
@@ -232,7 +232,7 @@ int cf_conv_variants(const cf_ctx *ctx, int G, int32_t *variant_out, int32_t max
 /* Pin the conv kernel variant of every layer for grid size G (e.g. a cached
  * autotuning result).  CF_ERR_UNSUPPORTED if a variant does not fit its layer. */
 int cf_set_conv_variants(cf_ctx *ctx, int G, const int32_t *variants, int32_t n_layers);
-/* Number of conv kernel variants in this build and the name of one (tile shape,
+/* Number of conv kernel variants in the library and the name of one (tile shape,
  * waves, output-channel tile; "p8" = bf16 tap-pair kernel). */
 int cf_conv_variant_count(void);
 const char *cf_conv_variant_name(int32_t variant);
