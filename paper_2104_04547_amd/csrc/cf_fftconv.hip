@@ -73,8 +73,12 @@ __host__ __device__ constexpr int plane_lds_bytes(int D, bool f32 = false) {
 }
 constexpr int kZpBytes = 32 * 8 * 8;
 
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+// two floats rounded to bf16 (nearest even) by one conversion, lo in the low half
 __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
-  return (uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)lo) | ((uint32_t)__builtin_bit_cast(uint16_t, (bf16_t)hi) << 16);
+  const float2v two = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(two, bf16x2v));
 }
 
 // One complex value of channel c from a spectrum row [col][re | im][8]: fp32
@@ -951,19 +955,26 @@ __global__ __launch_bounds__(128 * RG) __attribute__((amdgpu_waves_per_eu(3))) v
       if (full + ph < hsteps) step(full + ph, ph);
   }
 
-  // epilogue through LDS: rows of NT bf16 in the spectrum layout, then contiguous stores
+  // epilogue through LDS: rows of NT bf16 in the spectrum layout, then contiguous
+  // stores.  Lanes 2m and 2m + 1 hold columns n and n + 1 of one 8-channel group:
+  // each lane packs its rows r and r + 1, the pair swaps halves by a DPP move, and
+  // the even lane writes row r, the odd lane row r + 1, as 32-bit words
   __syncthreads();
-  bf16_t *ot = reinterpret_cast<bf16_t *>(lds);
+  const int odd = lane & 1;
+  const uint32_t sel = odd ? 0x03020706u : 0x05040100u;  // byte picks from {partner, own}
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = wave_m * kRowsZH + mb * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
+    for (int r = 0; r < 16; r += 2) {
+      const int row = wave_m * kRowsZH + mb * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3) + odd;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const int n = (wave_n * NB + nb) * 32 + lrow;
+        const int n = (wave_n * NB + nb) * 32 + (lrow & ~1);
         const int part = n / HALF, co = n % HALF;
-        ot[(row * opitch + (co >> 3) * 32 + part * 16) / 2 + (co & 7)] = (bf16_t)acc[mb][nb][r];
+        const uint32_t own = pack_bf16x2(acc[mb][nb][r], acc[mb][nb][r + 1]);
+        const uint32_t other = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)own, 0xB1, 0xF, 0xF, false);
+        *reinterpret_cast<uint32_t *>(lds + row * opitch + (co >> 3) * 32 + part * 16 + (co & 7) * 2) =
+            __builtin_amdgcn_perm(other, own, sel);
       }
     }
   __syncthreads();
