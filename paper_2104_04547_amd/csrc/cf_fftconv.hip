@@ -82,10 +82,11 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
 }
 
 // One complex value of channel c from a spectrum row [col][re | im][8]: fp32
-// directly; bf16 by lane pairs (c, c ^ 1), LX lanes apart, that read two channels
-// at once (even channels the re pair, odd channels the im pair) and swap halves,
-// so both lanes of a pair must be active.
-template <bool F32, int LX = 1>
+// directly; bf16 from the two 32-bit words that hold the re and the im of the
+// channel pair (c & ~1, c | 1), channel c being the low (even c) or the high half
+// of each: a byte permute moves that half to the top of a float (one instruction
+// per value, no exchange with the other channel's lane).
+template <bool F32>
 __device__ inline void spec_get(const void *Y, int col, int c, float &r, float &i) {
   if constexpr (F32) {
     const float *Yf = reinterpret_cast<const float *>(Y);
@@ -94,17 +95,15 @@ __device__ inline void spec_get(const void *Y, int col, int c, float &r, float &
     return;
   }
   const uint32_t *Yw = reinterpret_cast<const uint32_t *>(Y);
-  const bool odd = c & 1;
-  const uint32_t two = Yw[col * 8 + (odd ? 4 : 0) + (c >> 1)];
-  const float lo = __uint_as_float(two << 16), hi = __uint_as_float(two & 0xffff0000u);
-  const float other = __shfl_xor(odd ? lo : hi, LX);
-  r = odd ? other : lo;
-  i = odd ? hi : other;
+  const uint32_t wr = Yw[col * 8 + (c >> 1)], wi = Yw[col * 8 + 4 + (c >> 1)];
+  const uint32_t sel = (c & 1) ? 0x03020c0cu : 0x01000c0cu;  // 0x0c: a zero byte
+  r = __uint_as_float(__builtin_amdgcn_perm(wr, wr, sel));
+  i = __uint_as_float(__builtin_amdgcn_perm(wi, wi, sel));
 }
 
-// The inverse of spec_get: fp32 directly; bf16 lane pairs swap halves so that
-// each lane stores two channels as one 32-bit word, rounded to bf16.
-template <bool F32, int LX = 1>
+// The inverse of spec_get: fp32 directly; bf16 as the two 16-bit halves of one
+// rounding of (r, i), stored into the re and the im word of the channel pair.
+template <bool F32>
 __device__ inline void spec_put(void *Ov, int col, int c, float r, float i) {
   if constexpr (F32) {
     float *Of = reinterpret_cast<float *>(Ov);
@@ -112,10 +111,10 @@ __device__ inline void spec_put(void *Ov, int col, int c, float r, float i) {
     Of[col * 16 + 8 + c] = i;
     return;
   }
-  uint32_t *O = reinterpret_cast<uint32_t *>(Ov);
-  const bool odd = c & 1;
-  const float other = __shfl_xor(odd ? r : i, LX);
-  O[col * 8 + (odd ? 4 : 0) + (c >> 1)] = pack_bf16x2(odd ? other : r, odd ? i : other);
+  uint16_t *O = reinterpret_cast<uint16_t *>(Ov);
+  const uint32_t two = pack_bf16x2(r, i);
+  O[(col * 8 + (c >> 1)) * 2 + (c & 1)] = (uint16_t)two;
+  O[(col * 8 + 4 + (c >> 1)) * 2 + (c & 1)] = (uint16_t)(two >> 16);
 }
 
 // inverse, all 256 threads (ky = tid >> 3, c = tid & 7): Zp[ky][c] = H(Y0)[ky] + i H(Y16)[ky]
@@ -141,13 +140,6 @@ __device__ inline void dc_nyquist_split(const float2 *Zp, void *O, int tid) {
   spec_put<F32>(O, ky * kNX + kNX - 1, c, 0.5f * (a.y + b.y), -0.5f * (a.x - b.x));
 }
 
-
-
-
-
-
-
-
 // ---------------------------------------------------------------- lane-pair transforms
 //
 // Every 32-point FFT of the plane kernels is shared by two adjacent lanes
@@ -157,8 +149,7 @@ __device__ inline void dc_nyquist_split(const float2 *Zp, void *O, int tid) {
 // the register file holds half the transform state (at 24^3: 118 VGPRs for the
 // fused transform against 153 with one transform per lane, four waves per SIMD
 // instead of three).  Lane h = tid & 1 of a pair, partner tid ^ 1 (a quad
-// permutation, so the exchange is a DPP move); the channel pair (c, c ^ 1) of a
-// bf16 spectrum access is then two lanes apart.
+// permutation, so the exchange is a DPP move).
 
 __device__ inline float pair_swap(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // lanes 1,0,3,2
@@ -169,7 +160,7 @@ __device__ inline float pair_swap(float v) {
 template <bool F32>
 __device__ inline void col_inv_load2(const void *Y, int kxp, int c, int h, float (&re)[16], float (&im)[16]) {
 #pragma unroll
-  for (int n = 0; n < 16; ++n) spec_get<F32, 2>(Y, (2 * n + h) * kNX + kxp, c, re[n], im[n]);
+  for (int n = 0; n < 16; ++n) spec_get<F32>(Y, (2 * n + h) * kNX + kxp, c, re[n], im[n]);
 }
 __device__ inline void col_inv_load_dc2(const float2 *Zp, int c, int h, float (&re)[16], float (&im)[16]) {
 #pragma unroll
@@ -242,7 +233,7 @@ __device__ inline void col_fwd_store2(void *O, float2 *Zp, int kxp, int c, int h
                                       const float (&im)[16]) {
   if (kxp) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) spec_put<F32, 2>(O, (2 * m + h) * kNX + kxp, c, re[m], im[m]);
+    for (int m = 0; m < 16; ++m) spec_put<F32>(O, (2 * m + h) * kNX + kxp, c, re[m], im[m]);
   } else {
 #pragma unroll
     for (int m = 0; m < 16; ++m) Zp[(2 * m + h) * 8 + c] = make_float2(re[m], im[m]);
